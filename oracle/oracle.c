@@ -1,0 +1,583 @@
+/*
+ * oracle.c -- plain, single-threaded FP64 reference of the geometric docking
+ * hot path.  TEST INFRASTRUCTURE ONLY: it exists to check the GPU library and
+ * must never be linked or called by the product path (only tests, the smoke
+ * check and the benchmark's CPU-baseline leg use it).  It shares no source
+ * with the GPU library.
+ *
+ * What it computes (paper: Gadioli et al., "Tunable Approximations to Control
+ * Time-to-Solution in an HPC Molecular Docking Mini-App"):
+ *
+ *  - Overlap score, Eq. 1 (Section III-A): o = l / sum_i min_j d^2(L_i, P_j).
+ *    Read on a lattice of spacing h anchored at the origin: every ligand atom
+ *    and pocket point is snapped to its cell floor(x/h), and min_j d^2 becomes
+ *    D(c) = min over occupied cells c' of |c - c'|^2 (integer, cell units).
+ *    S = sum_i D(cell(X_i)) is the integer "overlap count"; o = l / (h^2 S)
+ *    and smaller S ranks better.  D is evaluated by brute force over the
+ *    occupied cells (memoised per cell), i.e. by its definition.
+ *  - Feasibility ("CheckBumps", Alg. 1, Section III-B): a shape is infeasible
+ *    when a pair of atoms more than 3 bonds apart comes closer than the clash
+ *    distance (strict d^2 < clash_dist^2).  A sweep of one fragment tests the
+ *    pairs that straddle the rotatable bond; the endpoint flag tests all.
+ *  - MatchProbesShape with the five knobs, Alg. 2 (Section III-C): for each
+ *    repetition, for each rotamer in list order, the left and then the right
+ *    fragment is swept through its angle schedule (coarse step when the
+ *    fragment's relative size is <= threshold; otherwise either the flat fine
+ *    step, or the tile-peeling refinement of Eq. 2/3), and the best feasible
+ *    angle is committed.
+ *  - Rigid orientations: each run starts from a unit quaternion that rotates
+ *    the ligand about its centroid and places the centroid at the pocket
+ *    centroid; per orientation the endpoint (S, clash, chosen angles, pose)
+ *    is recorded and the orientations are ranked by (clash, S, index).
+ *
+ * Numerical conventions (the GPU library reproduces the FP64 parts of these
+ * formulas in the same operation order, so FP64 states agree bit for bit):
+ *  - Angles are integer degrees; c = cos(deg * (pi/180)), s = sin(...) (libm).
+ *  - Rotation about unit axis k by angle theta (right-hand rule):
+ *      R = c I + s [k]x + (1-c) k k^T, written element by element below,
+ *      Y = p + R (X - p), p = the moving fragment's own bond atom.
+ *  - Axis k = (X_b - X_a) / |X_b - X_a| for both fragments of rotamer (a,b).
+ *  - Compiled with -ffp-contract=off: no fused multiply-adds.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_OK 0
+#define ORC_ERR_ARG 1
+#define ORC_ERR_GRAPH 2
+#define ORC_ERR_ROTAMER 3
+#define ORC_ERR_KNOB 4
+
+static const double ORC_PI = 3.14159265358979323846;
+
+/* ------------------------------------------------------------------------ */
+/* Pocket: occupied cells and the squared-distance field D (Eq. 1 on a grid) */
+
+typedef struct {
+    double h;
+    int n_points;
+    double* pts;        /* n x 3, FP64 widening of the FP32 input */
+    int n_occ;
+    int64_t* occ;       /* unique occupied cells, n_occ x 3 */
+    double centroid[3]; /* mean of the points, summed in input order */
+    int64_t mlo[3], mdim[3];
+    int64_t* memo;      /* D per cell of the memo box, -1 = not computed yet */
+} orc_pocket;
+
+static int64_t cell_of(double v, double h) { return (int64_t)floor(v / h); }
+
+static int cmp_cell(const void* a, const void* b) {
+    const int64_t* x = (const int64_t*)a;
+    const int64_t* y = (const int64_t*)b;
+    for (int k = 0; k < 3; k++) {
+        if (x[k] < y[k]) return -1;
+        if (x[k] > y[k]) return 1;
+    }
+    return 0;
+}
+
+orc_pocket* orc_pocket_new(const float* xyz, int n, double h) {
+    if (n < 1 || !(h > 0)) return NULL;
+    orc_pocket* P = (orc_pocket*)calloc(1, sizeof(orc_pocket));
+    P->h = h;
+    P->n_points = n;
+    P->pts = (double*)malloc(sizeof(double) * 3 * n);
+    int64_t* cells = (int64_t*)malloc(sizeof(int64_t) * 3 * n);
+    double sx = 0, sy = 0, sz = 0;
+    for (int i = 0; i < n; i++) {
+        double x = (double)xyz[3 * i], y = (double)xyz[3 * i + 1], z = (double)xyz[3 * i + 2];
+        P->pts[3 * i] = x; P->pts[3 * i + 1] = y; P->pts[3 * i + 2] = z;
+        sx = sx + x; sy = sy + y; sz = sz + z;
+        cells[3 * i] = cell_of(x, h); cells[3 * i + 1] = cell_of(y, h); cells[3 * i + 2] = cell_of(z, h);
+    }
+    P->centroid[0] = sx / (double)n; P->centroid[1] = sy / (double)n; P->centroid[2] = sz / (double)n;
+    qsort(cells, n, sizeof(int64_t) * 3, cmp_cell);
+    int m = 0;
+    for (int i = 0; i < n; i++) {
+        if (m > 0 && cmp_cell(cells + 3 * i, cells + 3 * (m - 1)) == 0) continue;
+        memmove(cells + 3 * m, cells + 3 * i, sizeof(int64_t) * 3);
+        m++;
+    }
+    P->n_occ = m;
+    P->occ = cells;
+    int64_t lo[3], hi[3];
+    for (int k = 0; k < 3; k++) { lo[k] = cells[k]; hi[k] = cells[k]; }
+    for (int i = 0; i < m; i++)
+        for (int k = 0; k < 3; k++) {
+            if (cells[3 * i + k] < lo[k]) lo[k] = cells[3 * i + k];
+            if (cells[3 * i + k] > hi[k]) hi[k] = cells[3 * i + k];
+        }
+    const int64_t margin = 64;
+    int64_t total = 1;
+    for (int k = 0; k < 3; k++) {
+        P->mlo[k] = lo[k] - margin;
+        P->mdim[k] = hi[k] - lo[k] + 1 + 2 * margin;
+        total *= P->mdim[k];
+    }
+    P->memo = (int64_t*)malloc(sizeof(int64_t) * total);
+    for (int64_t i = 0; i < total; i++) P->memo[i] = -1;
+    return P;
+}
+
+void orc_pocket_free(orc_pocket* P) {
+    if (!P) return;
+    free(P->pts); free(P->occ); free(P->memo); free(P);
+}
+
+void orc_pocket_centroid(const orc_pocket* P, double* c) { c[0] = P->centroid[0]; c[1] = P->centroid[1]; c[2] = P->centroid[2]; }
+int orc_pocket_n_occ(const orc_pocket* P) { return P->n_occ; }
+void orc_pocket_occ(const orc_pocket* P, int64_t* out) { memcpy(out, P->occ, sizeof(int64_t) * 3 * P->n_occ); }
+
+/* D(c) = min over occupied cells o of |c - o|^2, by brute force. */
+static int64_t D_brute(const orc_pocket* P, int64_t cx, int64_t cy, int64_t cz) {
+    int64_t best = INT64_MAX;
+    for (int i = 0; i < P->n_occ; i++) {
+        int64_t dx = cx - P->occ[3 * i], dy = cy - P->occ[3 * i + 1], dz = cz - P->occ[3 * i + 2];
+        int64_t d = dx * dx + dy * dy + dz * dz;
+        if (d < best) best = d;
+    }
+    return best;
+}
+
+int64_t orc_D(orc_pocket* P, int64_t cx, int64_t cy, int64_t cz) {
+    int64_t ix = cx - P->mlo[0], iy = cy - P->mlo[1], iz = cz - P->mlo[2];
+    if (ix < 0 || iy < 0 || iz < 0 || ix >= P->mdim[0] || iy >= P->mdim[1] || iz >= P->mdim[2])
+        return D_brute(P, cx, cy, cz);
+    int64_t idx = (iz * P->mdim[1] + iy) * P->mdim[0] + ix;
+    if (P->memo[idx] < 0) P->memo[idx] = D_brute(P, cx, cy, cz);
+    return P->memo[idx];
+}
+
+/* S(X) = sum_i D(cell(X_i)) over the given FP64 coordinates (n x 3). */
+int64_t orc_score_xyz(orc_pocket* P, int n, const double* X) {
+    int64_t S = 0;
+    for (int i = 0; i < n; i++)
+        S += orc_D(P, cell_of(X[3 * i], P->h), cell_of(X[3 * i + 1], P->h), cell_of(X[3 * i + 2], P->h));
+    return S;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Ligand topology: validation, bond-count distances, fragments              */
+
+typedef struct {
+    int l, nb, nr;
+    const int* bonds;
+    const int* rot;
+    int* deg;
+    int* dist;          /* l x l bond-count distances */
+    unsigned char* left; /* nr x l: atom is in the left fragment of rotamer b */
+} orc_topo;
+
+static void topo_free(orc_topo* T) { free(T->deg); free(T->dist); free(T->left); }
+
+/* BFS from src; if (ea,eb) >= 0 that edge is ignored.  dist[] gets -1 when unreachable. */
+static void bfs(const orc_topo* T, int src, int ea, int eb, int* dist) {
+    int l = T->l;
+    int* queue = (int*)malloc(sizeof(int) * l);
+    for (int i = 0; i < l; i++) dist[i] = -1;
+    int qh = 0, qt = 0;
+    dist[src] = 0;
+    queue[qt++] = src;
+    while (qh < qt) {
+        int u = queue[qh++];
+        for (int b = 0; b < T->nb; b++) {
+            int a = T->bonds[2 * b], c = T->bonds[2 * b + 1], w;
+            if (a == u) w = c; else if (c == u) w = a; else continue;
+            if ((a == ea && c == eb) || (a == eb && c == ea)) continue;
+            if (dist[w] < 0) { dist[w] = dist[u] + 1; queue[qt++] = w; }
+        }
+    }
+    free(queue);
+}
+
+static int topo_build(orc_topo* T, int l, int nb, const int* bonds, int nr, const int* rot) {
+    memset(T, 0, sizeof(*T));
+    if (l < 1 || nb < 0 || nr < 0) return ORC_ERR_GRAPH;
+    T->l = l; T->nb = nb; T->nr = nr; T->bonds = bonds; T->rot = rot;
+    T->deg = (int*)calloc(l, sizeof(int));
+    T->dist = (int*)malloc(sizeof(int) * l * l);
+    T->left = (unsigned char*)calloc((size_t)(nr > 0 ? nr : 1) * l, 1);
+    for (int b = 0; b < nb; b++) {
+        int a = bonds[2 * b], c = bonds[2 * b + 1];
+        if (a < 0 || c < 0 || a >= l || c >= l || a == c) return ORC_ERR_GRAPH;
+        for (int e = 0; e < b; e++) {
+            int a2 = bonds[2 * e], c2 = bonds[2 * e + 1];
+            if ((a == a2 && c == c2) || (a == c2 && c == a2)) return ORC_ERR_GRAPH;
+        }
+        T->deg[a]++; T->deg[c]++;
+    }
+    for (int i = 0; i < l; i++) {
+        bfs(T, i, -1, -1, T->dist + (size_t)i * l);
+        for (int j = 0; j < l; j++)
+            if (T->dist[(size_t)i * l + j] < 0) return ORC_ERR_GRAPH; /* disconnected */
+    }
+    int* d = (int*)malloc(sizeof(int) * l);
+    for (int r = 0; r < nr; r++) {
+        int a = rot[2 * r], c = rot[2 * r + 1];
+        if (a < 0 || c < 0 || a >= l || c >= l || a == c) { free(d); return ORC_ERR_ROTAMER; }
+        int is_bond = 0;
+        for (int b = 0; b < nb; b++) {
+            int x = bonds[2 * b], y = bonds[2 * b + 1];
+            if ((x == a && y == c) || (x == c && y == a)) is_bond = 1;
+        }
+        if (!is_bond || T->deg[a] < 2 || T->deg[c] < 2) { free(d); return ORC_ERR_ROTAMER; }
+        /* left = atoms reachable from a without using the bond (a,c) */
+        bfs(T, a, a, c, d);
+        if (d[c] >= 0) { free(d); return ORC_ERR_ROTAMER; } /* not a bridge */
+        for (int i = 0; i < l; i++) T->left[(size_t)r * l + i] = d[i] >= 0;
+    }
+    free(d);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Knobs and angle schedules (Alg. 2, Eq. 2, Eq. 3)                           */
+
+typedef struct {
+    int hp_step, lp_step;  /* integer degrees, each a divisor of 360 */
+    double threshold;      /* relative fragment size; <= threshold -> coarse step */
+    int repetitions;
+    int refine;            /* tile-peeling iterative refinement */
+    double clash_dist;
+    int clash_min_bonds;   /* pairs at >= this many bonds are checked */
+} orc_knobs;
+
+static int knobs_ok(const orc_knobs* k) {
+    if (k->hp_step < 1 || k->hp_step > 360 || 360 % k->hp_step) return 0;
+    if (k->lp_step < 1 || k->lp_step > 360 || 360 % k->lp_step) return 0;
+    if (!(k->threshold >= 0.0 && k->threshold <= 1.0)) return 0;
+    if (k->repetitions < 1) return 0;
+    if (!(k->clash_dist >= 0.0)) return 0;
+    if (k->clash_min_bonds < 1) return 0;
+    return 1;
+}
+
+/* Tile size x for the peel/tile refinement: minimise Eq. 2, y = 360/x + x/hp,
+ * over divisors x of 360 that are multiples of hp; ties go to the smaller x.
+ * (Eq. 3's continuous optimum sqrt(360 hp) is generally not a divisor.) */
+int orc_tile_size(int hp) {
+    int best = -1, besty = 0;
+    for (int x = hp; x <= 360; x += hp) {
+        if (360 % x) continue;
+        int y = 360 / x + x / hp;
+        if (best < 0 || y < besty) { best = x; besty = y; }
+    }
+    return best;
+}
+
+/* Flat schedule {0, step, ..., 360-step}. */
+static int flat_schedule(int step, int* out) {
+    int n = 360 / step;
+    for (int k = 0; k < n; k++) out[k] = k * step;
+    return n;
+}
+
+/* Peel elements: the central element of each tile of size x. */
+static int peel_schedule(int hp, int* out) {
+    int x = orc_tile_size(hp);
+    int off = (x / (2 * hp)) * hp;
+    int n = 360 / x;
+    for (int t = 0; t < n; t++) out[t] = t * x + off;
+    return n;
+}
+
+/* Public helper for tests: mode 0 = coarse, 1 = flat fine, 2 = refinement
+ * (returns the peel list; the tile list is t*x + k*hp, k < x/hp). */
+int orc_side_mode(const orc_knobs* k, int side_size, int l) {
+    double rel = (double)side_size / (double)l;
+    if (rel <= k->threshold) return 0;
+    return k->refine ? 2 : 1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Rigid-body arithmetic                                                      */
+
+static void axis_angle_matrix(const double k[3], int deg, double R[9]) {
+    double rad = (double)deg * (ORC_PI / 180.0);
+    double c = cos(rad), s = sin(rad), t = 1.0 - c;
+    R[0] = t * k[0] * k[0] + c;        R[1] = t * k[0] * k[1] - s * k[2]; R[2] = t * k[0] * k[2] + s * k[1];
+    R[3] = t * k[0] * k[1] + s * k[2]; R[4] = t * k[1] * k[1] + c;        R[5] = t * k[1] * k[2] - s * k[0];
+    R[6] = t * k[0] * k[2] - s * k[1]; R[7] = t * k[1] * k[2] + s * k[0]; R[8] = t * k[2] * k[2] + c;
+}
+
+static void rotate_about(const double p[3], const double R[9], const double* x, double* y) {
+    double d0 = x[0] - p[0], d1 = x[1] - p[1], d2 = x[2] - p[2];
+    y[0] = p[0] + (R[0] * d0 + R[1] * d1 + R[2] * d2);
+    y[1] = p[1] + (R[3] * d0 + R[4] * d1 + R[5] * d2);
+    y[2] = p[2] + (R[6] * d0 + R[7] * d1 + R[8] * d2);
+}
+
+static void quat_matrix(const double* q, double R[9]) {
+    double n = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    double w = q[0] / n, x = q[1] / n, y = q[2] / n, z = q[3] / n;
+    R[0] = 1.0 - 2.0 * (y * y + z * z); R[1] = 2.0 * (x * y - w * z);       R[2] = 2.0 * (x * z + w * y);
+    R[3] = 2.0 * (x * y + w * z);       R[4] = 1.0 - 2.0 * (x * x + z * z); R[5] = 2.0 * (y * z - w * x);
+    R[6] = 2.0 * (x * z - w * y);       R[7] = 2.0 * (y * z + w * x);       R[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+/* Place the ligand: X = R(q) (x - c_L) + c_P. */
+static void place(int l, const float* x, const float* y, const float* z, const double* q, const double cP[3],
+                  double* X) {
+    double sx = 0, sy = 0, sz = 0;
+    for (int i = 0; i < l; i++) { sx = sx + (double)x[i]; sy = sy + (double)y[i]; sz = sz + (double)z[i]; }
+    double cL[3] = {sx / (double)l, sy / (double)l, sz / (double)l};
+    double R[9];
+    quat_matrix(q, R);
+    for (int i = 0; i < l; i++) {
+        double d0 = (double)x[i] - cL[0], d1 = (double)y[i] - cL[1], d2 = (double)z[i] - cL[2];
+        X[3 * i + 0] = (R[0] * d0 + R[1] * d1 + R[2] * d2) + cP[0];
+        X[3 * i + 1] = (R[3] * d0 + R[4] * d1 + R[5] * d2) + cP[1];
+        X[3 * i + 2] = (R[6] * d0 + R[7] * d1 + R[8] * d2) + cP[2];
+    }
+}
+
+static double dist2(const double* a, const double* b) {
+    double dx = a[0] - b[0], dy = a[1] - b[1], dz = a[2] - b[2];
+    return dx * dx + dy * dy + dz * dz;
+}
+
+/* Whole-ligand clash: any pair at >= min_bonds bonds with d^2 < cd2. */
+static int clash_all(const orc_topo* T, const double* X, double cd2, int min_bonds) {
+    for (int i = 0; i < T->l; i++)
+        for (int j = i + 1; j < T->l; j++)
+            if (T->dist[(size_t)i * T->l + j] >= min_bonds && dist2(X + 3 * i, X + 3 * j) < cd2) return 1;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* One orientation: the greedy sweep of Alg. 2                                */
+
+typedef struct {
+    orc_pocket* P;
+    const orc_topo* T;
+    const orc_knobs* K;
+    double cd2;
+    double* Y;       /* candidate pose scratch, l x 3 */
+    int64_t n_cand;  /* candidates evaluated */
+} sweep_ctx;
+
+/* Evaluate one candidate angle for the moving set; returns feasibility, S via *S. */
+static int eval_candidate(sweep_ctx* C, const double* X, const unsigned char* moving, const double p[3],
+                          const double k[3], int deg, int64_t* S) {
+    int l = C->T->l;
+    double R[9];
+    axis_angle_matrix(k, deg, R);
+    memcpy(C->Y, X, sizeof(double) * 3 * l);
+    for (int i = 0; i < l; i++)
+        if (moving[i]) rotate_about(p, R, X + 3 * i, C->Y + 3 * i);
+    C->n_cand++;
+    int feasible = 1;
+    for (int i = 0; i < l && feasible; i++) {
+        if (!moving[i]) continue;
+        for (int j = 0; j < l; j++) {
+            if (moving[j]) continue;
+            if (C->T->dist[(size_t)i * l + j] < C->K->clash_min_bonds) continue;
+            if (dist2(C->Y + 3 * i, C->Y + 3 * j) < C->cd2) { feasible = 0; break; }
+        }
+    }
+    *S = orc_score_xyz(C->P, l, C->Y);
+    return feasible;
+}
+
+/* Pick the best feasible angle among `angles`: lowest S, ties to the earliest
+ * position; returns the position or -1 when no candidate is feasible. */
+static int best_of(sweep_ctx* C, const double* X, const unsigned char* moving, const double p[3], const double k[3],
+                   const int* angles, int n) {
+    int best = -1;
+    int64_t bestS = 0;
+    for (int t = 0; t < n; t++) {
+        int64_t S;
+        int ok = eval_candidate(C, X, moving, p, k, angles[t], &S);
+        if (ok && (best < 0 || S < bestS)) { best = t; bestS = S; }
+    }
+    return best;
+}
+
+static int sweep_side(sweep_ctx* C, double* X, int r, int side) {
+    const orc_topo* T = C->T;
+    int l = T->l;
+    int a = T->rot[2 * r], c = T->rot[2 * r + 1];
+    unsigned char* moving = (unsigned char*)malloc(l);
+    int size = 0;
+    for (int i = 0; i < l; i++) {
+        int in_left = T->left[(size_t)r * l + i];
+        moving[i] = side == 0 ? in_left : !in_left;
+        size += moving[i];
+    }
+    double p[3], k[3];
+    const double* piv = X + 3 * (side == 0 ? a : c);
+    p[0] = piv[0]; p[1] = piv[1]; p[2] = piv[2];
+    double ax = X[3 * c] - X[3 * a], ay = X[3 * c + 1] - X[3 * a + 1], az = X[3 * c + 2] - X[3 * a + 2];
+    double nrm = sqrt(ax * ax + ay * ay + az * az);
+    k[0] = ax / nrm; k[1] = ay / nrm; k[2] = az / nrm;
+
+    int angles[360];
+    int theta = 0;
+    int mode = orc_side_mode(C->K, size, l);
+    if (mode == 0 || mode == 1) {
+        int n = flat_schedule(mode == 0 ? C->K->lp_step : C->K->hp_step, angles);
+        int b = best_of(C, X, moving, p, k, angles, n);
+        theta = b < 0 ? 0 : angles[b];
+    } else {
+        int hp = C->K->hp_step, x = orc_tile_size(hp);
+        int n = peel_schedule(hp, angles);
+        int t = best_of(C, X, moving, p, k, angles, n);
+        if (t < 0) t = 0;
+        int m = x / hp;
+        for (int j = 0; j < m; j++) angles[j] = t * x + j * hp;
+        int b = best_of(C, X, moving, p, k, angles, m);
+        theta = b < 0 ? 0 : angles[b];
+    }
+    if (theta != 0) {
+        double R[9];
+        axis_angle_matrix(k, theta, R);
+        for (int i = 0; i < l; i++)
+            if (moving[i]) {
+                double y[3];
+                rotate_about(p, R, X + 3 * i, y);
+                X[3 * i] = y[0]; X[3 * i + 1] = y[1]; X[3 * i + 2] = y[2];
+            }
+    }
+    free(moving);
+    return theta;
+}
+
+/*
+ * Dock one ligand in all given orientations.
+ * Outputs per orientation o: S[o], clash[o], angles[o][rep][rot][side]
+ * (int16 degrees, may be NULL), xyz[o][atom][3] (FP64, may be NULL).
+ * *n_cand gets the number of evaluated candidate poses (sweep candidates plus
+ * one endpoint evaluation per orientation).
+ */
+int orc_dock(orc_pocket* P, int l, const float* x, const float* y, const float* z, int nb, const int* bonds, int nr,
+             const int* rot, const orc_knobs* K, int n_orient, const double* quats, int64_t* S, uint8_t* clash,
+             int16_t* angles, double* xyz, int64_t* n_cand) {
+    if (!P || !K || n_orient < 0) return ORC_ERR_ARG;
+    if (!knobs_ok(K)) return ORC_ERR_KNOB;
+    orc_topo T;
+    int rc = topo_build(&T, l, nb, bonds, nr, rot);
+    if (rc != ORC_OK) { topo_free(&T); return rc; }
+    sweep_ctx C;
+    C.P = P; C.T = &T; C.K = K;
+    C.cd2 = K->clash_dist * K->clash_dist;
+    C.Y = (double*)malloc(sizeof(double) * 3 * l);
+    C.n_cand = 0;
+    double* X = (double*)malloc(sizeof(double) * 3 * l);
+    for (int o = 0; o < n_orient; o++) {
+        place(l, x, y, z, quats + 4 * o, P->centroid, X);
+        for (int rep = 0; rep < K->repetitions; rep++)
+            for (int r = 0; r < nr; r++)
+                for (int side = 0; side < 2; side++) {
+                    int th = sweep_side(&C, X, r, side);
+                    if (angles) angles[(((size_t)o * K->repetitions + rep) * nr + r) * 2 + side] = (int16_t)th;
+                }
+        S[o] = orc_score_xyz(P, l, X);
+        clash[o] = (uint8_t)clash_all(&T, X, C.cd2, K->clash_min_bonds);
+        C.n_cand++;
+        if (xyz) memcpy(xyz + (size_t)o * 3 * l, X, sizeof(double) * 3 * l);
+    }
+    if (n_cand) *n_cand = C.n_cand;
+    free(X); free(C.Y);
+    topo_free(&T);
+    return ORC_OK;
+}
+
+/* Rank orientations by (clash, S, index) ascending and keep the first k. */
+static const int64_t* g_S;
+static const uint8_t* g_clash;
+static int cmp_rank(const void* a, const void* b) {
+    int i = *(const int*)a, j = *(const int*)b;
+    if (g_clash[i] != g_clash[j]) return g_clash[i] < g_clash[j] ? -1 : 1;
+    if (g_S[i] != g_S[j]) return g_S[i] < g_S[j] ? -1 : 1;
+    return i < j ? -1 : (i > j);
+}
+int orc_topk(int n, const int64_t* S, const uint8_t* clash, int k, int* out) {
+    if (k < 0 || k > n) return ORC_ERR_KNOB;
+    int* idx = (int*)malloc(sizeof(int) * (n > 0 ? n : 1));
+    for (int i = 0; i < n; i++) idx[i] = i;
+    g_S = S; g_clash = clash;
+    qsort(idx, n, sizeof(int), cmp_rank);
+    memcpy(out, idx, sizeof(int) * k);
+    free(idx);
+    return ORC_OK;
+}
+
+/* Overlap o = l / (h^2 S); S = 0 gives +inf. */
+double orc_overlap(int l, int64_t S, double h) { return (double)l / (h * h * (double)S); }
+
+/*
+ * Exact score of given poses (FP32 coordinates widened to FP64): S and the
+ * whole-ligand clash flag, for one ligand topology.
+ */
+int orc_score_poses(orc_pocket* P, int l, int nb, const int* bonds, int n_poses, const float* px, const float* py,
+                    const float* pz, double clash_dist, int min_bonds, int64_t* S, uint8_t* clash) {
+    orc_topo T;
+    int rc = topo_build(&T, l, nb, bonds, 0, NULL);
+    if (rc != ORC_OK) { topo_free(&T); return rc; }
+    double* X = (double*)malloc(sizeof(double) * 3 * l);
+    double cd2 = clash_dist * clash_dist;
+    for (int p = 0; p < n_poses; p++) {
+        for (int i = 0; i < l; i++) {
+            X[3 * i] = (double)px[(size_t)p * l + i];
+            X[3 * i + 1] = (double)py[(size_t)p * l + i];
+            X[3 * i + 2] = (double)pz[(size_t)p * l + i];
+        }
+        S[p] = orc_score_xyz(P, l, X);
+        clash[p] = (uint8_t)clash_all(&T, X, cd2, min_bonds);
+    }
+    free(X);
+    topo_free(&T);
+    return ORC_OK;
+}
+
+/* Bond-count distance matrix and left-fragment masks, for tests. */
+int orc_topology(int l, int nb, const int* bonds, int nr, const int* rot, int* dist, uint8_t* left) {
+    orc_topo T;
+    int rc = topo_build(&T, l, nb, bonds, nr, rot);
+    if (rc == ORC_OK) {
+        if (dist) memcpy(dist, T.dist, sizeof(int) * l * l);
+        if (left) memcpy(left, T.left, (size_t)nr * l);
+    }
+    topo_free(&T);
+    return rc;
+}
+
+/* Rigid placement of one orientation (for tests): X = R(q)(x - c_L) + c_P. */
+void orc_place(int l, const float* x, const float* y, const float* z, const double* q, const double* cP, double* X) {
+    place(l, x, y, z, q, cP, X);
+}
+
+/*
+ * Apply a list of fragment rotations (rotamer r, side 0=left/1=right, integer
+ * degrees) to the FP64 pose X in order, with the same kinematics as a sweep
+ * commit (for tests of the kinematic invariants).
+ */
+int orc_apply_torsions(int l, int nb, const int* bonds, int nr, const int* rot, double* X, int n_moves,
+                       const int* moves) {
+    orc_topo T;
+    int rc = topo_build(&T, l, nb, bonds, nr, rot);
+    if (rc != ORC_OK) { topo_free(&T); return rc; }
+    for (int m = 0; m < n_moves; m++) {
+        int r = moves[3 * m], side = moves[3 * m + 1], deg = moves[3 * m + 2];
+        if (r < 0 || r >= nr) { topo_free(&T); return ORC_ERR_ARG; }
+        int a = rot[2 * r], c = rot[2 * r + 1];
+        double p[3], k[3], R[9];
+        const double* piv = X + 3 * (side == 0 ? a : c);
+        p[0] = piv[0]; p[1] = piv[1]; p[2] = piv[2];
+        double ax = X[3 * c] - X[3 * a], ay = X[3 * c + 1] - X[3 * a + 1], az = X[3 * c + 2] - X[3 * a + 2];
+        double nrm = sqrt(ax * ax + ay * ay + az * az);
+        k[0] = ax / nrm; k[1] = ay / nrm; k[2] = az / nrm;
+        axis_angle_matrix(k, deg, R);
+        for (int i = 0; i < l; i++) {
+            int in_left = T.left[(size_t)r * l + i];
+            if ((side == 0) != (in_left != 0)) continue;
+            double y[3];
+            rotate_about(p, R, X + 3 * i, y);
+            X[3 * i] = y[0]; X[3 * i + 1] = y[1]; X[3 * i + 2] = y[2];
+        }
+    }
+    topo_free(&T);
+    return ORC_OK;
+}
