@@ -1,0 +1,284 @@
+/*
+ * gd.h -- C ABI of the MI355X geometric docking library (libgd.so).
+ *
+ * The library docks ligands into a protein pocket with the geometric method
+ * of Gadioli et al., "Tunable Approximations to Control Time-to-Solution in
+ * an HPC Molecular Docking Mini-App": for every ligand it enumerates rigid
+ * orientations in the pocket, sweeps each rotatable bond greedily under the
+ * paper's five tunable knobs (Alg. 2, Section III-C), scores every candidate
+ * pose with the overlap score (Eq. 1, Section III-A) evaluated exactly on an
+ * integer pocket distance grid, rejects intramolecular bumps, and reduces the
+ * orientations to the best poses per ligand.  A differentiable refinement on
+ * a Gaussian-blurred pocket density is provided next to the discrete search.
+ *
+ * Conventions for every call:
+ *  - Every call returns gd_status; nothing throws across the ABI.  On a
+ *    non-OK status gd_last_error() returns a thread-local message and no
+ *    output has been written.  Validation happens before any device work.
+ *  - Host inputs (ligands, quaternions, pocket points) are borrowed for the
+ *    duration of the call only and copied to library-owned device memory.
+ *  - Outputs marked "device" are caller-allocated device buffers of the
+ *    documented size.  Work is enqueued on `stream` (a hipStream_t, NULL =
+ *    the default stream) and the call returns without waiting unless noted.
+ *  - Objects (gd_pocket, gd_batch) belong to the caller and are released with
+ *    their destroy call.  A pocket is immutable after creation and may be
+ *    shared read-only by concurrent calls; one gd_batch must not be used by
+ *    two calls at the same time.
+ *  - Lengths are in Angstrom, angles in integer degrees.
+ */
+#ifndef GD_H
+#define GD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GD_OK = 0,
+    GD_ERR_ARG = 1,      /* null pointer, negative size, bad descriptor field        */
+    GD_ERR_GRAPH = 2,    /* bond index out of range, self/duplicate bond, disconnected
+                            graph, more than GD_MAX_ATOMS atoms                       */
+    GD_ERR_ROTAMER = 3,  /* rotamer is not a bond, not a bridge, or has a terminal end */
+    GD_ERR_KNOB = 4,     /* step not an integer divisor of 360, threshold outside [0,1],
+                            repetitions < 1, top_k outside [1, n_orient], bad quaternion */
+    GD_ERR_OOM = 5,      /* device or host allocation failed                          */
+    GD_ERR_HIP = 6,      /* HIP runtime error (message carries the HIP error string)  */
+    GD_ERR_CAPACITY = 7  /* input exceeds a documented limit (grid size, counts)       */
+} gd_status;
+
+#define GD_MAX_ATOMS 128   /* atoms per ligand */
+#define GD_MAX_ROT 64      /* rotatable bonds per ligand */
+
+/* Message for the last non-OK status on the calling thread ("" if none). */
+const char* gd_last_error(void);
+
+/* ------------------------------------------------------------------------ */
+/* Pocket                                                                    */
+
+typedef struct gd_pocket gd_pocket;
+
+typedef struct {
+    const float* xyz;         /* host, n_points x 3 row-major: PASS sphere centres
+                                 (Section III-A), the pocket point cloud P of Eq. 1 */
+    int32_t n_points;         /* >= 1 */
+    float grid_h;             /* lattice spacing h for Eq. 1, a power of two (0.5) */
+    float pad;                /* margin around the points' bounding box covered by the
+                                 tabulated distance grid (12.0); atoms outside it are
+                                 scored exactly by a slower path                      */
+    float blur_sigma;         /* Gaussian width for the refinement density; 0 = none */
+    float blur_h;             /* lattice spacing of the density grid (0.375)         */
+    float blur_cutoff_sigmas; /* density terms beyond this many sigma are dropped (4) */
+    float blur_pad;           /* margin of the density grid (8.0)                    */
+} gd_pocket_desc;
+
+/*
+ * Build the pocket on the device: the occupied cells floor(P_j / h), the exact
+ * integer squared distance D(c) = min over occupied c' of |c - c'|^2 on the
+ * padded box (uint16), the pocket centroid (FP64, points summed in input
+ * order), and optionally the blurred density grid.  Synchronous.
+ * Errors: GD_ERR_ARG (null, n_points < 1, h not a power of two, negative pad),
+ * GD_ERR_CAPACITY (more than 512 cells per axis, or D would exceed 65535).
+ */
+gd_status gd_create_pocket(const gd_pocket_desc* desc, void* stream, gd_pocket** out);
+gd_status gd_destroy_pocket(gd_pocket* pocket);
+
+typedef struct {
+    int32_t box_lo[3];     /* lattice index of the first cell of the distance grid */
+    int32_t box_dim[3];    /* cells per axis                                        */
+    int32_t n_occupied;    /* distinct occupied cells                               */
+    double centroid[3];    /* pocket centroid                                       */
+    float grid_h;
+    int32_t blur_lo[3];    /* density grid: first node index (node = blur_h * index) */
+    int32_t blur_dim[3];   /* nodes per axis; 0 when no density grid was built      */
+    float blur_h;
+} gd_pocket_info;
+
+gd_status gd_pocket_get_info(const gd_pocket* pocket, gd_pocket_info* info);
+/* Copy the distance grid to host: box_dim[0]*box_dim[1]*box_dim[2] uint16, x fastest. */
+gd_status gd_pocket_read_grid(const gd_pocket* pocket, uint16_t* host_out);
+/* Copy the density grid to host: blur_dim[0]*blur_dim[1]*blur_dim[2] float, x fastest. */
+gd_status gd_pocket_read_density(const gd_pocket* pocket, float* host_out);
+
+/* ------------------------------------------------------------------------ */
+/* Ligands and knobs                                                         */
+
+/*
+ * A ragged batch in CSR form with ligand-local atom indices (host memory).
+ * Atoms, bond graph and rotamers as in Section II: a rotamer is a bond whose
+ * removal splits the ligand into two non-empty fragments.  For rotamer (a,b)
+ * the "left" fragment is the side of a; the list order is the sweep order.
+ */
+typedef struct {
+    int32_t n_ligands;
+    const int32_t* atom_off;  /* n_ligands+1 */
+    const float* x;           /* atom coordinates, structure of arrays */
+    const float* y;
+    const float* z;
+    const int32_t* bond_off;  /* n_ligands+1 */
+    const int32_t* bonds;     /* 2 per bond */
+    const int32_t* rot_off;   /* n_ligands+1 */
+    const int32_t* rot;       /* 2 per rotamer: (a, b) */
+} gd_ligands;
+
+/*
+ * The five knobs of Alg. 2 (Section III-C) plus the rigid orientations, the
+ * size of the per-ligand result and the bump rule.
+ */
+typedef struct {
+    int32_t hp_step_deg;       /* high-precision step, integer divisor of 360           */
+    int32_t lp_step_deg;       /* low-precision step, integer divisor of 360            */
+    float threshold;           /* fragments with relative size <= threshold use lp      */
+    int32_t repetitions;       /* >= 1: passes over the rotamer list                    */
+    int32_t enable_refinement; /* tile peeling (Eq. 2/3) for fragments above threshold  */
+    int32_t n_orient;          /* rigid orientations, 1..65535                          */
+    const double* quats;       /* host, n_orient x 4 unit quaternions (w,x,y,z)         */
+    int32_t top_k;             /* poses kept per ligand, 1..n_orient                     */
+    float clash_dist;          /* bump distance (2.0): infeasible if d < clash_dist     */
+    int32_t clash_min_bonds;   /* only pairs at least this many bonds apart bump (4)    */
+} gd_knobs;
+
+/* One ranked pose of a ligand. */
+typedef struct {
+    int32_t orient;   /* orientation index */
+    int32_t S;        /* integer overlap count: sum over atoms of D(cell(atom)) */
+    int32_t clash;    /* 1 if any pair >= clash_min_bonds apart is closer than clash_dist */
+    int32_t n_atoms;
+    double overlap;   /* Eq. 1 on the lattice: n_atoms / (h^2 S), +inf when S = 0 */
+} gd_pose_rec;
+
+typedef enum {
+    GD_PER_LIGAND = 0, /* one kernel launch per ligand                               */
+    GD_BATCHED = 1     /* one persistent launch over a device work queue, captured as
+                          a HIP graph and replayed on later calls                     */
+} gd_mode;
+
+/* Counters written by a docking call (device int64[GD_N_COUNTERS]). */
+enum {
+    GD_CNT_POSES = 0,      /* candidate poses scored (knob-determined)          */
+    GD_CNT_FALLBACK = 1,   /* candidates re-evaluated in FP64 near a boundary   */
+    GD_CNT_OOB = 2,        /* atom evaluations outside the tabulated grid box   */
+    GD_CNT_SWEEPS = 3,     /* fragment sweeps performed                         */
+    GD_N_COUNTERS = 4
+};
+
+/* ------------------------------------------------------------------------ */
+/* Docking                                                                   */
+
+typedef struct gd_batch gd_batch;
+
+/*
+ * Validate and prepare a ligand batch for one pocket and knob setting: bond
+ * distances, fragments, the pairs each sweep must check, angle schedules and
+ * the work queue order, all copied to the device.  Synchronous on `stream`.
+ * Errors: GD_ERR_GRAPH, GD_ERR_ROTAMER, GD_ERR_KNOB, GD_ERR_ARG, GD_ERR_OOM.
+ */
+gd_status gd_prepare_batch(const gd_pocket* pocket, const gd_ligands* ligands, const gd_knobs* knobs,
+                           void* stream, gd_batch** out);
+gd_status gd_destroy_batch(gd_batch* batch);
+
+typedef struct {
+    int32_t n_ligands, max_atoms, max_rot, repetitions, top_k, n_orient;
+    int64_t poses_expected; /* closed-form candidate count of one docking call */
+    int64_t n_pairs_total;  /* straddling far pairs summed over rotamers         */
+} gd_batch_info;
+gd_status gd_batch_get_info(const gd_batch* batch, gd_batch_info* info);
+
+/*
+ * Dock a prepared batch (Alg. 2 per orientation, then top-k per ligand).
+ * Outputs (device, caller-allocated):
+ *   out       n_ligands * top_k gd_pose_rec, rank order (clash, S, orient) ascending
+ *   angles    n_ligands * top_k * repetitions * max_rot * 2 uint16 (chosen angle of
+ *             each fragment sweep: [rep][rotamer][left,right]); may be NULL
+ *   pose_xyz  n_ligands * top_k * max_atoms * 3 float (final pose, atom-major xyz;
+ *             rows beyond a ligand's atom count are zero); may be NULL
+ *   counters  GD_N_COUNTERS int64, overwritten; may be NULL
+ * Asynchronous on `stream`.
+ */
+gd_status gd_dock_prepared(const gd_pocket* pocket, gd_batch* batch, gd_mode mode, void* stream,
+                           gd_pose_rec* out, uint16_t* angles, float* pose_xyz, int64_t* counters);
+
+/* gd_prepare_batch + gd_dock_prepared + gd_destroy_batch; synchronous. */
+gd_status gd_dock_batch(const gd_pocket* pocket, const gd_ligands* ligands, const gd_knobs* knobs, gd_mode mode,
+                        void* stream, gd_pose_rec* out, uint16_t* angles, float* pose_xyz, int64_t* counters);
+
+/*
+ * Kernel tiling of the docking kernel.  waves_per_block: 1,2,4,8; angle_block:
+ * candidate poses scored side by side per wavefront pass (4, 8, 16, 32);
+ * pairs_per_lane: straddling pairs each lane holds while sweeping the
+ * angles (1, 2, 4, 8).  Results do not depend on the tiling.
+ */
+typedef struct {
+    int32_t waves_per_block, angle_block, pairs_per_lane;
+} gd_tiling;
+gd_status gd_batch_set_tiling(gd_batch* batch, const gd_tiling* tiling);
+gd_status gd_batch_get_tiling(const gd_batch* batch, gd_tiling* tiling);
+/*
+ * Time every tiling on a sample of the batch (HIP events, `reps` runs each)
+ * and keep the fastest; the choice is cached per device, pocket grid size and
+ * knob setting in the file named by cache_path (may be NULL).  Synchronous.
+ */
+gd_status gd_batch_autotune(const gd_pocket* pocket, gd_batch* batch, void* stream, int32_t reps,
+                            const char* cache_path, gd_tiling* chosen);
+
+/* ------------------------------------------------------------------------ */
+/* Exact scoring of given poses                                              */
+
+/*
+ * Score poses exactly: S = sum_i D(floor(x_i / h)) (Eq. 1 on the lattice) and
+ * the whole-ligand bump flag.  Pose p belongs to ligand pose_lig[p] (host) of
+ * `topo` (its bonds define the bump pairs); its coordinates are rows
+ * pose_off[p] .. pose_off[p] + n_atoms-1 of px/py/pz, where pose_off is the
+ * running sum of the poses' atom counts (device arrays).  Outputs device
+ * int32 S_out[n_poses], uint8 clash_out[n_poses].  Asynchronous.
+ */
+gd_status gd_score_poses(const gd_pocket* pocket, const gd_ligands* topo, int32_t n_poses, const int32_t* pose_lig,
+                         const float* px, const float* py, const float* pz, float clash_dist,
+                         int32_t clash_min_bonds, void* stream, int32_t* S_out, uint8_t* clash_out);
+
+/* ------------------------------------------------------------------------ */
+/* Differentiable refinement on the blurred density                          */
+
+/*
+ * The surrogate F(t, q, tau) = sum_i rho~(X_i) where rho~ is the trilinear
+ * interpolation of rho(g) = sum_j exp(-|g - P_j|^2 / (2 sigma^2)) (cutoff) on
+ * the density lattice, and X = R(q/|q|) (FK_tau(X0) - c0) + c0 + t: X0 is the
+ * pose being refined, c0 its centroid, FK_tau rotates, root (atom 0) first,
+ * the side of every rotamer not containing atom 0 by tau_b about its current
+ * axis.  Parameters per pose: t[3], q[4], tau[max_rot] (device float arrays,
+ * rows of n_poses).  X0 as in gd_score_poses.
+ */
+typedef struct {
+    int32_t steps;      /* ascent steps (50)                                      */
+    float lr_t;         /* translation step per unit gradient (A per unit)        */
+    float lr_q;         /* quaternion step                                        */
+    float lr_tau;       /* torsion step (radians per unit gradient)               */
+    float max_dt;       /* cap on |delta t| per step (A)                          */
+    float max_dtau;     /* cap on |delta tau_b| per step (radians)                */
+} gd_refine_opts;
+
+gd_status gd_surrogate_fwd(const gd_pocket* pocket, const gd_ligands* topo, int32_t n_poses, const int32_t* pose_lig,
+                           const float* px, const float* py, const float* pz, const float* t, const float* q,
+                           const float* tau, int32_t tau_stride, void* stream, float* F_out);
+gd_status gd_surrogate_bwd(const gd_pocket* pocket, const gd_ligands* topo, int32_t n_poses, const int32_t* pose_lig,
+                           const float* px, const float* py, const float* pz, const float* t, const float* q,
+                           const float* tau, int32_t tau_stride, const float* dF, void* stream, float* dt_out,
+                           float* dq_out, float* dtau_out);
+
+/*
+ * Refine poses by `steps` ascent steps on F, then judge each refined pose with
+ * the exact discrete score: accepted iff bump-free and S_refined < S_input.
+ * px/py/pz are updated in place with the refined pose where accepted (the
+ * input pose is kept otherwise).  Outputs (device): F_out[n_poses] surrogate
+ * of the final iterate, S_out/clash_out of the returned pose, accepted_out.
+ */
+gd_status gd_refine(const gd_pocket* pocket, const gd_ligands* topo, int32_t n_poses, const int32_t* pose_lig,
+                    float* px, float* py, float* pz, const gd_refine_opts* opts, float clash_dist,
+                    int32_t clash_min_bonds, void* stream, float* F_out, int32_t* S_out, uint8_t* clash_out,
+                    uint8_t* accepted_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GD_H */

@@ -1,0 +1,213 @@
+// C ABI: exact pose scoring and the kernel-tiling autotuner.
+#include <hip/hip_runtime.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "gd_internal.h"
+#include "runtime.h"
+
+namespace gd {
+
+// Stream-ordered device copies of small host arrays, released after the call.
+struct AsyncScratch {
+    hipStream_t s;
+    std::vector<void*> ptrs;
+    explicit AsyncScratch(hipStream_t st) : s(st) {}
+    ~AsyncScratch() {
+        for (void* p : ptrs) (void)hipFreeAsync(p, s);
+    }
+    template <class T>
+    hipError_t put(const std::vector<T>& v, const T** out) {
+        void* p = nullptr;
+        size_t n = std::max<size_t>(v.size() * sizeof(T), 16);
+        hipError_t e = hipMallocAsync(&p, n, s);
+        if (e != hipSuccess) return e;
+        ptrs.push_back(p);
+        if (!v.empty()) {
+            e = hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
+            if (e != hipSuccess) return e;
+        }
+        *out = (const T*)p;
+        return hipSuccess;
+    }
+};
+
+// Validates the pose list against the topology and fills the CSR offsets.
+gd_status pose_layout(const gd_ligands* topo, int32_t n_poses, const int32_t* pose_lig, const TopoHost& T,
+                      std::vector<int32_t>& lig, std::vector<int32_t>& off) {
+    if (n_poses < 0) return fail(GD_ERR_ARG, "n_poses < 0");
+    if (n_poses > 0 && !pose_lig) return fail(GD_ERR_ARG, "null pose_lig");
+    lig.assign(pose_lig, pose_lig + n_poses);
+    off.resize(n_poses);
+    int64_t o = 0;
+    for (int p = 0; p < n_poses; p++) {
+        if (lig[p] < 0 || lig[p] >= topo->n_ligands) return fail(GD_ERR_ARG, "pose %d: ligand index out of range", p);
+        off[p] = (int32_t)o;
+        o += T.n_atoms[lig[p]];
+        if (o > (int64_t)INT32_MAX) return fail(GD_ERR_CAPACITY, "more than 2^31 pose atoms");
+    }
+    return GD_OK;
+}
+
+gd_status score_poses(const gd_pocket* P, const gd_ligands* topo, int32_t n_poses, const int32_t* pose_lig,
+                      const float* px, const float* py, const float* pz, float clash_dist, int32_t min_bonds,
+                      hipStream_t s, int32_t* S_out, uint8_t* clash_out) {
+    if (!P || !topo || !S_out || !clash_out) return fail(GD_ERR_ARG, "gd_score_poses: null argument");
+    if (n_poses > 0 && (!px || !py || !pz)) return fail(GD_ERR_ARG, "gd_score_poses: null coordinates");
+    if (!(clash_dist >= 0.f) || clash_dist > 100.f) return fail(GD_ERR_ARG, "gd_score_poses: bad clash_dist");
+    TopoHost T;
+    gd_status st;
+    if ((st = prepare_topology(topo, min_bonds, T)) != GD_OK) return st;
+    std::vector<int32_t> lig, off;
+    if ((st = pose_layout(topo, n_poses, pose_lig, T, lig, off)) != GD_OK) return st;
+    if (n_poses == 0) return GD_OK;
+    AsyncScratch A(s);
+    ScoreDev D;
+    hipError_t e;
+    if ((e = A.put(lig, &D.pose_lig)) != hipSuccess || (e = A.put(off, &D.pose_off)) != hipSuccess ||
+        (e = A.put(T.n_atoms, &D.n_atoms)) != hipSuccess || (e = A.put(T.far_off, &D.far_off)) != hipSuccess ||
+        (e = A.put(T.n_far, &D.n_far)) != hipSuccess || (e = A.put(T.efar, &D.efar)) != hipSuccess)
+        return hip_fail(e, "gd_score_poses");
+    D.px = px;
+    D.py = py;
+    D.pz = pz;
+    const double cd = (double)clash_dist;
+    if ((e = launch_score(P->dev, D, n_poses, cd * cd, S_out, clash_out, s)) != hipSuccess)
+        return hip_fail(e, "gd_score_poses");
+    return GD_OK;
+}
+
+// --------------------------------------------------------------------------
+// autotuner
+
+static std::string tune_key(const gd_pocket* P, const gd_batch* B) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    hipDeviceProp_t prop;
+    (void)hipGetDeviceProperties(&prop, dev);
+    std::ostringstream k;
+    int lbin = (B->dev.lmax + 31) / 32;
+    k << prop.gcnArchName << "|box" << P->dev.dim[0] << "x" << P->dev.dim[1] << "x" << P->dev.dim[2] << "|n"
+      << B->nmax << "|l" << lbin << "|r" << B->dev.reps;
+    std::string s = k.str();
+    for (char& c : s)
+        if (c == ' ') c = '_';
+    return s;
+}
+
+static bool cache_lookup(const char* path, const std::string& key, Tiling& t) {
+    if (!path) return false;
+    std::ifstream f(path);
+    std::string line;
+    bool found = false;
+    while (std::getline(f, line)) {
+        std::istringstream is(line);
+        std::string k;
+        Tiling c;
+        if (is >> k >> c.waves_per_block >> c.angle_block >> c.pairs_per_lane && k == key) {
+            t = c;
+            found = true;
+        }
+    }
+    return found;
+}
+
+static void cache_store(const char* path, const std::string& key, const Tiling& t) {
+    if (!path) return;
+    std::ofstream f(path, std::ios::app);
+    f << key << " " << t.waves_per_block << " " << t.angle_block << " " << t.pairs_per_lane << "\n";
+}
+
+gd_status autotune(const gd_pocket* P, gd_batch* B, hipStream_t s, int reps, const char* cache, gd_tiling* chosen) {
+    if (!P || !B) return fail(GD_ERR_ARG, "gd_batch_autotune: null argument");
+    if (reps < 1) reps = 1;
+    const std::string key = tune_key(P, B);
+    Tiling best = B->tiling;
+    if (!cache_lookup(cache, key, best)) {
+        // a strided sample of the work queue keeps the LPT mix of costs
+        std::vector<int32_t> items(2 * (size_t)B->dev.n_items);
+        hipError_t e = hipMemcpy(items.data(), B->dev.items, items.size() * 4, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "gd_batch_autotune");
+        const int want = 4096;
+        int stride = std::max(1, B->dev.n_items / want);
+        std::vector<int32_t> sample;
+        for (int i = 0; i < B->dev.n_items; i += stride) {
+            sample.push_back(items[2 * i]);
+            sample.push_back(items[2 * i + 1]);
+        }
+        DevBuf sb;
+        if ((e = sb.upload(sample.data(), sample.size() * 4, s)) != hipSuccess) return hip_fail(e, "gd_batch_autotune");
+        BatchDev D = B->dev;
+        D.items = (const int32_t*)sb.ptr;
+        D.n_items = (int32_t)(sample.size() / 2);
+        hipEvent_t e0, e1;
+        (void)hipEventCreate(&e0);
+        (void)hipEventCreate(&e1);
+        float best_ms = 1e30f;
+        for (int w : {2, 4, 8})
+            for (int nb : {4, 8, 16})
+                for (int ppl : {2, 4, 8}) {
+                    Tiling t;
+                    t.waves_per_block = w;
+                    t.angle_block = nb;
+                    t.pairs_per_lane = ppl;
+                    if (dock_lds_bytes(D.lmax, B->nmax, w) > lds_limit_per_block()) continue;
+                    int grid = persistent_grid(t, D.lmax, B->nmax, D.n_items);
+                    float tot = 0.f;
+                    bool ok = true;
+                    for (int r = 0; r <= reps && ok; r++) {  // first run warms up
+                        ok &= launch_reset(D.head, D.counters, s) == hipSuccess;
+                        (void)hipEventRecord(e0, s);
+                        ok &= launch_dock(P->dev, D, B->nmax, t, true, 0, grid, s) == hipSuccess;
+                        (void)hipEventRecord(e1, s);
+                        ok &= hipEventSynchronize(e1) == hipSuccess;
+                        float ms = 0.f;
+                        (void)hipEventElapsedTime(&ms, e0, e1);
+                        if (r > 0) tot += ms;
+                    }
+                    if (!ok) continue;
+                    if (tot < best_ms) {
+                        best_ms = tot;
+                        best = t;
+                    }
+                }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (best_ms < 1e30f) cache_store(cache, key, best);
+    }
+    B->tiling = best;
+    if (chosen) {
+        chosen->waves_per_block = best.waves_per_block;
+        chosen->angle_block = best.angle_block;
+        chosen->pairs_per_lane = best.pairs_per_lane;
+    }
+    return GD_OK;
+}
+
+}  // namespace gd
+
+using namespace gd;
+
+extern "C" {
+
+gd_status gd_score_poses(const gd_pocket* pocket, const gd_ligands* topo, int32_t n_poses, const int32_t* pose_lig,
+                         const float* px, const float* py, const float* pz, float clash_dist, int32_t clash_min_bonds,
+                         void* stream, int32_t* S_out, uint8_t* clash_out) {
+    clear_error();
+    return score_poses(pocket, topo, n_poses, pose_lig, px, py, pz, clash_dist, clash_min_bonds, (hipStream_t)stream,
+                       S_out, clash_out);
+}
+
+gd_status gd_batch_autotune(const gd_pocket* pocket, gd_batch* batch, void* stream, int32_t reps,
+                            const char* cache_path, gd_tiling* chosen) {
+    clear_error();
+    return autotune(pocket, batch, (hipStream_t)stream, reps, cache_path, chosen);
+}
+
+}  // extern "C"

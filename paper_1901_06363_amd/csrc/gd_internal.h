@@ -1,0 +1,128 @@
+// Internal data layout shared by the host runtime and the HIP kernels.
+#pragma once
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/gd.h"
+
+namespace gd {
+
+constexpr int kWave = 64;
+constexpr int kMaxAtoms = GD_MAX_ATOMS;
+constexpr int kMaxRot = GD_MAX_ROT;
+constexpr int kMaxSched = 360;  // longest angle schedule (1-degree steps)
+
+// Sweep schedule of one fragment (Alg. 2): flat list {k*step} or tile peeling.
+enum SchedMode : int32_t { kFlat = 0, kPeel = 1 };
+
+struct alignas(16) RotInfo {
+    int32_t a, c;             // bond atoms; a is on the left side
+    int32_t pair_off;         // first straddling far pair (global index)
+    int32_t n_pairs;
+    int32_t mv_off[2];        // moving-atom lists of the left / right sweep
+    int32_t n_mv[2];
+    int32_t mode[2];          // kFlat or kPeel per side
+    int32_t step[2];          // flat: step; peel: fine step hp
+    int32_t tile[2];          // peel: tile size x
+    int32_t off[2];           // peel: offset of the central element
+    int32_t n_cand[2];        // candidates of this side per repetition
+};
+
+struct alignas(16) LigMeta {
+    double cL[3];             // ligand centroid (input order sum / l)
+    int32_t atom_off;         // into the SoA coordinate arrays
+    int32_t l;                // atoms
+    int32_t nr;               // rotamers
+    int32_t rot_off;          // into RotInfo
+    int32_t far_off;          // endpoint far pairs (i<j), packed i | j<<8
+    int32_t n_far;
+    int32_t ang_off;          // per-orientation angle records of this ligand
+    int32_t pad0;
+    int64_t key_off;          // first endpoint key of this ligand
+    int64_t cand_per_orient;  // closed-form candidates per orientation
+};
+
+// Device view of a pocket.
+struct PocketDev {
+    const uint16_t* edt;      // D on the box, x fastest
+    const int32_t* occ;       // occupied cells (global lattice), 3 per cell
+    int32_t n_occ;
+    int32_t lo[3];            // box origin (lattice index)
+    int32_t dim[3];
+    double h, inv_h;
+    double cP[3];
+    // density grid
+    const float* rho;
+    int32_t blo[3], bdim[3];
+    float bh, inv_bh;
+};
+
+// Kernel-visible view of a prepared batch.
+struct BatchDev {
+    const LigMeta* lig;
+    const RotInfo* rot;
+    const float* x;
+    const float* y;
+    const float* z;
+    const uint16_t* pairs;    // straddling far pairs: left atom | right atom << 8
+    const uint8_t* mv;        // moving-atom lists
+    const uint16_t* efar;     // whole-ligand far pairs
+    const double* qmat;       // n_orient x 9 rotation matrices of the orientations
+    int32_t n_lig, n_orient, reps, top_k;
+    int32_t lmax, rmax;
+    double cd2;               // clash distance squared (FP64, as the oracle)
+    float cd2f;
+    // outputs of the sweep stage
+    uint64_t* keys;           // per (ligand, orientation): clash<<63 | S<<32 | orient
+    uint16_t* ang;            // per (ligand, orientation): reps*nr*2 chosen angles
+    // work queue of the batched form
+    const int32_t* items;     // (ligand, first orientation) pairs in LPT order
+    int32_t n_items, orient_per_item;
+    int32_t* head;            // queue head (reset before each launch)
+    unsigned long long* counters;
+};
+
+// Kernel-visible view of poses to score (CSR by pose).
+struct ScoreDev {
+    const int32_t* pose_lig;  // ligand of each pose
+    const int32_t* pose_off;  // first coordinate row of each pose
+    const int32_t* n_atoms;   // per ligand
+    const int32_t* far_off;   // per ligand, into efar
+    const int32_t* n_far;
+    const uint16_t* efar;     // far pairs i<j, packed i | j<<8
+    const float* px;
+    const float* py;
+    const float* pz;
+};
+
+struct Tiling {
+    int waves_per_block = 4;
+    int angle_block = 8;
+    int pairs_per_lane = 4;
+};
+
+// Trig tables of integer degrees (libm, FP64, and their FP32 roundings).
+void trig_tables(double* c64, double* s64, float* c32, float* s32);
+
+}  // namespace gd
+
+#include <hip/hip_runtime.h>
+
+namespace gd {
+// launchers (dock.hip)
+hipError_t upload_trig_tables();
+size_t dock_lds_bytes(int lmax, int nmax, int waves);
+size_t lds_limit_per_block();
+hipError_t launch_dock(const PocketDev& P, const BatchDev& B, int nmax, const Tiling& t, bool persistent, int lig,
+                       int grid, hipStream_t s);
+int persistent_grid(const Tiling& t, int lmax, int nmax, int n_items);
+hipError_t launch_reset(int* head, unsigned long long* counters, hipStream_t s);
+hipError_t launch_topk(const BatchDev& B, gd_pose_rec* out, uint16_t* ang_out, double h, hipStream_t s);
+hipError_t launch_score(const PocketDev& P, const ScoreDev& S, int n_poses, double cd2, int32_t* S_out,
+                        uint8_t* clash_out, hipStream_t s);
+hipError_t launch_replay(const PocketDev& P, const BatchDev& B, const gd_pose_rec* recs, float* xyz, int nmax,
+                         hipStream_t s);
+
+}  // namespace gd

@@ -1,0 +1,70 @@
+// Host-side objects behind the opaque handles of gd.h.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "gd_internal.h"
+
+namespace gd {
+
+// Owned device allocation.
+struct DevBuf {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf();
+    void reset();
+    hipError_t alloc(size_t n);
+    hipError_t upload(const void* src, size_t n, hipStream_t s);  // synchronous
+};
+
+struct GraphKey {
+    const void* pocket;
+    const void* out;
+    const void* angles;
+    const void* xyz;
+    const void* counters;
+    int w, nb, ppl;
+    bool operator==(const GraphKey& o) const {
+        return pocket == o.pocket && out == o.out && angles == o.angles && xyz == o.xyz && counters == o.counters &&
+               w == o.w && nb == o.nb && ppl == o.ppl;
+    }
+};
+
+gd_status fail(gd_status st, const char* fmt, ...);
+gd_status hip_fail(hipError_t e, const char* where);
+void clear_error();
+const char* last_error();
+int tile_size(int hp);
+
+// Host topology of a ligand set for scoring: atom counts and far pairs.
+struct TopoHost {
+    std::vector<int32_t> n_atoms, far_off, n_far;
+    std::vector<uint16_t> efar;
+};
+gd_status prepare_topology(const gd_ligands* L, int min_bonds, TopoHost& T);
+gd_status validate_ligands_struct(const gd_ligands* L);
+
+}  // namespace gd
+
+struct gd_pocket {
+    gd::PocketDev dev{};
+    gd::DevBuf edt, occ, rho;
+    double centroid[3] = {0, 0, 0};
+    double blur_h = 0;
+};
+
+struct gd_batch {
+    gd::BatchDev dev{};
+    gd::DevBuf lig, rot, x, y, z, pairs, mv, efar, qmat, items, keys, ang, head, counters;
+    gd_batch_info info{};
+    gd::Tiling tiling;
+    int nmax = 1;
+    double h = 0.5;
+    hipGraphExec_t graph_exec = nullptr;
+    gd::GraphKey graph_key{};
+    ~gd_batch();
+};
