@@ -1,0 +1,203 @@
+#!/usr/bin/env python
+"""Benchmark of the docking hot path on one MI355X.
+
+Workload (the screening configuration): 10,000 synthetic ligands (20-80 heavy
+atoms, 2-12 rotatable bonds) x one 4,000-point ellipsoid pocket (12/9/7 A,
+0.5 A grid), 512 rigid orientations, 15-degree torsion steps, one repetition,
+top-8 poses per ligand.  One step = one batched docking call over the whole
+batch: queue reset, the persistent docking kernel (placement, greedy sweeps,
+scoring, bump tests, FP64 commits, endpoint), top-k reduction and replay of
+the selected poses.  The batch is prepared (validated, topology and work queue
+built, copied to HBM) before the timed region.
+
+Prints one JSON line: poses scored per second (the knob-determined candidate
+count; every candidate is scored and bump-tested), ligands per second, the
+per-ligand-launch form on a subset for the batched-vs-per-ligand comparison,
+the roofline of the docking kernel and the CPU oracle baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X published FP32 vector peak
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(w, ligs, q, n_sample):
+    """The FP64 oracle, single-threaded, on the first n_sample ligands."""
+    import oracle
+    pts = w.pocket_points()
+    O = oracle.OraclePocket(pts, 0.5)
+    kn = oracle.knobs(**w.knob_dict())
+    t0 = time.perf_counter()
+    poses = 0
+    for i in range(n_sample):
+        r = oracle.dock(O, ligs.ligand(i), kn, q, want_xyz=False)
+        poses += r.n_cand
+    dt = time.perf_counter() - t0
+    return dict(value=poses / dt, unit="poses/s", cores=1, kind="oracle",
+                sample="first %d ligands of the workload, all %d orientations, %d candidate poses in %.1f s"
+                       % (n_sample, len(q), poses, dt))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--per-ligand-sample", type=int, default=1000)
+    ap.add_argument("--cpu-sample", type=int, default=48)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-per-ligand", action="store_true")
+    ap.add_argument("--tiling", type=str, default="")
+    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--n-ligands", type=int, default=0, help="override the ligand count (testing only)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (ligand batches shard trivially "
+              "across GPUs, see DESIGN.md); got --gpus %d" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1901_06363_amd as gd
+    from synth import configs
+
+    torch.cuda.set_device(0)
+    w = configs.SCREEN
+    n_lig = args.n_ligands or w.n_ligands
+    t = time.perf_counter()
+    ligs = w.ligands(0, n_lig)
+    pts = w.pocket_points()
+    q = w.quaternions()
+    log("inputs generated in %.1f s" % (time.perf_counter() - t))
+
+    stream = torch.cuda.current_stream()
+    P = gd.Pocket(pts, 0.5, 12.0)
+    t = time.perf_counter()
+    B = gd.Batch(P, ligs, q, hp=w.hp, top_k=w.top_k)
+    prep_s = time.perf_counter() - t
+    log("batch prepared in %.2f s: %d ligands, %d poses per call" % (prep_s, B.n_ligands, B.poses_expected))
+    if args.tiling:
+        B.set_tiling(*[int(v) for v in args.tiling.split(",")])
+    if args.autotune:
+        log("autotuned tiling", B.autotune(reps=1))
+    tiling = B.tiling()
+
+    out = B.alloc_outputs(want_angles=True, want_xyz=True)
+    for _ in range(args.warmup):
+        B.dock(gd.BATCHED, out)
+    torch.cuda.synchronize()
+    log("warmup done")
+
+    B.enable_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        B.dock(gd.BATCHED, out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kernel_ms = B.read_timing()
+    B.enable_timing(False)
+    dt = t1 - t0
+    host = out.host()
+    counters = host["counters"]
+    assert counters[0] == B.poses_expected, (counters[0], B.poses_expected)
+    value = B.poses_expected * args.steps / dt
+    ms_per_step = dt * 1e3 / args.steps
+    k_ms = float(np.mean(kernel_ms))
+    log("timed %d steps: %.1f ms/step, docking kernel %.1f ms" % (args.steps, ms_per_step, k_ms))
+
+    # batched vs per-ligand launches on the same subset, and exactness between them
+    per_lig = None
+    if not args.no_per_ligand and args.per_ligand_sample > 0:
+        ns = min(args.per_ligand_sample, n_lig)
+        sub = w.ligands(0, ns)
+        Bs = gd.Batch(P, sub, q, hp=w.hp, top_k=w.top_k)
+        rb = Bs.dock(gd.BATCHED)
+        torch.cuda.synchronize()
+        tb0 = time.perf_counter()
+        rb = Bs.dock(gd.BATCHED, rb)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - tb0
+        hb = rb.host()
+        rp = Bs.dock(gd.PER_LIGAND)
+        torch.cuda.synchronize()
+        tp0 = time.perf_counter()
+        rp = Bs.dock(gd.PER_LIGAND, rp)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - tp0
+        hp_ = rp.host()
+        same = all(np.array_equal(hb[k], hp_[k]) for k in ("orient", "S", "clash", "angles", "xyz"))
+        per_lig = dict(ligands=ns, per_ligand_poses_per_s=Bs.poses_expected / tp,
+                       batched_poses_per_s=Bs.poses_expected / tb, batched_over_per_ligand=tp / tb,
+                       results_identical=bool(same))
+        log("per-ligand subset:", per_lig)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(w, ligs, q, min(args.cpu_sample, n_lig))
+        cpu["cores"] = 1
+        log("cpu baseline:", cpu)
+
+    achieved = B.algo_flops / (k_ms * 1e-3) / 1e12
+    line = {
+        "metric": "poses scored/s (batched persistent form; ligands/s and per-ligand launches alongside)",
+        "value": value,
+        "unit": "poses/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "screen: %d ligands (20-80 atoms, 2-12 rotatable bonds) x 4,000-point pocket, "
+                        "512 orientations, 15-degree steps, 1 repetition, top-8" % n_lig,
+            "ligands": n_lig,
+            "orientations": len(q),
+            "hp_step_deg": w.hp,
+            "poses_per_step": B.poses_expected,
+            "tiling": list(tiling),
+        },
+        "ligands_per_s": n_lig * args.steps / dt,
+        "atoms_per_s": B.n_atoms_total * args.steps / dt,
+        "fallback_per_pose": float(counters[1]) / float(counters[0]),
+        "oob_lookups": int(counters[2]),
+        "prep_s": prep_s,
+        "end_to_end_poses_per_s_incl_prep": B.poses_expected / (prep_s + dt / args.steps),
+        "per_ligand": per_lig,
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": FP32_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
+            "traffic": None,
+            "kernel": "dock_persistent_kernel",
+            "kernel_ms": k_ms,
+            "algo_flops_per_launch": B.algo_flops,
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -180,10 +180,26 @@ gd_status gd_destroy_batch(gd_batch* batch);
 
 typedef struct {
     int32_t n_ligands, max_atoms, max_rot, repetitions, top_k, n_orient;
-    int64_t poses_expected; /* closed-form candidate count of one docking call */
-    int64_t n_pairs_total;  /* straddling far pairs summed over rotamers         */
+    int64_t poses_expected; /* closed-form candidate count of one docking call    */
+    int64_t n_pairs_total;  /* straddling far pairs summed over rotamers            */
+    int64_t n_atoms_total;  /* atoms summed over ligands                            */
+    double algo_flops;      /* direct-evaluation work of one docking call: per
+                               candidate 24 flop per moving atom (rotation about
+                               the pivot and cell index) + 8 flop per straddling
+                               far pair; per endpoint 3 per atom + 8 per far pair */
+    double algo_bytes;      /* distance-grid bytes gathered: 2 per atom lookup    */
 } gd_batch_info;
 gd_status gd_batch_get_info(const gd_batch* batch, gd_batch_info* info);
+
+/*
+ * Kernel timing: when enabled, every docking call of the batch brackets its
+ * docking kernel with a pair of HIP events on the call's stream (kept in a
+ * ring of the last 256 calls).  gd_batch_read_timing waits for the recorded
+ * events and writes up to max_n durations in milliseconds, oldest first,
+ * returning their number in *n_out; reading clears the ring.
+ */
+gd_status gd_batch_enable_timing(gd_batch* batch, int32_t enable);
+gd_status gd_batch_read_timing(gd_batch* batch, float* ms_out, int32_t max_n, int32_t* n_out);
 
 /*
  * Dock a prepared batch (Alg. 2 per orientation, then top-k per ligand).

@@ -163,11 +163,23 @@ class Batch:
         self.n_ligands, self.max_atoms, self.max_rot = inf.n_ligands, inf.max_atoms, inf.max_rot
         self.repetitions, self.top_k, self.n_orient = inf.repetitions, inf.top_k, inf.n_orient
         self.poses_expected, self.n_pairs_total = inf.poses_expected, inf.n_pairs_total
+        self.n_atoms_total, self.algo_flops, self.algo_bytes = inf.n_atoms_total, inf.algo_flops, inf.algo_bytes
 
     def __del__(self):
         if getattr(self, "_h", None) and _abi._lib is not None:
             _abi._lib.gd_destroy_batch(self._h)
             self._h = None
+
+    def enable_timing(self, on=True):
+        """Bracket the docking kernel of every later call with HIP events."""
+        _abi.check(_abi.load().gd_batch_enable_timing(self._h, int(bool(on))))
+
+    def read_timing(self, max_n=256):
+        """Docking-kernel durations (ms) of the calls since the last read, oldest first."""
+        buf = (ctypes.c_float * max_n)()
+        n = ctypes.c_int32(0)
+        _abi.check(_abi.load().gd_batch_read_timing(self._h, buf, int(max_n), ctypes.byref(n)))
+        return [buf[i] for i in range(n.value)]
 
     def set_tiling(self, waves_per_block, angle_block, pairs_per_lane):
         t = _abi.Tiling(waves_per_block, angle_block, pairs_per_lane)

@@ -41,7 +41,8 @@ class Knobs(ctypes.Structure):
 
 class BatchInfo(ctypes.Structure):
     _fields_ = [("n_ligands", I32), ("max_atoms", I32), ("max_rot", I32), ("repetitions", I32), ("top_k", I32),
-                ("n_orient", I32), ("poses_expected", ctypes.c_int64), ("n_pairs_total", ctypes.c_int64)]
+                ("n_orient", I32), ("poses_expected", ctypes.c_int64), ("n_pairs_total", ctypes.c_int64),
+                ("n_atoms_total", ctypes.c_int64), ("algo_flops", ctypes.c_double), ("algo_bytes", ctypes.c_double)]
 
 
 class Tiling(ctypes.Structure):
@@ -64,6 +65,8 @@ SIGNATURES = [
     ("gd_destroy_batch", I32, [P]),
     ("gd_batch_get_info", I32, [P, P]),
     ("gd_batch_set_tiling", I32, [P, P]),
+    ("gd_batch_enable_timing", I32, [P, I32]),
+    ("gd_batch_read_timing", I32, [P, P, I32, P]),
     ("gd_batch_get_tiling", I32, [P, P]),
     ("gd_batch_autotune", I32, [P, P, P, I32, ctypes.c_char_p, P]),
     ("gd_dock_prepared", I32, [P, P, I32, P, P, P, P, P]),

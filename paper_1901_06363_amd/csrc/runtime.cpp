@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cstdlib>
+#include <functional>
 #include <limits>
 #include <map>
 #include <mutex>
@@ -431,6 +432,7 @@ struct LigPrep {
     std::vector<uint16_t> pairs, efar;
     std::vector<uint8_t> mv;
     double cost = 0;
+    double flops = 0, bytes = 0;  // direct-evaluation work per orientation
     int nmax = 1;
     int64_t n_pairs = 0;
 };
@@ -504,12 +506,16 @@ static void prep_one(const gd_ligands* L, const gd_knobs* K, int i, bool topo_on
             }
             cand += ri.n_cand[side];
             cost += (double)ri.n_cand[side] * (ri.n_mv[side] + 0.5 * ri.n_pairs + 8);
+            out.flops += (double)ri.n_cand[side] * (24.0 * ri.n_mv[side] + 8.0 * ri.n_pairs);
+            out.bytes += (double)ri.n_cand[side] * 2.0 * ri.n_mv[side];
         }
         out.n_pairs += ri.n_pairs;
         out.rot.push_back(ri);
     }
     M.cand_per_orient = cand * K->repetitions + 1;
     out.cost = cost * K->repetitions + l;
+    out.flops = out.flops * K->repetitions + 3.0 * l + 8.0 * (double)out.efar.size();
+    out.bytes = out.bytes * K->repetitions + 2.0 * l;
 }
 
 static gd_status prep_all(const gd_ligands* L, const gd_knobs* K, bool topo_only, int minb,
@@ -581,6 +587,7 @@ gd_status prepare_batch(const gd_pocket* pocket, const gd_ligands* L, const gd_k
     std::vector<uint8_t> mv;
     int lmax = 1, rmax = 0, nmax = 1;
     int64_t key_off = 0, ang_off = 0, poses = 0, npairs = 0;
+    double flops = 0, bytes = 0;
     for (int i = 0; i < n; i++) {
         LigPrep& p = preps[i];
         LigMeta m = p.meta;
@@ -604,6 +611,8 @@ gd_status prepare_batch(const gd_pocket* pocket, const gd_ligands* L, const gd_k
         ang_off += (int64_t)no * K->repetitions * m.nr * 2;
         poses += m.cand_per_orient * no;
         npairs += p.n_pairs;
+        flops += p.flops * no;
+        bytes += p.bytes * no;
         lmax = std::max(lmax, m.l);
         rmax = std::max(rmax, m.nr);
         nmax = std::max(nmax, p.nmax);
@@ -682,6 +691,9 @@ gd_status prepare_batch(const gd_pocket* pocket, const gd_ligands* L, const gd_k
     B->info.n_orient = no;
     B->info.poses_expected = poses;
     B->info.n_pairs_total = npairs;
+    B->info.n_atoms_total = atoms;
+    B->info.algo_flops = flops;
+    B->info.algo_bytes = bytes;
     B->h = pocket->dev.h;
     while (B->tiling.waves_per_block > 1 &&
            dock_lds_bytes(lmax, nmax, B->tiling.waves_per_block) > lds_limit_per_block())
@@ -698,25 +710,60 @@ gd_status prepare_batch(const gd_pocket* pocket, const gd_ligands* L, const gd_k
     return GD_OK;
 }
 
-static hipError_t enqueue_dock(const gd_pocket* P, gd_batch* B, gd_mode mode, hipStream_t s, gd_pose_rec* out,
-                               uint16_t* angles, float* pose_xyz, int64_t* counters) {
+// The two stages of a docking call: queue reset + docking kernel, then top-k
+// and pose replay.
+static hipError_t enqueue_dock_stage(const gd_pocket* P, gd_batch* B, gd_mode mode, hipStream_t s, int64_t* counters) {
     BatchDev D = B->dev;
     if (counters) D.counters = (unsigned long long*)counters;
     hipError_t e;
     if ((e = launch_reset(D.head, D.counters, s)) != hipSuccess) return e;
     if (mode == GD_BATCHED) {
         int grid = persistent_grid(B->tiling, D.lmax, B->nmax, D.n_items);
-        if ((e = launch_dock(P->dev, D, B->nmax, B->tiling, true, 0, grid, s)) != hipSuccess) return e;
-    } else {
-        const int w = B->tiling.waves_per_block;
-        const int grid = (D.n_orient + w - 1) / w;
-        for (int i = 0; i < D.n_lig; i++)
-            if ((e = launch_dock(P->dev, D, B->nmax, B->tiling, false, i, grid, s)) != hipSuccess) return e;
+        return launch_dock(P->dev, D, B->nmax, B->tiling, true, 0, grid, s);
     }
-    if ((e = launch_topk(D, out, angles, B->h, s)) != hipSuccess) return e;
-    if (pose_xyz)
-        if ((e = launch_replay(P->dev, D, out, pose_xyz, B->nmax, s)) != hipSuccess) return e;
+    const int w = B->tiling.waves_per_block;
+    const int grid = (D.n_orient + w - 1) / w;
+    for (int i = 0; i < D.n_lig; i++)
+        if ((e = launch_dock(P->dev, D, B->nmax, B->tiling, false, i, grid, s)) != hipSuccess) return e;
     return hipSuccess;
+}
+
+static hipError_t enqueue_post_stage(const gd_pocket* P, gd_batch* B, hipStream_t s, gd_pose_rec* out,
+                                     uint16_t* angles, float* pose_xyz) {
+    hipError_t e;
+    if ((e = launch_topk(B->dev, out, angles, B->h, s)) != hipSuccess) return e;
+    if (pose_xyz)
+        if ((e = launch_replay(P->dev, B->dev, out, pose_xyz, B->nmax, s)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+static hipError_t capture(hipStream_t s, hipGraphExec_t* exec, const std::function<hipError_t()>& body) {
+    hipGraph_t g;
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t le = body();
+    e = hipStreamEndCapture(s, &g);
+    if (le != hipSuccess) return le;
+    if (e != hipSuccess) return e;
+    e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    return e;
+}
+
+static hipError_t timing_mark(gd_batch* B, hipStream_t s, bool start) {
+    if (!B->timing) return hipSuccess;
+    int slot = (B->ring_head) % gd_batch::kRing;
+    hipEvent_t* ev = start ? &B->ev0[slot] : &B->ev1[slot];
+    if (!*ev) {
+        hipError_t e = hipEventCreate(ev);
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = hipEventRecord(*ev, s);
+    if (e == hipSuccess && !start) {
+        B->ring_head = (B->ring_head + 1) % gd_batch::kRing;
+        B->ring_count = std::min(B->ring_count + 1, gd_batch::kRing);
+    }
+    return e;
 }
 
 gd_status dock_prepared(const gd_pocket* P, gd_batch* B, gd_mode mode, hipStream_t s, gd_pose_rec* out,
@@ -730,37 +777,40 @@ gd_status dock_prepared(const gd_pocket* P, gd_batch* B, gd_mode mode, hipStream
     hipError_t e;
     const bool use_graph = mode == GD_BATCHED && s != nullptr && !getenv("GD_NO_GRAPH");
     if (!use_graph) {
-        if ((e = enqueue_dock(P, B, mode, s, out, angles, pose_xyz, counters)) != hipSuccess)
+        if ((e = timing_mark(B, s, true)) != hipSuccess || (e = enqueue_dock_stage(P, B, mode, s, counters)) != hipSuccess ||
+            (e = timing_mark(B, s, false)) != hipSuccess || (e = enqueue_post_stage(P, B, s, out, angles, pose_xyz)) != hipSuccess)
             return hip_fail(e, "gd_dock_prepared");
         return GD_OK;
     }
     GraphKey key{P, out, angles, pose_xyz, counters, B->tiling.waves_per_block, B->tiling.angle_block,
                  B->tiling.pairs_per_lane};
-    if (!B->graph_exec || !(B->graph_key == key)) {
-        if (B->graph_exec) {
-            (void)hipGraphExecDestroy(B->graph_exec);
-            B->graph_exec = nullptr;
-        }
-        hipGraph_t g;
-        if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess)
-            return hip_fail(e, "gd_dock_prepared: capture");
-        hipError_t le = enqueue_dock(P, B, mode, s, out, angles, pose_xyz, counters);
-        e = hipStreamEndCapture(s, &g);
-        if (le != hipSuccess) return hip_fail(le, "gd_dock_prepared: capture");
-        if (e != hipSuccess) return hip_fail(e, "gd_dock_prepared: capture");
-        e = hipGraphInstantiate(&B->graph_exec, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (e != hipSuccess) return hip_fail(e, "gd_dock_prepared: instantiate");
+    if (!B->graph_dock || !B->graph_post || !(B->graph_key == key)) {
+        if (B->graph_dock) (void)hipGraphExecDestroy(B->graph_dock);
+        if (B->graph_post) (void)hipGraphExecDestroy(B->graph_post);
+        B->graph_dock = B->graph_post = nullptr;
+        if ((e = capture(s, &B->graph_dock, [&]() { return enqueue_dock_stage(P, B, mode, s, counters); })) !=
+            hipSuccess)
+            return hip_fail(e, "gd_dock_prepared: graph capture");
+        if ((e = capture(s, &B->graph_post, [&]() { return enqueue_post_stage(P, B, s, out, angles, pose_xyz); })) !=
+            hipSuccess)
+            return hip_fail(e, "gd_dock_prepared: graph capture");
         B->graph_key = key;
     }
-    if ((e = hipGraphLaunch(B->graph_exec, s)) != hipSuccess) return hip_fail(e, "gd_dock_prepared: launch");
+    if ((e = timing_mark(B, s, true)) != hipSuccess || (e = hipGraphLaunch(B->graph_dock, s)) != hipSuccess ||
+        (e = timing_mark(B, s, false)) != hipSuccess || (e = hipGraphLaunch(B->graph_post, s)) != hipSuccess)
+        return hip_fail(e, "gd_dock_prepared: graph launch");
     return GD_OK;
 }
 
 }  // namespace gd
 
 gd_batch::~gd_batch() {
-    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph_dock) (void)hipGraphExecDestroy(graph_dock);
+    if (graph_post) (void)hipGraphExecDestroy(graph_post);
+    for (int i = 0; i < kRing; i++) {
+        if (ev0[i]) (void)hipEventDestroy(ev0[i]);
+        if (ev1[i]) (void)hipEventDestroy(ev1[i]);
+    }
 }
 
 // ----------------------------------------------------------------------------
@@ -830,6 +880,34 @@ gd_status gd_batch_get_info(const gd_batch* B, gd_batch_info* info) {
     clear_error();
     if (!B || !info) return fail(GD_ERR_ARG, "gd_batch_get_info: null argument");
     *info = B->info;
+    return GD_OK;
+}
+
+gd_status gd_batch_enable_timing(gd_batch* B, int32_t enable) {
+    clear_error();
+    if (!B) return fail(GD_ERR_ARG, "gd_batch_enable_timing: null batch");
+    B->timing = enable != 0;
+    B->ring_head = B->ring_count = 0;
+    return GD_OK;
+}
+
+gd_status gd_batch_read_timing(gd_batch* B, float* ms_out, int32_t max_n, int32_t* n_out) {
+    clear_error();
+    if (!B || !n_out || (max_n > 0 && !ms_out)) return fail(GD_ERR_ARG, "gd_batch_read_timing: null argument");
+    int n = std::min(B->ring_count, std::max(max_n, 0));
+    int first = (B->ring_head - B->ring_count + gd_batch::kRing) % gd_batch::kRing;
+    first = (first + (B->ring_count - n)) % gd_batch::kRing;
+    for (int k = 0; k < n; k++) {
+        int slot = (first + k) % gd_batch::kRing;
+        hipError_t e = hipEventSynchronize(B->ev1[slot]);
+        if (e != hipSuccess) return hip_fail(e, "gd_batch_read_timing");
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, B->ev0[slot], B->ev1[slot]);
+        if (e != hipSuccess) return hip_fail(e, "gd_batch_read_timing");
+        ms_out[k] = ms;
+    }
+    *n_out = n;
+    B->ring_head = B->ring_count = 0;
     return GD_OK;
 }
 

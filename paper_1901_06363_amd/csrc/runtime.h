@@ -64,7 +64,12 @@ struct gd_batch {
     gd::Tiling tiling;
     int nmax = 1;
     double h = 0.5;
-    hipGraphExec_t graph_exec = nullptr;
+    hipGraphExec_t graph_dock = nullptr;   // queue reset + docking kernel
+    hipGraphExec_t graph_post = nullptr;   // top-k + pose replay
     gd::GraphKey graph_key{};
+    static constexpr int kRing = 256;
+    bool timing = false;
+    hipEvent_t ev0[kRing] = {}, ev1[kRing] = {};
+    int ring_head = 0, ring_count = 0;
     ~gd_batch();
 };
