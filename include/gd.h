@@ -287,12 +287,14 @@ gd_status gd_surrogate_bwd(const gd_pocket* pocket, const gd_ligands* topo, int3
  * the exact discrete score: accepted iff bump-free and S_refined < S_input.
  * px/py/pz are updated in place with the refined pose where accepted (the
  * input pose is kept otherwise).  Outputs (device): F_out[n_poses] surrogate
- * of the final iterate, S_out/clash_out of the returned pose, accepted_out.
+ * of the final iterate, S_out/clash_out of the returned pose, accepted_out,
+ * and optionally (rx_out, ry_out, rz_out, may be NULL) the final iterate of
+ * every pose in the layout of px/py/pz.
  */
 gd_status gd_refine(const gd_pocket* pocket, const gd_ligands* topo, int32_t n_poses, const int32_t* pose_lig,
                     float* px, float* py, float* pz, const gd_refine_opts* opts, float clash_dist,
                     int32_t clash_min_bonds, void* stream, float* F_out, int32_t* S_out, uint8_t* clash_out,
-                    uint8_t* accepted_out);
+                    uint8_t* accepted_out, float* rx_out, float* ry_out, float* rz_out);
 
 #ifdef __cplusplus
 }

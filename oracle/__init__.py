@@ -90,6 +90,21 @@ def _load():
         lib.orc_place.argtypes = [ctypes.c_int, P, P, P, P, P, P]
         lib.orc_apply_torsions.argtypes = [ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P, P, ctypes.c_int, P]
         lib.orc_apply_torsions.restype = ctypes.c_int
+        D = ctypes.c_double
+        lib.orc_blur_new.argtypes = [P, D, D, D]
+        lib.orc_blur_new.restype = P
+        lib.orc_blur_free.argtypes = [P]
+        lib.orc_rho_node.argtypes = [P, P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64]
+        lib.orc_rho_node.restype = D
+        lib.orc_rho_interp.argtypes = [P, P, P, P]
+        lib.orc_rho_interp.restype = D
+        lib.orc_surrogate.argtypes = [P, P, ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P, P, P, P, P, P]
+        lib.orc_surrogate.restype = ctypes.c_int
+        lib.orc_refine.argtypes = [P, P, ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P, P, ctypes.c_int, D, D, D, D, D,
+                                   P, P, P]
+        lib.orc_refine.restype = ctypes.c_int
+        lib.orc_torsion_tree.argtypes = [ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P, P, P, P, P]
+        lib.orc_torsion_tree.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -240,3 +255,76 @@ def apply_torsions(lig: dict, X, moves) -> np.ndarray:
     if rc != OK:
         raise OracleError(rc)
     return X
+
+
+class OracleBlur:
+    """Blurred pocket density rho on the lattice bh*(i,j,k) (nodes by definition)."""
+
+    def __init__(self, pocket: OraclePocket, sigma=0.6, cutoff_sigmas=4.0, bh=0.375):
+        lib = _load()
+        self.pocket = pocket
+        # sigma, cutoff and spacing travel as float32 through the GPU ABI
+        self.sigma = float(np.float32(sigma))
+        self.cutoff = float(np.float32(cutoff_sigmas)) * self.sigma
+        self.bh = float(np.float32(bh))
+        self._ptr = lib.orc_blur_new(pocket._ptr, self.sigma, self.cutoff, self.bh)
+
+    def __del__(self):
+        if getattr(self, "_ptr", None) and _lib is not None:
+            _lib.orc_blur_free(self._ptr)
+            self._ptr = None
+
+    def node(self, i, j, k) -> float:
+        return float(_load().orc_rho_node(self.pocket._ptr, self._ptr, int(i), int(j), int(k)))
+
+    def interp(self, x):
+        x = np.ascontiguousarray(x, np.float64)
+        g = np.zeros(3)
+        v = _load().orc_rho_interp(self.pocket._ptr, self._ptr, _p(x), _p(g))
+        return float(v), g
+
+    def surrogate(self, lig: dict, X0, prm, want_grad=True):
+        """(F, dF/dprm, pose) with prm = [t(3), q(4), tau(nr)] (tau in list order)."""
+        bonds = np.ascontiguousarray(lig["bonds"], np.int32).reshape(-1)
+        rot = np.ascontiguousarray(lig["rot"], np.int32).reshape(-1)
+        X0 = np.ascontiguousarray(X0, np.float64)
+        prm = np.ascontiguousarray(prm, np.float64)
+        F = ctypes.c_double(0)
+        grad = np.zeros(len(prm)) if want_grad else None
+        X = np.zeros_like(X0)
+        rc = _load().orc_surrogate(self.pocket._ptr, self._ptr, len(X0), len(bonds) // 2, _p(bonds), len(rot) // 2,
+                                   _p(rot), _p(X0), _p(prm), ctypes.byref(F), _p(grad), _p(X))
+        if rc != OK:
+            raise OracleError(rc)
+        return F.value, grad, X
+
+    def refine(self, lig: dict, X0, steps=50, lr_t=0.002, lr_q=1e-5, lr_tau=5e-4, max_dt=0.1, max_dtau=0.05):
+        bonds = np.ascontiguousarray(lig["bonds"], np.int32).reshape(-1)
+        rot = np.ascontiguousarray(lig["rot"], np.int32).reshape(-1)
+        X0 = np.ascontiguousarray(X0, np.float64)
+        nr = len(rot) // 2
+        prm = np.zeros(7 + nr)
+        X = np.zeros_like(X0)
+        F = ctypes.c_double(0)
+        f32 = lambda v: float(np.float32(v))
+        rc = _load().orc_refine(self.pocket._ptr, self._ptr, len(X0), len(bonds) // 2, _p(bonds), nr, _p(rot), _p(X0),
+                                int(steps), f32(lr_t), f32(lr_q), f32(lr_tau), f32(max_dt), f32(max_dtau), _p(prm),
+                                _p(X), ctypes.byref(F))
+        if rc != OK:
+            raise OracleError(rc)
+        return prm, X, F.value
+
+
+def torsion_tree(lig: dict):
+    """(root-first order, near atoms, far atoms, moving masks nr x l)."""
+    bonds = np.ascontiguousarray(lig["bonds"], np.int32).reshape(-1)
+    rot = np.ascontiguousarray(lig["rot"], np.int32).reshape(-1)
+    l, nr = len(lig["x"]), len(rot) // 2
+    order = np.zeros(max(nr, 1), np.int32)
+    near = np.zeros(max(nr, 1), np.int32)
+    far = np.zeros(max(nr, 1), np.int32)
+    mov = np.zeros((max(nr, 1), l), np.uint8)
+    rc = _load().orc_torsion_tree(l, len(bonds) // 2, _p(bonds), nr, _p(rot), _p(order), _p(near), _p(far), _p(mov))
+    if rc != OK:
+        raise OracleError(rc)
+    return order[:nr], near[:nr], far[:nr], mov[:nr].astype(bool)

@@ -581,3 +581,322 @@ int orc_apply_torsions(int l, int nb, const int* bonds, int nr, const int* rot, 
     topo_free(&T);
     return ORC_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Smoothed surrogate for pose refinement (a differentiable stand-in for the
+ * overlap score, used only to propose refined poses; every refined pose is
+ * judged again with the exact lattice score S and the bump rule).
+ *
+ *   rho(g)  = sum_j exp(-|g - P_j|^2 / (2 sigma^2)) over points with
+ *             |g - P_j| <= cutoff, at lattice nodes g = bh * (i, j, k)
+ *   rho~(x) = trilinear interpolation of rho in the lattice cell containing x
+ *   F       = sum_i rho~(X_i)
+ *   X(t, q, tau) = R(q/|q|) (FK_tau(X0) - c0) + c0 + t, c0 = mean of X0;
+ *   FK_tau rotates, root first (bond distance of the rotamer's atom nearer to
+ *   atom 0, ties in list order), the side of rotamer b that does not contain
+ *   atom 0 by tau_b (radians, right-handed about near -> far atom) about its
+ *   current axis.                                                            */
+
+typedef struct {
+    double sigma, cutoff, bh;
+    int64_t lo[3], dim[3];
+    double* memo; /* NaN = unknown */
+} orc_blur;
+
+
+orc_blur* orc_blur_new(const orc_pocket* P, double sigma, double cutoff, double bh) {
+    orc_blur* B = (orc_blur*)calloc(1, sizeof(orc_blur));
+    B->sigma = sigma; B->cutoff = cutoff; B->bh = bh;
+    double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
+    for (int i = 0; i < P->n_points; i++)
+        for (int a = 0; a < 3; a++) {
+            if (P->pts[3 * i + a] < mn[a]) mn[a] = P->pts[3 * i + a];
+            if (P->pts[3 * i + a] > mx[a]) mx[a] = P->pts[3 * i + a];
+        }
+    int64_t total = 1;
+    for (int a = 0; a < 3; a++) {
+        B->lo[a] = (int64_t)floor((mn[a] - cutoff) / bh) - 2;
+        B->dim[a] = (int64_t)ceil((mx[a] + cutoff) / bh) + 2 - B->lo[a] + 1;
+        total *= B->dim[a];
+    }
+    B->memo = (double*)malloc(sizeof(double) * total);
+    for (int64_t i = 0; i < total; i++) B->memo[i] = NAN;
+    return B;
+}
+
+void orc_blur_free(orc_blur* B) {
+    if (!B) return;
+    free(B->memo);
+    free(B);
+}
+
+/* rho at node (i,j,k) by its definition (sum over points in input order). */
+double orc_rho_node(const orc_pocket* P, orc_blur* B, int64_t i, int64_t j, int64_t k) {
+    int64_t ix = i - B->lo[0], iy = j - B->lo[1], iz = k - B->lo[2];
+    int inside = ix >= 0 && iy >= 0 && iz >= 0 && ix < B->dim[0] && iy < B->dim[1] && iz < B->dim[2];
+    if (!inside) return 0.0; /* farther than the cutoff from every point */
+    int64_t idx = (iz * B->dim[1] + iy) * B->dim[0] + ix;
+    if (!isnan(B->memo[idx])) return B->memo[idx];
+    double g[3] = {B->bh * (double)i, B->bh * (double)j, B->bh * (double)k};
+    double cut2 = B->cutoff * B->cutoff, inv2s2 = 1.0 / (2.0 * B->sigma * B->sigma);
+    double s = 0.0;
+    for (int p = 0; p < P->n_points; p++) {
+        double d2 = dist2(g, P->pts + 3 * p);
+        if (d2 <= cut2) s += exp(-d2 * inv2s2);
+    }
+    B->memo[idx] = s;
+    return s;
+}
+
+/* Trilinear interpolation of rho at x and its gradient. */
+double orc_rho_interp(const orc_pocket* P, orc_blur* B, const double* x, double* grad) {
+    double u[3], f[3];
+    int64_t c[3];
+    for (int a = 0; a < 3; a++) {
+        u[a] = x[a] / B->bh;
+        c[a] = (int64_t)floor(u[a]);
+        f[a] = u[a] - (double)c[a];
+    }
+    double v = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+    for (int dz = 0; dz < 2; dz++)
+        for (int dy = 0; dy < 2; dy++)
+            for (int dx = 0; dx < 2; dx++) {
+                double r = orc_rho_node(P, B, c[0] + dx, c[1] + dy, c[2] + dz);
+                double wx = dx ? f[0] : 1.0 - f[0], wy = dy ? f[1] : 1.0 - f[1], wz = dz ? f[2] : 1.0 - f[2];
+                double sx = dx ? 1.0 : -1.0, sy = dy ? 1.0 : -1.0, sz = dz ? 1.0 : -1.0;
+                v += wx * wy * wz * r;
+                gx += sx * wy * wz * r;
+                gy += wx * sy * wz * r;
+                gz += wx * wy * sz * r;
+            }
+    if (grad) { grad[0] = gx / B->bh; grad[1] = gy / B->bh; grad[2] = gz / B->bh; }
+    return v;
+}
+
+/* Torsion tree: rotamers in root-first order with near/far atoms and the
+ * moving side (the side without atom 0). */
+typedef struct {
+    int nr;
+    int* order;          /* root-first order of rotamer indices */
+    int* near_atom;      /* per rotamer */
+    int* far_atom;
+    unsigned char* mov;  /* nr x l */
+} orc_tree;
+
+static void tree_free(orc_tree* T) { free(T->order); free(T->near_atom); free(T->far_atom); free(T->mov); }
+
+static int tree_build(const orc_topo* T, orc_tree* R) {
+    int l = T->l, nr = T->nr;
+    R->nr = nr;
+    R->order = (int*)malloc(sizeof(int) * (nr > 0 ? nr : 1));
+    R->near_atom = (int*)malloc(sizeof(int) * (nr > 0 ? nr : 1));
+    R->far_atom = (int*)malloc(sizeof(int) * (nr > 0 ? nr : 1));
+    R->mov = (unsigned char*)calloc((size_t)(nr > 0 ? nr : 1) * l, 1);
+    const int* d0 = T->dist; /* distances from atom 0 */
+    for (int r = 0; r < nr; r++) {
+        int a = T->rot[2 * r], c = T->rot[2 * r + 1];
+        int root_left = T->left[(size_t)r * l + 0];
+        R->near_atom[r] = root_left ? a : c;
+        R->far_atom[r] = root_left ? c : a;
+        for (int i = 0; i < l; i++) {
+            int in_left = T->left[(size_t)r * l + i];
+            R->mov[(size_t)r * l + i] = root_left ? !in_left : in_left;
+        }
+        R->order[r] = r;
+    }
+    /* stable insertion sort by the near atom's bond distance from atom 0 */
+    for (int i = 1; i < nr; i++) {
+        int v = R->order[i], j = i - 1;
+        while (j >= 0 && d0[R->near_atom[R->order[j]]] > d0[R->near_atom[v]]) { R->order[j + 1] = R->order[j]; j--; }
+        R->order[j + 1] = v;
+    }
+    return ORC_OK;
+}
+
+/* Rotate the moving set of rotamer r by angle (radians) about its current axis. */
+static void fk_rotate(const orc_tree* R, int l, int r, double ang, double* X) {
+    int na = R->near_atom[r], fa = R->far_atom[r];
+    double k[3] = {X[3 * fa] - X[3 * na], X[3 * fa + 1] - X[3 * na + 1], X[3 * fa + 2] - X[3 * na + 2]};
+    double nrm = sqrt(k[0] * k[0] + k[1] * k[1] + k[2] * k[2]);
+    k[0] /= nrm; k[1] /= nrm; k[2] /= nrm;
+    double c = cos(ang), s = sin(ang), t = 1.0 - c;
+    double M[9];
+    M[0] = t * k[0] * k[0] + c;        M[1] = t * k[0] * k[1] - s * k[2]; M[2] = t * k[0] * k[2] + s * k[1];
+    M[3] = t * k[0] * k[1] + s * k[2]; M[4] = t * k[1] * k[1] + c;        M[5] = t * k[1] * k[2] - s * k[0];
+    M[6] = t * k[0] * k[2] - s * k[1]; M[7] = t * k[1] * k[2] + s * k[0]; M[8] = t * k[2] * k[2] + c;
+    double p[3] = {X[3 * na], X[3 * na + 1], X[3 * na + 2]};
+    for (int i = 0; i < l; i++)
+        if (R->mov[(size_t)r * l + i]) {
+            double y[3];
+            rotate_about(p, M, X + 3 * i, y);
+            X[3 * i] = y[0]; X[3 * i + 1] = y[1]; X[3 * i + 2] = y[2];
+        }
+}
+
+/* Pose from parameters; Y gets FK_tau(X0) (before the rigid motion). */
+static void pose_from_params(const orc_tree* R, int l, const double* X0, const double* c0, const double* prm,
+                             double* Y, double* X) {
+    memcpy(Y, X0, sizeof(double) * 3 * l);
+    for (int k = 0; k < R->nr; k++) {
+        int r = R->order[k];
+        fk_rotate(R, l, r, prm[7 + r], Y);
+    }
+    double Rq[9];
+    quat_matrix(prm + 3, Rq);
+    for (int i = 0; i < l; i++) {
+        double d0 = Y[3 * i] - c0[0], d1 = Y[3 * i + 1] - c0[1], d2 = Y[3 * i + 2] - c0[2];
+        X[3 * i] = (Rq[0] * d0 + Rq[1] * d1 + Rq[2] * d2) + c0[0] + prm[0];
+        X[3 * i + 1] = (Rq[3] * d0 + Rq[4] * d1 + Rq[5] * d2) + c0[1] + prm[1];
+        X[3 * i + 2] = (Rq[6] * d0 + Rq[7] * d1 + Rq[8] * d2) + c0[2] + prm[2];
+    }
+}
+
+/* d R(qhat) / d qhat_k for the unit-quaternion matrix of quat_matrix. */
+static void dquat(const double* q, double D[4][9]) {
+    double w = q[0], x = q[1], y = q[2], z = q[3];
+    double Dw[9] = {0, -2 * z, 2 * y, 2 * z, 0, -2 * x, -2 * y, 2 * x, 0};
+    double Dx[9] = {0, 2 * y, 2 * z, 2 * y, -4 * x, -2 * w, 2 * z, 2 * w, -4 * x};
+    double Dy[9] = {-4 * y, 2 * x, 2 * w, 2 * x, 0, 2 * z, -2 * w, 2 * z, -4 * y};
+    double Dz[9] = {-4 * z, -2 * w, 2 * x, 2 * w, -4 * z, 2 * y, 2 * x, 2 * y, 0};
+    memcpy(D[0], Dw, sizeof(Dw)); memcpy(D[1], Dx, sizeof(Dx)); memcpy(D[2], Dy, sizeof(Dy)); memcpy(D[3], Dz, sizeof(Dz));
+}
+
+/*
+ * Surrogate value and analytic gradient.  prm = [t(3), q(4), tau(nr)];
+ * grad (may be NULL) gets dF/dprm; X (may be NULL) the pose.
+ */
+static double surrogate_eval(const orc_pocket* P, orc_blur* B, const orc_tree* R, int l, const double* X0,
+                             const double* c0, const double* prm, double* grad, double* Xout) {
+    double* Y = (double*)malloc(sizeof(double) * 3 * l);
+    double* X = (double*)malloc(sizeof(double) * 3 * l);
+    double* g = (double*)malloc(sizeof(double) * 3 * l);
+    pose_from_params(R, l, X0, c0, prm, Y, X);
+    double F = 0.0;
+    for (int i = 0; i < l; i++) F += orc_rho_interp(P, B, X + 3 * i, g + 3 * i);
+    if (grad) {
+        int nr = R->nr;
+        for (int k = 0; k < 7 + nr; k++) grad[k] = 0.0;
+        for (int i = 0; i < l; i++)
+            for (int a = 0; a < 3; a++) grad[a] += g[3 * i + a];
+        /* quaternion: G = sum_i g_i (Y_i - c0)^T, dF/dqhat_k = <G, dR/dqhat_k> */
+        double G[9] = {0};
+        for (int i = 0; i < l; i++)
+            for (int r = 0; r < 3; r++)
+                for (int c = 0; c < 3; c++) G[3 * r + c] += g[3 * i + r] * (Y[3 * i + c] - c0[c]);
+        const double* q = prm + 3;
+        double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+        double qh[4] = {q[0] / qn, q[1] / qn, q[2] / qn, q[3] / qn};
+        double D[4][9], gqh[4];
+        dquat(qh, D);
+        for (int k = 0; k < 4; k++) {
+            gqh[k] = 0.0;
+            for (int e = 0; e < 9; e++) gqh[k] += G[e] * D[k][e];
+        }
+        double dot = qh[0] * gqh[0] + qh[1] * gqh[1] + qh[2] * gqh[2] + qh[3] * gqh[3];
+        for (int k = 0; k < 4; k++) grad[3 + k] = (gqh[k] - qh[k] * dot) / qn;
+        /* torsions: dF/dtau_b = K_b . sum_{i moving} (X_i - A_b) x g_i, final frame */
+        for (int r = 0; r < nr; r++) {
+            int na = R->near_atom[r], fa = R->far_atom[r];
+            double K[3] = {X[3 * fa] - X[3 * na], X[3 * fa + 1] - X[3 * na + 1], X[3 * fa + 2] - X[3 * na + 2]};
+            double nrm = sqrt(K[0] * K[0] + K[1] * K[1] + K[2] * K[2]);
+            K[0] /= nrm; K[1] /= nrm; K[2] /= nrm;
+            double tq[3] = {0, 0, 0};
+            for (int i = 0; i < l; i++) {
+                if (!R->mov[(size_t)r * l + i]) continue;
+                double d[3] = {X[3 * i] - X[3 * na], X[3 * i + 1] - X[3 * na + 1], X[3 * i + 2] - X[3 * na + 2]};
+                const double* gi = g + 3 * i;
+                tq[0] += d[1] * gi[2] - d[2] * gi[1];
+                tq[1] += d[2] * gi[0] - d[0] * gi[2];
+                tq[2] += d[0] * gi[1] - d[1] * gi[0];
+            }
+            grad[7 + r] = K[0] * tq[0] + K[1] * tq[1] + K[2] * tq[2];
+        }
+    }
+    if (Xout) memcpy(Xout, X, sizeof(double) * 3 * l);
+    free(Y); free(X); free(g);
+    return F;
+}
+
+static void centroid3(int l, const double* X, double* c) {
+    double s[3] = {0, 0, 0};
+    for (int i = 0; i < l; i++) { s[0] = s[0] + X[3 * i]; s[1] = s[1] + X[3 * i + 1]; s[2] = s[2] + X[3 * i + 2]; }
+    c[0] = s[0] / (double)l; c[1] = s[1] / (double)l; c[2] = s[2] / (double)l;
+}
+
+/* Public: surrogate value, gradient and pose at given parameters. */
+int orc_surrogate(orc_pocket* P, orc_blur* B, int l, int nb, const int* bonds, int nr, const int* rot,
+                  const double* X0, const double* prm, double* F, double* grad, double* X) {
+    orc_topo T;
+    int rc = topo_build(&T, l, nb, bonds, nr, rot);
+    if (rc != ORC_OK) { topo_free(&T); return rc; }
+    orc_tree R;
+    tree_build(&T, &R);
+    double c0[3];
+    centroid3(l, X0, c0);
+    *F = surrogate_eval(P, B, &R, l, X0, c0, prm, grad, X);
+    tree_free(&R);
+    topo_free(&T);
+    return ORC_OK;
+}
+
+/*
+ * Gradient ascent on F from t = 0, q = (1,0,0,0), tau = 0:
+ *   dt = lr_t grad_t scaled down to |dt| <= max_dt;  q <- (q + lr_q grad_q)/|.|;
+ *   tau_b += clamp(lr_tau grad_tau_b, -max_dtau, max_dtau).
+ * Outputs the final parameters, pose and F of the final iterate.
+ */
+int orc_refine(orc_pocket* P, orc_blur* B, int l, int nb, const int* bonds, int nr, const int* rot, const double* X0,
+               int steps, double lr_t, double lr_q, double lr_tau, double max_dt, double max_dtau, double* prm_out,
+               double* X_out, double* F_out) {
+    orc_topo T;
+    int rc = topo_build(&T, l, nb, bonds, nr, rot);
+    if (rc != ORC_OK) { topo_free(&T); return rc; }
+    orc_tree R;
+    tree_build(&T, &R);
+    double c0[3];
+    centroid3(l, X0, c0);
+    int np = 7 + nr;
+    double* prm = (double*)calloc(np, sizeof(double));
+    double* grad = (double*)calloc(np, sizeof(double));
+    prm[3] = 1.0;
+    for (int s = 0; s < steps; s++) {
+        surrogate_eval(P, B, &R, l, X0, c0, prm, grad, NULL);
+        double dt[3] = {lr_t * grad[0], lr_t * grad[1], lr_t * grad[2]};
+        double n = sqrt(dt[0] * dt[0] + dt[1] * dt[1] + dt[2] * dt[2]);
+        double sc = n > max_dt ? max_dt / n : 1.0;
+        for (int a = 0; a < 3; a++) prm[a] += dt[a] * sc;
+        double qn = 0.0;
+        for (int k = 0; k < 4; k++) { prm[3 + k] += lr_q * grad[3 + k]; qn += prm[3 + k] * prm[3 + k]; }
+        qn = sqrt(qn);
+        for (int k = 0; k < 4; k++) prm[3 + k] /= qn;
+        for (int r = 0; r < nr; r++) {
+            double d = lr_tau * grad[7 + r];
+            if (d > max_dtau) d = max_dtau;
+            if (d < -max_dtau) d = -max_dtau;
+            prm[7 + r] += d;
+        }
+    }
+    *F_out = surrogate_eval(P, B, &R, l, X0, c0, prm, NULL, X_out);
+    memcpy(prm_out, prm, sizeof(double) * np);
+    free(prm); free(grad);
+    tree_free(&R);
+    topo_free(&T);
+    return ORC_OK;
+}
+
+/* Root-first order and moving sides of the torsion tree (for tests). */
+int orc_torsion_tree(int l, int nb, const int* bonds, int nr, const int* rot, int* order, int* near_atom,
+                     int* far_atom, uint8_t* mov) {
+    orc_topo T;
+    int rc = topo_build(&T, l, nb, bonds, nr, rot);
+    if (rc != ORC_OK) { topo_free(&T); return rc; }
+    orc_tree R;
+    tree_build(&T, &R);
+    memcpy(order, R.order, sizeof(int) * nr);
+    memcpy(near_atom, R.near_atom, sizeof(int) * nr);
+    memcpy(far_atom, R.far_atom, sizeof(int) * nr);
+    memcpy(mov, R.mov, (size_t)nr * l);
+    tree_free(&R);
+    topo_free(&T);
+    return ORC_OK;
+}

@@ -56,9 +56,12 @@ class Pocket:
         self.grid_h = float(grid_h)
 
     def __del__(self):
-        if getattr(self, "_h", None) and _abi._lib is not None:
-            _abi._lib.gd_destroy_pocket(self._h)
-            self._h = None
+        try:
+            if getattr(self, "_h", None) and _abi._lib is not None:
+                _abi._lib.gd_destroy_pocket(self._h)
+                self._h = None
+        except Exception:  # interpreter shutdown
+            pass
 
     @property
     def handle(self):
@@ -166,9 +169,12 @@ class Batch:
         self.n_atoms_total, self.algo_flops, self.algo_bytes = inf.n_atoms_total, inf.algo_flops, inf.algo_bytes
 
     def __del__(self):
-        if getattr(self, "_h", None) and _abi._lib is not None:
-            _abi._lib.gd_destroy_batch(self._h)
-            self._h = None
+        try:
+            if getattr(self, "_h", None) and _abi._lib is not None:
+                _abi._lib.gd_destroy_batch(self._h)
+                self._h = None
+        except Exception:  # interpreter shutdown
+            pass
 
     def enable_timing(self, on=True):
         """Bracket the docking kernel of every later call with HIP events."""

@@ -42,17 +42,107 @@ def score_poses(pocket, ligands, pose_lig, px, py, pz, clash_dist=2.0, clash_min
     return S, clash
 
 
-def surrogate_fwd(*a, **k):
-    raise NotImplementedError("surrogate kernels are not in this build")
+def _prm(t, q, tau, n):
+    torch = _torch()
+    t = t.contiguous().float()
+    q = q.contiguous().float()
+    if tau is None or tau.numel() == 0:
+        tau = torch.zeros((n, 1), dtype=torch.float32, device="cuda")
+    tau = tau.contiguous().float()
+    return t, q, tau, tau.shape[1]
 
 
-def surrogate_bwd(*a, **k):
-    raise NotImplementedError("surrogate kernels are not in this build")
+def surrogate_fwd(pocket, ligands, pose_lig, px, py, pz, t, q, tau, stream=None):
+    """F(t, q, tau) per pose (device float32 (n,))."""
+    torch = _torch()
+    lg = _lig_desc(ligands)
+    pl = np.ascontiguousarray(pose_lig, dtype=np.int32)
+    n = len(pl)
+    t, q, tau, stride = _prm(t, q, tau, n)
+    F = torch.empty(n, dtype=torch.float32, device="cuda")
+    _abi.check(_abi.load().gd_surrogate_fwd(pocket.handle, ctypes.byref(lg.desc), n,
+                                            pl.ctypes.data_as(ctypes.c_void_p), _dp(px), _dp(py), _dp(pz), _dp(t),
+                                            _dp(q), _dp(tau), stride, _stream_ptr(stream), _dp(F)))
+    return F
 
 
-def refine(*a, **k):
-    raise NotImplementedError("refinement kernels are not in this build")
+def surrogate_bwd(pocket, ligands, pose_lig, px, py, pz, t, q, tau, dF, stream=None):
+    """dF/dt, dF/dq, dF/dtau scaled by the upstream gradient dF (per pose)."""
+    torch = _torch()
+    lg = _lig_desc(ligands)
+    pl = np.ascontiguousarray(pose_lig, dtype=np.int32)
+    n = len(pl)
+    t, q, tau, stride = _prm(t, q, tau, n)
+    dF = dF.contiguous().float()
+    dt = torch.empty((n, 3), dtype=torch.float32, device="cuda")
+    dq = torch.empty((n, 4), dtype=torch.float32, device="cuda")
+    dtau = torch.empty((n, stride), dtype=torch.float32, device="cuda")
+    _abi.check(_abi.load().gd_surrogate_bwd(pocket.handle, ctypes.byref(lg.desc), n,
+                                            pl.ctypes.data_as(ctypes.c_void_p), _dp(px), _dp(py), _dp(pz), _dp(t),
+                                            _dp(q), _dp(tau), stride, _dp(dF), _stream_ptr(stream), _dp(dt), _dp(dq),
+                                            _dp(dtau)))
+    return dt, dq, dtau
 
 
-class SurrogateScore:
-    pass
+def refine(pocket, ligands, pose_lig, px, py, pz, steps=50, lr_t=0.002, lr_q=1e-5, lr_tau=5e-4, max_dt=0.1,
+           max_dtau=0.05, clash_dist=2.0, clash_min_bonds=4, stream=None, want_iterate=False):
+    """Gradient ascent on the surrogate, then exact rescoring; px/py/pz are
+    overwritten with the refined pose where it is accepted."""
+    torch = _torch()
+    lg = _lig_desc(ligands)
+    pl = np.ascontiguousarray(pose_lig, dtype=np.int32)
+    n = len(pl)
+    opts = _abi.RefineOpts(int(steps), float(lr_t), float(lr_q), float(lr_tau), float(max_dt), float(max_dtau))
+    F = torch.empty(n, dtype=torch.float32, device="cuda")
+    S = torch.empty(n, dtype=torch.int32, device="cuda")
+    clash = torch.empty(n, dtype=torch.uint8, device="cuda")
+    acc = torch.empty(n, dtype=torch.uint8, device="cuda")
+    it = [torch.empty_like(px) for _ in range(3)] if want_iterate else [None, None, None]
+    _abi.check(_abi.load().gd_refine(pocket.handle, ctypes.byref(lg.desc), n, pl.ctypes.data_as(ctypes.c_void_p),
+                                     _dp(px), _dp(py), _dp(pz), ctypes.byref(opts), float(clash_dist),
+                                     int(clash_min_bonds), _stream_ptr(stream), _dp(F), _dp(S), _dp(clash), _dp(acc),
+                                     _dp(it[0]), _dp(it[1]), _dp(it[2])))
+    out = dict(F=F, S=S, clash=clash, accepted=acc)
+    if want_iterate:
+        out["iterate"] = it
+    return out
+
+
+def _make_autograd():
+    torch = _torch()
+
+    class SurrogateScore(torch.autograd.Function):
+        """F = SurrogateScore.apply(t, q, tau, ctx_obj): differentiable in t, q and tau.
+
+        ctx_obj = (pocket, ligands, pose_lig, px, py, pz) fixes the poses being
+        refined; the backward kernel recomputes the pose from the parameters.
+        """
+
+        @staticmethod
+        def forward(ctx, t, q, tau, spec):
+            pocket, ligands, pose_lig, px, py, pz = spec
+            ctx.spec = spec
+            ctx.save_for_backward(t, q, tau)
+            return surrogate_fwd(pocket, ligands, pose_lig, px, py, pz, t.detach(), q.detach(), tau.detach())
+
+        @staticmethod
+        def backward(ctx, dF):
+            t, q, tau = ctx.saved_tensors
+            pocket, ligands, pose_lig, px, py, pz = ctx.spec
+            dt, dq, dtau = surrogate_bwd(pocket, ligands, pose_lig, px, py, pz, t.detach(), q.detach(), tau.detach(),
+                                         dF)
+            return dt, dq, dtau[:, :tau.shape[1]], None
+
+    return SurrogateScore
+
+
+class _LazyAutograd:
+    _cls = None
+
+    def __getattr__(self, name):
+        if _LazyAutograd._cls is None:
+            _LazyAutograd._cls = _make_autograd()
+        return getattr(_LazyAutograd._cls, name)
+
+
+SurrogateScore = _LazyAutograd()

@@ -14,33 +14,9 @@
 
 namespace gd {
 
-// Stream-ordered device copies of small host arrays, released after the call.
-struct AsyncScratch {
-    hipStream_t s;
-    std::vector<void*> ptrs;
-    explicit AsyncScratch(hipStream_t st) : s(st) {}
-    ~AsyncScratch() {
-        for (void* p : ptrs) (void)hipFreeAsync(p, s);
-    }
-    template <class T>
-    hipError_t put(const std::vector<T>& v, const T** out) {
-        void* p = nullptr;
-        size_t n = std::max<size_t>(v.size() * sizeof(T), 16);
-        hipError_t e = hipMallocAsync(&p, n, s);
-        if (e != hipSuccess) return e;
-        ptrs.push_back(p);
-        if (!v.empty()) {
-            e = hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
-            if (e != hipSuccess) return e;
-        }
-        *out = (const T*)p;
-        return hipSuccess;
-    }
-};
-
 // Validates the pose list against the topology and fills the CSR offsets.
-gd_status pose_layout(const gd_ligands* topo, int32_t n_poses, const int32_t* pose_lig, const TopoHost& T,
-                      std::vector<int32_t>& lig, std::vector<int32_t>& off) {
+gd_status pose_layout(const gd_ligands* topo, int32_t n_poses, const int32_t* pose_lig,
+                      const std::vector<int32_t>& n_atoms, std::vector<int32_t>& lig, std::vector<int32_t>& off) {
     if (n_poses < 0) return fail(GD_ERR_ARG, "n_poses < 0");
     if (n_poses > 0 && !pose_lig) return fail(GD_ERR_ARG, "null pose_lig");
     lig.assign(pose_lig, pose_lig + n_poses);
@@ -49,7 +25,7 @@ gd_status pose_layout(const gd_ligands* topo, int32_t n_poses, const int32_t* po
     for (int p = 0; p < n_poses; p++) {
         if (lig[p] < 0 || lig[p] >= topo->n_ligands) return fail(GD_ERR_ARG, "pose %d: ligand index out of range", p);
         off[p] = (int32_t)o;
-        o += T.n_atoms[lig[p]];
+        o += n_atoms[lig[p]];
         if (o > (int64_t)INT32_MAX) return fail(GD_ERR_CAPACITY, "more than 2^31 pose atoms");
     }
     return GD_OK;
@@ -65,7 +41,7 @@ gd_status score_poses(const gd_pocket* P, const gd_ligands* topo, int32_t n_pose
     gd_status st;
     if ((st = prepare_topology(topo, min_bonds, T)) != GD_OK) return st;
     std::vector<int32_t> lig, off;
-    if ((st = pose_layout(topo, n_poses, pose_lig, T, lig, off)) != GD_OK) return st;
+    if ((st = pose_layout(topo, n_poses, pose_lig, T.n_atoms, lig, off)) != GD_OK) return st;
     if (n_poses == 0) return GD_OK;
     AsyncScratch A(s);
     ScoreDev D;

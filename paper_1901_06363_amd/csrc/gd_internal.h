@@ -97,6 +97,24 @@ struct ScoreDev {
     const float* pz;
 };
 
+// Torsion trees of a ligand set for the refinement (rotamers root first).
+struct TreeDev {
+    const int32_t* n_atoms;   // per ligand
+    const int32_t* nr;        // per ligand
+    const int32_t* tree_off;  // per ligand, first tree entry
+    const int4* tree;         // per entry: near atom, far atom, rotamer index, 0
+    const uint32_t* tmask;    // per entry: 128-bit moving-side mask (4 words)
+};
+
+// Poses and their parameters for the surrogate kernels.
+struct PoseDev {
+    const int32_t* pose_lig;
+    const int32_t* pose_off;
+    const float* px;
+    const float* py;
+    const float* pz;
+};
+
 struct Tiling {
     int waves_per_block = 4;
     int angle_block = 8;
@@ -122,6 +140,20 @@ hipError_t launch_reset(int* head, unsigned long long* counters, hipStream_t s);
 hipError_t launch_topk(const BatchDev& B, gd_pose_rec* out, uint16_t* ang_out, double h, hipStream_t s);
 hipError_t launch_score(const PocketDev& P, const ScoreDev& S, int n_poses, double cd2, int32_t* S_out,
                         uint8_t* clash_out, hipStream_t s);
+struct RefineParams {
+    int steps;
+    float lr_t, lr_q, lr_tau, max_dt, max_dtau;
+};
+hipError_t launch_surrogate(const PocketDev& P, const TreeDev& T, const PoseDev& X, int n_poses, const float* t,
+                            const float* q, const float* tau, int tau_stride, const float* dF, float* F_out,
+                            float* dt_out, float* dq_out, float* dtau_out, int lmax, hipStream_t s);
+hipError_t launch_refine(const PocketDev& P, const TreeDev& T, const PoseDev& X, int n_poses,
+                         const RefineParams& rp, float* rx, float* ry, float* rz, float* F_out, int lmax,
+                         hipStream_t s);
+hipError_t launch_accept(const PoseDev& X, int n_poses, const int32_t* n_atoms, const float* rx, const float* ry,
+                         const float* rz, const int32_t* S_in, const int32_t* S_ref, const uint8_t* c_ref,
+                         float* px, float* py, float* pz, int32_t* S_out, uint8_t* clash_out, uint8_t* accepted,
+                         const uint8_t* c_in, hipStream_t s);
 hipError_t launch_replay(const PocketDev& P, const BatchDev& B, const gd_pose_rec* recs, float* xyz, int nmax,
                          hipStream_t s);
 

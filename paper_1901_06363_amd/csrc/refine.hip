@@ -1,31 +1,379 @@
-// Differentiable refinement on the blurred pocket density (placeholder until
-// the surrogate kernels land).
+// Pose refinement on a smoothed pocket density, in FP32.
+//
+//   rho(g)  = sum_j exp(-|g - P_j|^2 / (2 sigma^2)) (cut off) on the lattice
+//             bh * (i, j, k), tabulated on the host
+//   rho~(x) = trilinear interpolation of rho in the cell containing x
+//   F       = sum_i rho~(X_i)
+//   X(t, q, tau) = R(q/|q|) (FK_tau(X0) - c0) + c0 + t
+// FK_tau rotates, root (atom 0) first, the side of every rotamer that does not
+// hold atom 0 by tau_b about its current axis (near -> far atom, right-handed).
+//
+// Backward pass (no stored activations: the pose is recomputed):
+//   dF/dt     = sum_i g_i,               g_i = grad rho~(X_i)
+//   dF/dq     = (I - qh qh^T)/|q| * <G, dR/dqh>,  G = sum_i g_i (Y_i - c0)^T
+//   dF/dtau_b = K_b . sum_{i moving} (X_i - A_b) x g_i
+//             = K_b . (sum x_i x g_i - A_b x sum g_i)   (final-frame axis K_b, A_b)
+// One wavefront per pose; each lane holds two atoms (ligands of <= 128 atoms).
 #include <hip/hip_runtime.h>
 
+#include "device_common.h"
 #include "gd_internal.h"
-#include "runtime.h"
 
-using namespace gd;
+namespace gd {
 
-extern "C" {
+constexpr int kSlots = kMaxAtoms / kWave;  // atoms per lane
 
-gd_status gd_surrogate_fwd(const gd_pocket*, const gd_ligands*, int32_t, const int32_t*, const float*, const float*,
-                           const float*, const float*, const float*, const float*, int32_t, void*, float*) {
-    clear_error();
-    return fail(GD_ERR_ARG, "gd_surrogate_fwd: not available in this build");
+__device__ __forceinline__ float wsum(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
 }
 
-gd_status gd_surrogate_bwd(const gd_pocket*, const gd_ligands*, int32_t, const int32_t*, const float*, const float*,
-                           const float*, const float*, const float*, const float*, int32_t, const float*, void*,
-                           float*, float*, float*) {
-    clear_error();
-    return fail(GD_ERR_ARG, "gd_surrogate_bwd: not available in this build");
+// Trilinear density and its gradient; corners outside the tabulated box are 0
+// (every node beyond the box lies farther than the cutoff from the points).
+__device__ __forceinline__ float rho_tri(const PocketDev& P, float x, float y, float z, float& gx, float& gy,
+                                         float& gz) {
+    float ux = x * P.inv_bh, uy = y * P.inv_bh, uz = z * P.inv_bh;
+    float fx0 = floorf(ux), fy0 = floorf(uy), fz0 = floorf(uz);
+    float fx = ux - fx0, fy = uy - fy0, fz = uz - fz0;
+    int ix = (int)fx0 - P.blo[0], iy = (int)fy0 - P.blo[1], iz = (int)fz0 - P.blo[2];
+    float r[8];
+#pragma unroll
+    for (int c = 0; c < 8; c++) {
+        int jx = ix + (c & 1), jy = iy + ((c >> 1) & 1), jz = iz + (c >> 2);
+        bool in = (unsigned)jx < (unsigned)P.bdim[0] && (unsigned)jy < (unsigned)P.bdim[1] &&
+                  (unsigned)jz < (unsigned)P.bdim[2];
+        r[c] = in ? P.rho[((size_t)jz * P.bdim[1] + jy) * P.bdim[0] + jx] : 0.f;
+    }
+    float ax = 1.f - fx, ay = 1.f - fy, az = 1.f - fz;
+    // interpolate along x, then y, then z
+    float r00 = ax * r[0] + fx * r[1], r10 = ax * r[2] + fx * r[3];
+    float r01 = ax * r[4] + fx * r[5], r11 = ax * r[6] + fx * r[7];
+    float d00 = r[1] - r[0], d10 = r[3] - r[2], d01 = r[5] - r[4], d11 = r[7] - r[6];
+    float r0 = ay * r00 + fy * r10, r1 = ay * r01 + fy * r11;
+    gx = (az * (ay * d00 + fy * d10) + fz * (ay * d01 + fy * d11)) * P.inv_bh;
+    gy = (az * (r10 - r00) + fz * (r11 - r01)) * P.inv_bh;
+    gz = (r1 - r0) * P.inv_bh;
+    return az * r0 + fz * r1;
 }
 
-gd_status gd_refine(const gd_pocket*, const gd_ligands*, int32_t, const int32_t*, float*, float*, float*,
-                    const gd_refine_opts*, float, int32_t, void*, float*, int32_t*, uint8_t*, uint8_t*) {
-    clear_error();
-    return fail(GD_ERR_ARG, "gd_refine: not available in this build");
+__device__ __forceinline__ void quat_mat(const float* q, float* R) {
+    float n = sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    float w = q[0] / n, x = q[1] / n, y = q[2] / n, z = q[3] / n;
+    R[0] = 1.f - 2.f * (y * y + z * z); R[1] = 2.f * (x * y - w * z);       R[2] = 2.f * (x * z + w * y);
+    R[3] = 2.f * (x * y + w * z);       R[4] = 1.f - 2.f * (x * x + z * z); R[5] = 2.f * (y * z - w * x);
+    R[6] = 2.f * (x * z - w * y);       R[7] = 2.f * (y * z + w * x);       R[8] = 1.f - 2.f * (x * x + y * y);
 }
 
-}  // extern "C"
+// Per-wave state of one pose.
+struct PoseState {
+    int l, nr, tree0;
+    float x0[kSlots][3];  // input pose (this lane's atoms)
+    float c0[3];          // centroid of the input pose
+};
+
+__device__ void load_pose(const TreeDev& T, const PoseDev& X, int pose, PoseState& S) {
+    const int lane = lane_id();
+    const int lig = X.pose_lig[pose], off = X.pose_off[pose];
+    S.l = T.n_atoms[lig];
+    S.nr = T.nr[lig];
+    S.tree0 = T.tree_off[lig];
+    float s[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < kSlots; k++) {
+        int i = lane + k * kWave;
+        bool in = i < S.l;
+        S.x0[k][0] = in ? X.px[off + i] : 0.f;
+        S.x0[k][1] = in ? X.py[off + i] : 0.f;
+        S.x0[k][2] = in ? X.pz[off + i] : 0.f;
+        s[0] += S.x0[k][0];
+        s[1] += S.x0[k][1];
+        s[2] += S.x0[k][2];
+    }
+    for (int a = 0; a < 3; a++) S.c0[a] = wsum(s[a]) / (float)S.l;
+}
+
+// Forward kinematics + rigid motion; Ys gets FK_tau(X0) for this lane's
+// atoms, Xf the final pose.  lds: 3 * 128 floats of this wave.
+__device__ void pose_forward(const TreeDev& T, const PoseState& S, const float* t, const float* q, const float* tau,
+                             float* lds, float Ys[kSlots][3], float Xf[kSlots][3]) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int k = 0; k < kSlots; k++)
+        for (int a = 0; a < 3; a++) Ys[k][a] = S.x0[k][a];
+    for (int e = 0; e < S.nr; e++) {
+        const int4 te = T.tree[S.tree0 + e];
+        const uint32_t* mk = T.tmask + 4 * (size_t)(S.tree0 + e);
+#pragma unroll
+        for (int k = 0; k < kSlots; k++) {
+            int i = lane + k * kWave;
+            if (i < S.l) {
+                lds[i] = Ys[k][0];
+                lds[kMaxAtoms + i] = Ys[k][1];
+                lds[2 * kMaxAtoms + i] = Ys[k][2];
+            }
+        }
+        wave_sync();
+        const float px = lds[te.x], py = lds[kMaxAtoms + te.x], pz = lds[2 * kMaxAtoms + te.x];
+        float kx = lds[te.y] - px, ky = lds[kMaxAtoms + te.y] - py, kz = lds[2 * kMaxAtoms + te.y] - pz;
+        wave_sync();
+        float inv = 1.f / sqrtf(kx * kx + ky * ky + kz * kz);
+        kx *= inv;
+        ky *= inv;
+        kz *= inv;
+        float s, c;
+        sincosf(tau[te.z], &s, &c);
+        float tt = 1.f - c;
+        float R[9] = {tt * kx * kx + c,      tt * kx * ky - s * kz, tt * kx * kz + s * ky,
+                      tt * kx * ky + s * kz, tt * ky * ky + c,      tt * ky * kz - s * kx,
+                      tt * kx * kz - s * ky, tt * ky * kz + s * kx, tt * kz * kz + c};
+#pragma unroll
+        for (int k = 0; k < kSlots; k++) {
+            int i = lane + k * kWave;
+            bool mv = i < S.l && ((mk[i >> 5] >> (i & 31)) & 1u);
+            if (mv) {
+                float d0 = Ys[k][0] - px, d1 = Ys[k][1] - py, d2 = Ys[k][2] - pz;
+                Ys[k][0] = px + (R[0] * d0 + R[1] * d1 + R[2] * d2);
+                Ys[k][1] = py + (R[3] * d0 + R[4] * d1 + R[5] * d2);
+                Ys[k][2] = pz + (R[6] * d0 + R[7] * d1 + R[8] * d2);
+            }
+        }
+    }
+    float Rq[9];
+    quat_mat(q, Rq);
+#pragma unroll
+    for (int k = 0; k < kSlots; k++) {
+        float d0 = Ys[k][0] - S.c0[0], d1 = Ys[k][1] - S.c0[1], d2 = Ys[k][2] - S.c0[2];
+        Xf[k][0] = (Rq[0] * d0 + Rq[1] * d1 + Rq[2] * d2) + S.c0[0] + t[0];
+        Xf[k][1] = (Rq[3] * d0 + Rq[4] * d1 + Rq[5] * d2) + S.c0[1] + t[1];
+        Xf[k][2] = (Rq[6] * d0 + Rq[7] * d1 + Rq[8] * d2) + S.c0[2] + t[2];
+    }
+}
+
+// F and (optionally) dF/d(t, q, tau) at the given parameters.  gtau is indexed
+// by rotamer (list order); only lane-uniform values are returned.
+template <bool GRAD>
+__device__ float surrogate_eval(const PocketDev& P, const TreeDev& T, const PoseState& S, const float* t,
+                                const float* q, const float* tau, float* lds, float* gt, float* gq, float* gtau,
+                                float Xout[kSlots][3]) {
+    const int lane = lane_id();
+    float Ys[kSlots][3], Xf[kSlots][3], g[kSlots][3];
+    pose_forward(T, S, t, q, tau, lds, Ys, Xf);
+    float F = 0.f;
+#pragma unroll
+    for (int k = 0; k < kSlots; k++) {
+        int i = lane + k * kWave;
+        if (i < S.l) {
+            F += rho_tri(P, Xf[k][0], Xf[k][1], Xf[k][2], g[k][0], g[k][1], g[k][2]);
+        } else {
+            g[k][0] = g[k][1] = g[k][2] = 0.f;
+        }
+        if (Xout)
+            for (int a = 0; a < 3; a++) Xout[k][a] = Xf[k][a];
+    }
+    F = wsum(F);
+    if (!GRAD) return F;
+    // translation
+    for (int a = 0; a < 3; a++) gt[a] = wsum(g[0][a] + g[1][a]);
+    // quaternion
+    float G[9];
+    for (int r = 0; r < 3; r++)
+        for (int c = 0; c < 3; c++) {
+            float v = 0.f;
+#pragma unroll
+            for (int k = 0; k < kSlots; k++) v += g[k][r] * (Ys[k][c] - S.c0[c]);
+            G[3 * r + c] = wsum(v);
+        }
+    {
+        float n = sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+        float w = q[0] / n, x = q[1] / n, y = q[2] / n, z = q[3] / n;
+        float Dw[9] = {0, -2 * z, 2 * y, 2 * z, 0, -2 * x, -2 * y, 2 * x, 0};
+        float Dx[9] = {0, 2 * y, 2 * z, 2 * y, -4 * x, -2 * w, 2 * z, 2 * w, -4 * x};
+        float Dy[9] = {-4 * y, 2 * x, 2 * w, 2 * x, 0, 2 * z, -2 * w, 2 * z, -4 * y};
+        float Dz[9] = {-4 * z, -2 * w, 2 * x, 2 * w, -4 * z, 2 * y, 2 * x, 2 * y, 0};
+        float gh[4] = {0, 0, 0, 0};
+        for (int e = 0; e < 9; e++) {
+            gh[0] += G[e] * Dw[e];
+            gh[1] += G[e] * Dx[e];
+            gh[2] += G[e] * Dy[e];
+            gh[3] += G[e] * Dz[e];
+        }
+        float qh[4] = {w, x, y, z};
+        float dot = qh[0] * gh[0] + qh[1] * gh[1] + qh[2] * gh[2] + qh[3] * gh[3];
+        for (int k = 0; k < 4; k++) gq[k] = (gh[k] - qh[k] * dot) / n;
+    }
+    // torsions, in the final frame
+    for (int k = 0; k < kSlots; k++) {
+        int i = lane + k * kWave;
+        if (i < S.l) {
+            lds[i] = Xf[k][0];
+            lds[kMaxAtoms + i] = Xf[k][1];
+            lds[2 * kMaxAtoms + i] = Xf[k][2];
+        }
+    }
+    wave_sync();
+    for (int e = 0; e < S.nr; e++) {
+        const int4 te = T.tree[S.tree0 + e];
+        const uint32_t* mk = T.tmask + 4 * (size_t)(S.tree0 + e);
+        float sxg[3] = {0, 0, 0}, sg[3] = {0, 0, 0};
+#pragma unroll
+        for (int k = 0; k < kSlots; k++) {
+            int i = lane + k * kWave;
+            bool mv = i < S.l && ((mk[i >> 5] >> (i & 31)) & 1u);
+            if (mv) {
+                sxg[0] += Xf[k][1] * g[k][2] - Xf[k][2] * g[k][1];
+                sxg[1] += Xf[k][2] * g[k][0] - Xf[k][0] * g[k][2];
+                sxg[2] += Xf[k][0] * g[k][1] - Xf[k][1] * g[k][0];
+                sg[0] += g[k][0];
+                sg[1] += g[k][1];
+                sg[2] += g[k][2];
+            }
+        }
+        for (int a = 0; a < 3; a++) {
+            sxg[a] = wsum(sxg[a]);
+            sg[a] = wsum(sg[a]);
+        }
+        float ax = lds[te.x], ay = lds[kMaxAtoms + te.x], az = lds[2 * kMaxAtoms + te.x];
+        float kx = lds[te.y] - ax, ky = lds[kMaxAtoms + te.y] - ay, kz = lds[2 * kMaxAtoms + te.y] - az;
+        float inv = 1.f / sqrtf(kx * kx + ky * ky + kz * kz);
+        // sum (x_i - A) x g_i = sum x_i x g_i - A x sum g_i
+        float tx = sxg[0] - (ay * sg[2] - az * sg[1]);
+        float ty = sxg[1] - (az * sg[0] - ax * sg[2]);
+        float tz = sxg[2] - (ax * sg[1] - ay * sg[0]);
+        gtau[te.z] = (kx * tx + ky * ty + kz * tz) * inv;
+    }
+    wave_sync();
+    return F;
+}
+
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256) surrogate_kernel(PocketDev P, TreeDev T, PoseDev X, int n_poses,
+                                                        const float* t, const float* q, const float* tau,
+                                                        int tau_stride, const float* dF, float* F_out, float* dt_out,
+                                                        float* dq_out, float* dtau_out) {
+    __shared__ float lds_all[4][3 * kMaxAtoms];
+    const int wave = threadIdx.x / kWave;
+    const int pose = blockIdx.x * 4 + wave;
+    if (pose >= n_poses) return;
+    float* lds = lds_all[wave];
+    PoseState S;
+    load_pose(T, X, pose, S);
+    const float* tp = t + 3 * (size_t)pose;
+    const float* qp = q + 4 * (size_t)pose;
+    const float* taup = tau + (size_t)tau_stride * pose;
+    if (!dF) {
+        float F = surrogate_eval<false>(P, T, S, tp, qp, taup, lds, nullptr, nullptr, nullptr, nullptr);
+        if (lane_id() == 0) F_out[pose] = F;
+        return;
+    }
+    float gt[3], gq[4], gtau[kMaxRot];
+    for (int r = 0; r < kMaxRot; r++) gtau[r] = 0.f;
+    float F = surrogate_eval<true>(P, T, S, tp, qp, taup, lds, gt, gq, gtau, nullptr);
+    const float up = dF[pose];
+    if (lane_id() == 0) {
+        if (F_out) F_out[pose] = F;
+        for (int a = 0; a < 3; a++) dt_out[3 * (size_t)pose + a] = up * gt[a];
+        for (int a = 0; a < 4; a++) dq_out[4 * (size_t)pose + a] = up * gq[a];
+        for (int r = 0; r < tau_stride; r++) dtau_out[(size_t)tau_stride * pose + r] = r < S.nr ? up * gtau[r] : 0.f;
+    }
+}
+
+// The whole ascent of one pose in one wavefront: parameters stay in
+// registers; the final pose is written to (rx, ry, rz).
+__global__ void __launch_bounds__(256) refine_kernel(PocketDev P, TreeDev T, PoseDev X, int n_poses, RefineParams rp,
+                                                     float* rx, float* ry, float* rz, float* F_out) {
+    __shared__ float lds_all[4][3 * kMaxAtoms];
+    const int wave = threadIdx.x / kWave;
+    const int pose = blockIdx.x * 4 + wave;
+    if (pose >= n_poses) return;
+    float* lds = lds_all[wave];
+    PoseState S;
+    load_pose(T, X, pose, S);
+    float t[3] = {0.f, 0.f, 0.f}, q[4] = {1.f, 0.f, 0.f, 0.f}, tau[kMaxRot];
+    float gt[3], gq[4], gtau[kMaxRot];
+    for (int r = 0; r < kMaxRot; r++) tau[r] = gtau[r] = 0.f;
+    for (int s = 0; s < rp.steps; s++) {
+        surrogate_eval<true>(P, T, S, t, q, tau, lds, gt, gq, gtau, nullptr);
+        float dt[3] = {rp.lr_t * gt[0], rp.lr_t * gt[1], rp.lr_t * gt[2]};
+        float n = sqrtf(dt[0] * dt[0] + dt[1] * dt[1] + dt[2] * dt[2]);
+        float sc = n > rp.max_dt ? rp.max_dt / n : 1.f;
+        for (int a = 0; a < 3; a++) t[a] += dt[a] * sc;
+        float qn = 0.f;
+        for (int a = 0; a < 4; a++) {
+            q[a] += rp.lr_q * gq[a];
+            qn += q[a] * q[a];
+        }
+        qn = sqrtf(qn);
+        for (int a = 0; a < 4; a++) q[a] /= qn;
+        for (int r = 0; r < S.nr; r++) tau[r] += fminf(fmaxf(rp.lr_tau * gtau[r], -rp.max_dtau), rp.max_dtau);
+    }
+    float Xf[kSlots][3];
+    float F = surrogate_eval<false>(P, T, S, t, q, tau, lds, nullptr, nullptr, nullptr, Xf);
+    const int off = X.pose_off[pose];
+    for (int k = 0; k < kSlots; k++) {
+        int i = lane_id() + k * kWave;
+        if (i < S.l) {
+            rx[off + i] = Xf[k][0];
+            ry[off + i] = Xf[k][1];
+            rz[off + i] = Xf[k][2];
+        }
+    }
+    if (lane_id() == 0) F_out[pose] = F;
+}
+
+// Keep the refined pose iff it is bump-free and strictly improves S.
+__global__ void __launch_bounds__(256) accept_kernel(PoseDev X, int n_poses, const int32_t* n_atoms, const float* rx,
+                                                     const float* ry, const float* rz, const int32_t* S_in,
+                                                     const int32_t* S_ref, const uint8_t* c_ref, float* px, float* py,
+                                                     float* pz, int32_t* S_out, uint8_t* clash_out, uint8_t* accepted,
+                                                     const uint8_t* c_in) {
+    const int wave = threadIdx.x / kWave;
+    const int pose = blockIdx.x * 4 + wave;
+    if (pose >= n_poses) return;
+    const bool acc = !c_ref[pose] && S_ref[pose] < S_in[pose];
+    const int off = X.pose_off[pose], l = n_atoms[X.pose_lig[pose]];
+    if (acc)
+        for (int i = lane_id(); i < l; i += kWave) {
+            px[off + i] = rx[off + i];
+            py[off + i] = ry[off + i];
+            pz[off + i] = rz[off + i];
+        }
+    if (lane_id() == 0) {
+        accepted[pose] = acc;
+        S_out[pose] = acc ? S_ref[pose] : S_in[pose];
+        clash_out[pose] = acc ? c_ref[pose] : c_in[pose];
+    }
+}
+
+hipError_t launch_surrogate(const PocketDev& P, const TreeDev& T, const PoseDev& X, int n_poses, const float* t,
+                            const float* q, const float* tau, int tau_stride, const float* dF, float* F_out,
+                            float* dt_out, float* dq_out, float* dtau_out, int lmax, hipStream_t s) {
+    (void)lmax;
+    if (n_poses <= 0) return hipSuccess;
+    hipLaunchKernelGGL(surrogate_kernel, dim3((n_poses + 3) / 4), dim3(256), 0, s, P, T, X, n_poses, t, q, tau,
+                       tau_stride, dF, F_out, dt_out, dq_out, dtau_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_refine(const PocketDev& P, const TreeDev& T, const PoseDev& X, int n_poses,
+                         const RefineParams& rp, float* rx, float* ry, float* rz, float* F_out, int lmax,
+                         hipStream_t s) {
+    (void)lmax;
+    if (n_poses <= 0) return hipSuccess;
+    hipLaunchKernelGGL(refine_kernel, dim3((n_poses + 3) / 4), dim3(256), 0, s, P, T, X, n_poses, rp, rx, ry, rz,
+                       F_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_accept(const PoseDev& X, int n_poses, const int32_t* n_atoms, const float* rx, const float* ry,
+                         const float* rz, const int32_t* S_in, const int32_t* S_ref, const uint8_t* c_ref,
+                         float* px, float* py, float* pz, int32_t* S_out, uint8_t* clash_out, uint8_t* accepted,
+                         const uint8_t* c_in, hipStream_t s) {
+    if (n_poses <= 0) return hipSuccess;
+    hipLaunchKernelGGL(accept_kernel, dim3((n_poses + 3) / 4), dim3(256), 0, s, X, n_poses, n_atoms, rx, ry, rz,
+                       S_in, S_ref, c_ref, px, py, pz, S_out, clash_out, accepted, c_in);
+    return hipGetLastError();
+}
+
+}  // namespace gd

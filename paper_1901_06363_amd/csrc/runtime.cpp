@@ -562,6 +562,48 @@ gd_status prepare_topology(const gd_ligands* L, int min_bonds, TopoHost& T) {
     return GD_OK;
 }
 
+gd_status prepare_tree(const gd_ligands* L, TreeHost& out) {
+    gd_status st;
+    if ((st = validate_ligands_struct(L)) != GD_OK) return st;
+    const int n = L->n_ligands;
+    out.n_atoms.resize(n);
+    out.nr.resize(n);
+    out.tree_off.resize(n);
+    out.tree.clear();
+    out.mask.clear();
+    for (int i = 0; i < n; i++) {
+        Topo T;
+        if ((st = build_topo(L, i, T)) != GD_OK) return st;
+        const int l = T.l, nr = T.nr, r0 = L->rot_off[i];
+        out.n_atoms[i] = l;
+        out.nr[i] = nr;
+        out.tree_off[i] = (int32_t)(out.tree.size() / 4);
+        std::vector<int> order(nr), near(nr), far(nr);
+        for (int r = 0; r < nr; r++) {
+            int a = L->rot[2 * (r0 + r)], c = L->rot[2 * (r0 + r) + 1];
+            bool root_left = T.left[(size_t)r * l + 0] != 0;
+            near[r] = root_left ? a : c;
+            far[r] = root_left ? c : a;
+            order[r] = r;
+        }
+        // root first: by the bond distance of the near atom from atom 0
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int x, int y) { return T.dist[near[x]] < T.dist[near[y]]; });
+        for (int e = 0; e < nr; e++) {
+            int r = order[e];
+            out.tree.insert(out.tree.end(), {near[r], far[r], r, 0});
+            bool root_left = T.left[(size_t)r * l + 0] != 0;
+            uint32_t w[4] = {0, 0, 0, 0};
+            for (int a = 0; a < l; a++) {
+                bool in_left = T.left[(size_t)r * l + a] != 0;
+                if (root_left != in_left) w[a >> 5] |= 1u << (a & 31);
+            }
+            out.mask.insert(out.mask.end(), w, w + 4);
+        }
+    }
+    return GD_OK;
+}
+
 static void quat_matrix(const double* q, double* R) {
     double n = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
     double w = q[0] / n, x = q[1] / n, y = q[2] / n, z = q[3] / n;

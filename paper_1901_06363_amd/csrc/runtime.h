@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "gd_internal.h"
@@ -46,7 +47,47 @@ struct TopoHost {
     std::vector<uint16_t> efar;
 };
 gd_status prepare_topology(const gd_ligands* L, int min_bonds, TopoHost& T);
+
+// Host torsion trees for the refinement: per ligand the rotamers root first.
+struct TreeHost {
+    std::vector<int32_t> n_atoms, nr, tree_off;
+    std::vector<int32_t> tree;   // 4 per entry: near, far, rotamer index, 0
+    std::vector<uint32_t> mask;  // 4 words per entry
+};
+gd_status prepare_tree(const gd_ligands* L, TreeHost& out);
 gd_status validate_ligands_struct(const gd_ligands* L);
+
+// Stream-ordered device copies of small host arrays, released after the call.
+struct AsyncScratch {
+    hipStream_t s;
+    std::vector<void*> ptrs;
+    explicit AsyncScratch(hipStream_t st) : s(st) {}
+    ~AsyncScratch() {
+        for (void* p : ptrs) (void)hipFreeAsync(p, s);
+    }
+    template <class T>
+    hipError_t put(const std::vector<T>& v, const T** out) {
+        void* p = nullptr;
+        size_t n = std::max<size_t>(v.size() * sizeof(T), 16);
+        hipError_t e = hipMallocAsync(&p, n, s);
+        if (e != hipSuccess) return e;
+        ptrs.push_back(p);
+        if (!v.empty()) {
+            e = hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
+            if (e != hipSuccess) return e;
+        }
+        *out = (const T*)p;
+        return hipSuccess;
+    }
+    hipError_t scratch(size_t bytes, void** out) {
+        hipError_t e = hipMallocAsync(out, std::max<size_t>(bytes, 16), s);
+        if (e == hipSuccess) ptrs.push_back(*out);
+        return e;
+    }
+};
+
+gd_status pose_layout(const gd_ligands* topo, int32_t n_poses, const int32_t* pose_lig,
+                      const std::vector<int32_t>& n_atoms, std::vector<int32_t>& lig, std::vector<int32_t>& off);
 
 }  // namespace gd
 

@@ -87,7 +87,8 @@ GRID = Workload("grid", lig_seed=2, n_ligands=100_000, lmin=20, lmax=80, bmin=2,
 
 REFINE = Workload("refine", lig_seed=4, n_ligands=4096, lmin=20, lmax=80, bmin=2, bmax=12, ring_frac=0.0,
                   pockets=[(1000, 1000, (8.0, 6.0, 5.0))], n_orient=256, hp=10, top_k=64,
-                  extra=dict(blur_sigma=0.6, blur_h=0.375, steps=50))
+                  extra=dict(blur_sigma=0.6, blur_h=0.375, steps=50, lr_t=0.002, lr_q=1e-5, lr_tau=5e-4, max_dt=0.1,
+                             max_dtau=0.05))
 
 LARGE = Workload("large", lig_seed=5, n_ligands=1_000_000, lmin=15, lmax=120, bmin=0, bmax=16, ring_frac=0.05,
                  pockets=[(1010, 10_000, (16.0, 12.0, 9.0))], n_orient=1024, hp=10, top_k=8, chunk=65_536)

@@ -1,0 +1,177 @@
+"""Pins of the oracle's smoothed surrogate and its analytic gradient.
+
+Closed forms (a one-point pocket), trilinear identities, central finite
+differences in FP64 (h = 1e-4, relative error 1e-3 per parameter group;
+stencils in which an atom crosses a lattice face, where the trilinear
+gradient jumps, are retried with h = 1e-7 and otherwise excluded and
+counted), and an independent leaf-first forward-kinematics implementation.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth import configs
+from tests import refimpl
+
+SIG, CUTS, BH = 0.6, 4.0, 0.375
+
+
+def _blur(pts):
+    P = oracle.OraclePocket(pts, 0.5)
+    return P, oracle.OracleBlur(P, SIG, CUTS, BH)
+
+
+def test_one_point_density_closed_form():
+    pts = np.array([[0.31, -0.52, 0.77]], np.float32)
+    _, B = _blur(pts)
+    p = pts[0].astype(np.float64)
+    sig = float(np.float32(SIG))
+    cut = float(np.float32(CUTS)) * sig
+    bh = float(np.float32(BH))
+    for i in range(-8, 9):
+        for j in (-3, 0, 2):
+            for k in (-1, 1, 4):
+                g = bh * np.array([i, j, k], np.float64)
+                d2 = ((g - p) ** 2).sum()
+                want = np.exp(-d2 / (2 * sig * sig)) if d2 <= cut * cut else 0.0
+                assert B.node(i, j, k) == pytest.approx(want, rel=1e-14, abs=1e-300)
+
+
+def test_trilinear_identities():
+    pts = configs.SINGLE.pocket_points()
+    _, B = _blur(pts)
+    bh = float(np.float32(BH))
+    rng = np.random.default_rng(0)
+    c = np.floor(pts.mean(0) / bh).astype(int)
+    for _ in range(50):
+        n = c + rng.integers(-6, 7, 3)
+        v, _ = B.interp(bh * n.astype(np.float64))
+        assert v == pytest.approx(B.node(*n), rel=1e-12, abs=1e-15)
+        # linear along an edge of the cell
+        s = rng.random()
+        x = bh * (n + np.array([s, 0.0, 0.0]))
+        v, g = B.interp(x)
+        want = (1 - s) * B.node(*n) + s * B.node(n[0] + 1, n[1], n[2])
+        assert v == pytest.approx(want, rel=1e-10, abs=1e-12)
+        assert g[0] == pytest.approx((B.node(n[0] + 1, n[1], n[2]) - B.node(*n)) / bh, rel=1e-10, abs=1e-10)
+
+
+def _pose(lig, shift):
+    X = np.stack([lig["x"], lig["y"], lig["z"]], 1).astype(np.float64)
+    return X - X.mean(0) + shift
+
+
+def _cells(X):
+    return np.floor(X / float(np.float32(BH)))
+
+
+def _fd_grad(B, lig, X0, prm, h):
+    g = np.zeros(len(prm))
+    crossed = np.zeros(len(prm), bool)
+    _, _, Xc = B.surrogate(lig, X0, prm, want_grad=False)
+    for k in range(len(prm)):
+        for hh in (h, 1e-7):
+            e = np.zeros(len(prm))
+            e[k] = hh
+            Fp, _, Xp = B.surrogate(lig, X0, prm + e, want_grad=False)
+            Fm, _, Xm = B.surrogate(lig, X0, prm - e, want_grad=False)
+            ok = np.array_equal(_cells(Xp), _cells(Xc)) and np.array_equal(_cells(Xm), _cells(Xc))
+            if ok:
+                g[k] = (Fp - Fm) / (2 * hh)
+                break
+        else:
+            crossed[k] = True
+    return g, crossed
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_gradient_matches_central_differences(seed):
+    pts = configs.SINGLE.pocket_points()
+    P, B = _blur(pts)
+    lig = synth.ligands(4, seed, 1, 20, 40, 2, 8).ligand(0)
+    rng = np.random.default_rng(seed)
+    X0 = _pose(lig, pts.mean(0).astype(np.float64) + rng.normal(0, 1.0, 3))
+    nr = len(lig["rot"])
+    q = rng.normal(size=4)
+    q /= np.linalg.norm(q)
+    prm = np.concatenate([rng.normal(0, 0.3, 3), q, rng.normal(0, 0.4, nr)])
+    F, g, _ = B.surrogate(lig, X0, prm)
+    fd, crossed = _fd_grad(B, lig, X0, prm, 1e-4)
+    assert crossed.sum() <= 2, crossed
+    for sl in (slice(0, 3), slice(3, 7), slice(7, 7 + nr)):
+        keep = ~crossed[sl]
+        a, b = g[sl][keep], fd[sl][keep]
+        if len(a):
+            assert np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-6) <= 1e-3, (sl, a, b)
+
+
+def test_quaternion_gradient_is_tangent():
+    pts = configs.SINGLE.pocket_points()
+    P, B = _blur(pts)
+    lig = synth.ligands(4, 11, 1, 20, 40, 2, 8).ligand(0)
+    X0 = _pose(lig, pts.mean(0).astype(np.float64))
+    rng = np.random.default_rng(1)
+    for _ in range(10):
+        q = rng.normal(size=4)
+        q /= np.linalg.norm(q)
+        prm = np.concatenate([rng.normal(0, 0.3, 3), q, rng.normal(0, 0.4, len(lig["rot"]))])
+        _, g, _ = B.surrogate(lig, X0, prm)
+        assert abs(np.dot(g[3:7], q)) <= 1e-10 * max(1.0, np.linalg.norm(g[3:7]))
+
+
+def test_forward_kinematics_independent():
+    """FK applied root first about current axes equals leaf-first rotations
+    about the original axes (scipy rotation vectors), then the rigid motion."""
+    pts = configs.SINGLE.pocket_points()
+    _, B = _blur(pts)
+    rng = np.random.default_rng(2)
+    for i in range(6):
+        lig = synth.ligands(4, 20 + i, 1, 20, 60, 3, 10).ligand(0)
+        l = len(lig["x"])
+        X0 = _pose(lig, pts.mean(0).astype(np.float64))
+        nr = len(lig["rot"])
+        order, near, far, mov = oracle.torsion_tree(lig)
+        dist = refimpl.bond_distances(l, lig["bonds"])
+        depth = dist[0][near]
+        assert np.all(np.diff(depth[order]) >= 0)  # root first
+        for r in range(nr):
+            a, c = lig["rot"][r]
+            m = refimpl.left_mask(l, lig["bonds"], a, c)
+            assert np.array_equal(mov[r], ~m if m[0] else m)  # the side without atom 0 moves
+        tau = rng.normal(0, 0.8, nr)
+        q = rng.normal(size=4)
+        q /= np.linalg.norm(q)
+        t = rng.normal(0, 0.5, 3)
+        _, _, X = B.surrogate(lig, X0, np.concatenate([t, q, tau]), want_grad=False)
+        Y = X0.copy()
+        for r in order[::-1]:  # leaf first, original axes
+            k = X0[far[r]] - X0[near[r]]
+            k /= np.linalg.norm(k)
+            R = refimpl.Rotation.from_rotvec(tau[r] * k)
+            Y[mov[r]] = X0[near[r]] + R.apply(Y[mov[r]] - X0[near[r]])
+        c0 = X0.mean(0)
+        Rq = refimpl.Rotation.from_quat([q[1], q[2], q[3], q[0]])
+        Y = Rq.apply(Y - c0) + c0 + t
+        assert np.allclose(X, Y, atol=1e-10)
+        # identity parameters give back the input pose
+        _, _, Xi = B.surrogate(lig, X0, np.concatenate([[0, 0, 0, 1, 0, 0, 0], np.zeros(nr)]), want_grad=False)
+        assert np.allclose(Xi, X0, atol=1e-12)
+
+
+def test_ascent_increases_the_surrogate():
+    pts = configs.SINGLE.pocket_points()
+    P, B = _blur(pts)
+    rng = np.random.default_rng(3)
+    ups = 0
+    for i in range(8):
+        lig = synth.ligands(4, 40 + i, 1, 20, 40, 2, 8).ligand(0)
+        X0 = _pose(lig, pts.mean(0).astype(np.float64) + rng.normal(0, 1.5, 3))
+        F0, _, _ = B.surrogate(lig, X0, np.concatenate([[0, 0, 0, 1, 0, 0, 0], np.zeros(len(lig["rot"]))]))
+        prm, X, F = B.refine(lig, X0, steps=50)
+        ups += F > F0
+        # the refined pose is rigid-body + torsion motion of the input: bonds keep their length
+        b = lig["bonds"]
+        assert np.allclose(np.linalg.norm(X[b[:, 0]] - X[b[:, 1]], axis=1),
+                           np.linalg.norm(X0[b[:, 0]] - X0[b[:, 1]], axis=1), atol=1e-9)
+    assert ups >= 7
