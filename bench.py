@@ -86,7 +86,7 @@ def main():
     log("inputs generated in %.1f s" % (time.perf_counter() - t))
 
     stream = torch.cuda.current_stream()
-    P = gd.Pocket(pts, 0.5, 12.0)
+    P = gd.Pocket(pts, 0.5, w.pad)
     t = time.perf_counter()
     B = gd.Batch(P, ligs, q, hp=w.hp, top_k=w.top_k)
     prep_s = time.perf_counter() - t
@@ -175,6 +175,7 @@ def main():
             "hp_step_deg": w.hp,
             "poses_per_step": B.poses_expected,
             "tiling": list(tiling),
+            "grid_pad_A": w.pad,
         },
         "ligands_per_s": n_lig * args.steps / dt,
         "atoms_per_s": B.n_atoms_total * args.steps / dt,

@@ -122,6 +122,9 @@ gd_status autotune(const gd_pocket* P, gd_batch* B, hipStream_t s, int reps, con
         BatchDev D = B->dev;
         D.items = (const int32_t*)sb.ptr;
         D.n_items = (int32_t)(sample.size() / 2);
+        DevBuf dcopy;
+        if ((e = dcopy.upload(&D, sizeof(BatchDev), s)) != hipSuccess) return hip_fail(e, "gd_batch_autotune");
+        DockLaunch L{(const PocketDev*)P->devcopy.ptr, (const BatchDev*)dcopy.ptr, D.counters, D.lmax, B->nmax};
         hipEvent_t e0, e1;
         (void)hipEventCreate(&e0);
         (void)hipEventCreate(&e1);
@@ -140,7 +143,7 @@ gd_status autotune(const gd_pocket* P, gd_batch* B, hipStream_t s, int reps, con
                     for (int r = 0; r <= reps && ok; r++) {  // first run warms up
                         ok &= launch_reset(D.head, D.counters, s) == hipSuccess;
                         (void)hipEventRecord(e0, s);
-                        ok &= launch_dock(P->dev, D, B->nmax, t, true, 0, grid, s) == hipSuccess;
+                        ok &= launch_dock(L, t, true, 0, grid, s) == hipSuccess;
                         (void)hipEventRecord(e1, s);
                         ok &= hipEventSynchronize(e1) == hipSuccess;
                         float ms = 0.f;

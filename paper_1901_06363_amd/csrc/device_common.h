@@ -18,10 +18,31 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ int wave_sum(int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+// Cross-lane reductions with DPP row shifts (inclusive prefix within each row
+// of 16 lanes) and readlane of the four row results: no LDS round trips.
+// DPP controls: row_shr:n = 0x110 + n; row_mask/bank_mask 0xf; invalid source
+// lanes read the identity passed as `old`.
+template <class Op>
+__device__ __forceinline__ int dpp_row_scan(int v, int ident, Op op) {
+    v = op(v, __builtin_amdgcn_update_dpp(ident, v, 0x111, 0xf, 0xf, false));
+    v = op(v, __builtin_amdgcn_update_dpp(ident, v, 0x112, 0xf, 0xf, false));
+    v = op(v, __builtin_amdgcn_update_dpp(ident, v, 0x114, 0xf, 0xf, false));
+    v = op(v, __builtin_amdgcn_update_dpp(ident, v, 0x118, 0xf, 0xf, false));
     return v;
+}
+
+__device__ __forceinline__ int wave_sum(int v) {
+    v = dpp_row_scan(v, 0, [](int a, int b) { return a + b; });
+    return __builtin_amdgcn_readlane(v, 15) + __builtin_amdgcn_readlane(v, 31) + __builtin_amdgcn_readlane(v, 47) +
+           __builtin_amdgcn_readlane(v, 63);
+}
+
+__device__ __forceinline__ float wave_maxf(float v) {
+    // non-negative inputs: the integer order of the bit patterns is the float order
+    int b = dpp_row_scan(__float_as_int(v), 0, [](int a, int c) { return a > c ? a : c; });
+    int m = max(max(__builtin_amdgcn_readlane(b, 15), __builtin_amdgcn_readlane(b, 31)),
+                max(__builtin_amdgcn_readlane(b, 47), __builtin_amdgcn_readlane(b, 63)));
+    return __int_as_float(m);
 }
 
 __device__ __forceinline__ double wave_max(double v) {
@@ -30,18 +51,29 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+    int b = dpp_row_scan((int)v, -1, [](int a, int c) { return (uint32_t)a < (uint32_t)c ? a : c; });
+    uint32_t m0 = (uint32_t)__builtin_amdgcn_readlane(b, 15), m1 = (uint32_t)__builtin_amdgcn_readlane(b, 31);
+    uint32_t m2 = (uint32_t)__builtin_amdgcn_readlane(b, 47), m3 = (uint32_t)__builtin_amdgcn_readlane(b, 63);
+    m0 = m0 < m1 ? m0 : m1;
+    m2 = m2 < m3 ? m2 : m3;
+    return m0 < m2 ? m0 : m2;
+}
+
 __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        uint32_t lo = __shfl_xor((uint32_t)v, o);
-        uint32_t hi = __shfl_xor((uint32_t)(v >> 32), o);
-        uint64_t w = ((uint64_t)hi << 32) | lo;
-        v = w < v ? w : v;
-    }
-    return v;
+    const uint32_t hi = wave_min_u32((uint32_t)(v >> 32));
+    const uint32_t lo = wave_min_u32((uint32_t)(v >> 32) == hi ? (uint32_t)v : 0xffffffffu);
+    return ((uint64_t)hi << 32) | lo;
 }
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// A wave-uniform double moved to scalar registers.
+__device__ __forceinline__ double uniform_d(double v) {
+    long long b = __double_as_longlong(v);
+    int lo = __builtin_amdgcn_readfirstlane((int)b), hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
 
 // --------------------------------------------------------------------------
 // exact distance field lookups

@@ -16,15 +16,17 @@
 //   pair distance   d^2(t) = A + B cos t + C sin t
 // with P0 = p + (k.u)k, U = u - (k.u)k, V = k x u, u = X_moving - p, and
 // A = |u|^2 + |v|^2 - 2(k.u)(k.v), B = -2(u.v - (k.u)(k.v)), C = -2 v.(k x u),
-// v = X_fixed - p.  Every FP32 decision carries a rounding-error bound; a cell
-// index or bump decision within that bound of a boundary is marked uncertain,
-// and any uncertain candidate that could still win the sweep is re-evaluated
-// with the FP64 formulas above, so the chosen angle equals the FP64 choice.
+// v = X_fixed - p.  Over a full turn d^2 never drops below A - sqrt(B^2 + C^2),
+// so pairs that cannot bump at any angle are dropped once per sweep.  Every
+// FP32 decision carries a rounding-error bound; a cell index or bump decision
+// within that bound of a boundary is marked uncertain, and any uncertain
+// candidate that could still win the sweep is re-evaluated with the FP64
+// formulas above, so the chosen angle equals the FP64 choice.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "gd_internal.h"
 #include "device_common.h"
+#include "gd_internal.h"
 
 namespace gd {
 
@@ -60,34 +62,43 @@ __device__ __forceinline__ void rotate_about(double px, double py, double pz, co
 // --------------------------------------------------------------------------
 // per-wave LDS
 
+constexpr int kSurvCap = 512;  // straddling pairs that can still bump in one sweep
+
 struct WaveLds {
-    double* X;     // [3][lp] FP64 master coordinates (x, y, z planes)
-    double* AD;    // [8][lp] per-atom sweep data: u (3), k.u, k x u (3), |u|^2
-    float* MV;     // [9][lp] moving atoms: P0 (3), U (3), V (3) in cell units
-    int* Slo;      // [nmax]
-    int* Shi;      // [nmax]
-    uint8_t* st;   // [nmax] bit0: certain bump, bit1: possible bump
+    double* X;       // [3][lp] FP64 master coordinates (x, y, z planes)
+    double* SW;      // [8] FP64 axis k (3) and pivot p (3) of the sweep in progress
+    float* AD;       // [8][lp] per-atom sweep data: u (3), k.u, k x u (3), |u|^2
+    float4* MV;      // [lp][3] moving atoms: P0, U, V in cell units (w unused)
+    int* Slo;        // [nmax] lower bound of each candidate's S over the moving atoms
+    int* Shi;        // [nmax] upper bound
+    uint8_t* st;     // [nmax] bit0: certain bump, bit1: possible bump
+    uint16_t* surv;  // [kSurvCap] the pairs that survive the sweep's prune
+    int* red;        // [128] transpose buffer of the score reduction
 };
 
-__host__ __device__ inline int lds_pitch(int lmax) { return (lmax + 1) & ~1; }
+__host__ __device__ inline int lds_pitch(int lmax) { return (lmax + 3) & ~3; }
 __host__ __device__ inline size_t wave_lds_bytes(int lmax, int nmax) {
     int lp = lds_pitch(lmax);
-    size_t b = sizeof(double) * 3 * lp + sizeof(double) * 8 * lp + sizeof(float) * 9 * lp +
-               sizeof(int) * 2 * nmax + ((nmax + 15) & ~15);
+    size_t b = sizeof(double) * 3 * lp + sizeof(double) * 8 + sizeof(float) * 8 * lp + sizeof(float4) * 3 * lp +
+               sizeof(int) * 2 * nmax + ((nmax + 15) & ~15) + sizeof(uint16_t) * kSurvCap + sizeof(int) * 128;
     return (b + 15) & ~(size_t)15;
 }
-
-__host__ __device__ inline size_t replay_lds_bytes(int lmax) { return sizeof(double) * 3 * lds_pitch(lmax); }
+__host__ __device__ inline size_t replay_lds_bytes(int lmax) {
+    return sizeof(double) * 3 * lds_pitch(lmax) + sizeof(double) * 8;
+}
 
 __device__ inline WaveLds carve(char* base, int lmax, int nmax) {
     int lp = lds_pitch(lmax);
     WaveLds W;
     W.X = (double*)base;
-    W.AD = W.X + 3 * lp;
-    W.MV = (float*)(W.AD + 8 * lp);
-    W.Slo = (int*)(W.MV + 9 * lp);
+    W.SW = W.X + 3 * lp;
+    W.AD = (float*)(W.SW + 8);
+    W.MV = (float4*)(W.AD + 8 * lp);
+    W.Slo = (int*)(W.MV + 3 * lp);
     W.Shi = W.Slo + nmax;
     W.st = (uint8_t*)(W.Shi + nmax);
+    W.surv = (uint16_t*)(W.st + ((nmax + 15) & ~15));
+    W.red = (int*)(W.surv + kSurvCap);
     return W;
 }
 
@@ -96,24 +107,27 @@ struct Acc {
     int oob = 0;
 };
 
-// State of the sweep in progress (wave-uniform values).
+// Wave-uniform state of the sweep in progress used by the FP32 passes.
 struct Sweep {
     const uint8_t* mvl;       // moving atoms
     const uint16_t* pairs;    // straddling far pairs (left | right << 8)
-    int m, npairs, side, l, lp;
-    double kx, ky, kz, px, py, pz;
+    int m, npairs, side, lp;
     float gcell;              // guard for cell decisions (cell units)
     float thr_lo, thr_hi;     // bump thresholds on FP32 d^2
+    int nsurv;                // pairs that can bump at some angle of this sweep
+    bool pruned;              // survivors listed in LDS (else test every pair)
 };
 
 // --------------------------------------------------------------------------
 // FP64 evaluation of one candidate of the current sweep: S over the moving
 // atoms and feasibility over the straddling far pairs.
 
-__device__ bool eval_fp64(const PocketDev& P, const BatchDev& B, const Sweep& sw, const WaveLds& W, int deg,
-                          int& S_out, Acc& acc) {
+__device__ __noinline__ bool eval_fp64(const PocketDev& P, const BatchDev& B, const Sweep& sw, const WaveLds& W,
+                                       int deg, int& S_out, Acc& acc) {
     const int lane = lane_id();
-    const Mat3 R = axis_angle(sw.kx, sw.ky, sw.kz, deg);
+    const double kx = uniform_d(W.SW[0]), ky = uniform_d(W.SW[1]), kz = uniform_d(W.SW[2]);
+    const double px = uniform_d(W.SW[3]), py = uniform_d(W.SW[4]), pz = uniform_d(W.SW[5]);
+    const Mat3 R = axis_angle(kx, ky, kz, deg);
     const double* Xx = W.X;
     const double* Xy = W.X + sw.lp;
     const double* Xz = W.X + 2 * sw.lp;
@@ -121,7 +135,7 @@ __device__ bool eval_fp64(const PocketDev& P, const BatchDev& B, const Sweep& sw
     for (int j = lane; j < sw.m; j += kWave) {
         int i = sw.mvl[j];
         double yx, yy, yz;
-        rotate_about(sw.px, sw.py, sw.pz, R, Xx[i], Xy[i], Xz[i], yx, yy, yz);
+        rotate_about(px, py, pz, R, Xx[i], Xy[i], Xz[i], yx, yy, yz);
         S += D_exact(P, yx, yy, yz, acc.oob);
     }
     S = wave_sum(S);
@@ -131,7 +145,7 @@ __device__ bool eval_fp64(const PocketDev& P, const BatchDev& B, const Sweep& sw
         int li = pr & 0xff, ri = pr >> 8;
         int mv = sw.side == 0 ? li : ri, fx = sw.side == 0 ? ri : li;
         double yx, yy, yz;
-        rotate_about(sw.px, sw.py, sw.pz, R, Xx[mv], Xy[mv], Xz[mv], yx, yy, yz);
+        rotate_about(px, py, pz, R, Xx[mv], Xy[mv], Xz[mv], yx, yy, yz);
         clash |= dist2(yx, yy, yz, Xx[fx], Xy[fx], Xz[fx]) < B.cd2;
     }
     clash = __ballot(clash) != 0;
@@ -140,34 +154,74 @@ __device__ bool eval_fp64(const PocketDev& P, const BatchDev& B, const Sweep& sw
     return !clash;
 }
 
-// FP32 contribution of one candidate atom with an interval for cells within
-// the guard of a face.
-__device__ __forceinline__ void atom_cell_score(const PocketDev& P, float yx, float yy, float yz, float g, int& slo,
+// FP32 contribution of one candidate atom.  An atom within the guard of a
+// cell face, or outside the tabulated grid, widens the candidate's S range to
+// [S of the other atoms, unbounded]; such a candidate is re-evaluated in FP64
+// if it can still win its sweep.
+constexpr int kOpenHi = 0x20000000;
+
+__device__ __forceinline__ void atom_cell_score(const PocketDev& P, float yx, float yy, float yz, float lim, int& slo,
                                                 int& shi, int& oob) {
-    float fx = floorf(yx), fy = floorf(yy), fz = floorf(yz);
-    float rx = yx - fx, ry = yy - fy, rz = yz - fz;  // exact in FP32
-    int ix = (int)fx, iy = (int)fy, iz = (int)fz;
-    float lim = 0.5f - g;
-    bool ux = fabsf(rx - 0.5f) > lim, uy = fabsf(ry - 0.5f) > lim, uz = fabsf(rz - 0.5f) > lim;
-    if (!(ux | uy | uz)) {
-        int d = D_box(P, ix, iy, iz, oob);
+    const float fx = floorf(yx), fy = floorf(yy), fz = floorf(yz);
+    const int ix = (int)fx, iy = (int)fy, iz = (int)fz;
+    const bool sure = fabsf(yx - fx - 0.5f) <= lim && fabsf(yy - fy - 0.5f) <= lim && fabsf(yz - fz - 0.5f) <= lim &&
+                      (unsigned)ix < (unsigned)P.dim[0] && (unsigned)iy < (unsigned)P.dim[1] &&
+                      (unsigned)iz < (unsigned)P.dim[2];
+    if (sure) {
+        const int d = P.edt[(iz * P.dim[1] + iy) * P.dim[0] + ix];
         slo += d;
         shi += d;
-        return;
+    } else {
+        shi = kOpenHi;
+        oob += !((unsigned)ix < (unsigned)P.dim[0] && (unsigned)iy < (unsigned)P.dim[1] &&
+                 (unsigned)iz < (unsigned)P.dim[2]);
     }
-    // a coordinate within the guard of a face: the true cell is one of two per
-    // uncertain axis; take the range of D over those cells
-    int ax = ux ? (rx < 0.5f ? -1 : 1) : 0, ay = uy ? (ry < 0.5f ? -1 : 1) : 0, az = uz ? (rz < 0.5f ? -1 : 1) : 0;
-    int lo = 0x7fffffff, hi = 0;
-    for (int dz = 0; dz <= (az != 0); dz++)
-        for (int dy = 0; dy <= (ay != 0); dy++)
-            for (int dx = 0; dx <= (ax != 0); dx++) {
-                int d = D_box(P, ix + dx * ax, iy + dy * ay, iz + dz * az, oob);
-                lo = d < lo ? d : lo;
-                hi = d > hi ? d : hi;
-            }
-    slo += lo;
-    shi += hi;
+}
+
+// K pairs per lane starting at q0: FP32 A, B, C from the per-atom data, then
+// for each of the nw angles of the word a certain / possible bump bit.
+template <int K>
+__device__ __forceinline__ void bump_block(const Sweep& sw, const WaveLds& W, int q0, int nq, int nw, float cl,
+                                           float sl, uint64_t& cert, uint64_t& maybe) {
+    const int lane = lane_id();
+    const int lp = sw.lp;
+    const float* ux = W.AD;
+    const float* uy = W.AD + lp;
+    const float* uz = W.AD + 2 * lp;
+    const float* ku = W.AD + 3 * lp;
+    const float* wx = W.AD + 4 * lp;
+    const float* wy = W.AD + 5 * lp;
+    const float* wz = W.AD + 6 * lp;
+    const float* uu = W.AD + 7 * lp;
+    float A[K], Bc[K], Cs[K];
+#pragma unroll
+    for (int t = 0; t < K; t++) {
+        const int q = q0 + t * kWave + lane;
+        if (q < nq) {
+            uint16_t pr = sw.pruned ? W.surv[q] : sw.pairs[q];
+            int li = pr & 0xff, ri = pr >> 8;
+            int m = sw.side == 0 ? li : ri, f = sw.side == 0 ? ri : li;
+            float kk = ku[m] * ku[f];
+            float uv = ux[m] * ux[f] + uy[m] * uy[f] + uz[m] * uz[f];
+            float vw = ux[f] * wx[m] + uy[f] * wy[m] + uz[f] * wz[m];
+            A[t] = uu[m] + uu[f] - 2.f * kk;
+            Bc[t] = -2.f * (uv - kk);
+            Cs[t] = -2.f * vw;
+        } else {
+            A[t] = 3.0e38f;
+            Bc[t] = 0.f;
+            Cs[t] = 0.f;
+        }
+    }
+    for (int k = 0; k < nw; k++) {
+        const float c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cl), k));
+        const float s = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sl), k));
+        float d = fmaf(Cs[0], s, fmaf(Bc[0], c, A[0]));
+#pragma unroll
+        for (int t = 1; t < K; t++) d = fminf(d, fmaf(Cs[t], s, fmaf(Bc[t], c, A[t])));
+        if (__ballot(d < sw.thr_lo)) cert |= 1ull << k;
+        if (__ballot(d < sw.thr_hi)) maybe |= 1ull << k;
+    }
 }
 
 // Evaluate the candidate angles base + k*stride (k < n) of the current sweep;
@@ -178,10 +232,12 @@ __device__ int eval_candidates(const PocketDev& P, const BatchDev& B, const Swee
                                int stride, int n, Acc& acc) {
     const int lane = lane_id();
     constexpr int G = kWave / NB;
-    const int lp = sw.lp;
     acc.poses += n;
 
-    // ---- score pass: lanes = (angle within block, atom group)
+    // ---- score pass: lanes = (angle within block, atom group); four atoms
+    // per step so that four distance-grid gathers are in flight at once
+    const int nx = P.dim[0], ny = P.dim[1], nz = P.dim[2];
+    const float lim = 0.5f - sw.gcell;
     for (int kb = 0; kb < n; kb += NB) {
         const int k = kb + (lane & (NB - 1));
         const int g = lane / NB;
@@ -189,34 +245,63 @@ __device__ int eval_candidates(const PocketDev& P, const BatchDev& B, const Swee
         if (k < n) {
             const int deg = base + k * stride;
             const float c = c_cos32[deg], s = c_sin32[deg];
-            for (int j = g; j < sw.m; j += G) {
-                const float* mv = W.MV + j;
-                float yx = fmaf(s, mv[6 * lp], fmaf(c, mv[3 * lp], mv[0]));
-                float yy = fmaf(s, mv[7 * lp], fmaf(c, mv[4 * lp], mv[lp]));
-                float yz = fmaf(s, mv[8 * lp], fmaf(c, mv[5 * lp], mv[2 * lp]));
-                atom_cell_score(P, yx, yy, yz, sw.gcell, slo, shi, acc.oob);
+            int j = g;
+            for (; j + 3 * G < sw.m; j += 4 * G) {
+                int idx[4];
+                bool fast = true;
+#pragma unroll
+                for (int t = 0; t < 4; t++) {
+                    const int jj = j + t * G;
+                    const float4 p0 = W.MV[3 * jj], u = W.MV[3 * jj + 1], v = W.MV[3 * jj + 2];
+                    const float yx = fmaf(s, v.x, fmaf(c, u.x, p0.x));
+                    const float yy = fmaf(s, v.y, fmaf(c, u.y, p0.y));
+                    const float yz = fmaf(s, v.z, fmaf(c, u.z, p0.z));
+                    const float fx = floorf(yx), fy = floorf(yy), fz = floorf(yz);
+                    const int ix = (int)fx, iy = (int)fy, iz = (int)fz;
+                    fast &= fabsf(yx - fx - 0.5f) <= lim && fabsf(yy - fy - 0.5f) <= lim &&
+                            fabsf(yz - fz - 0.5f) <= lim && (unsigned)ix < (unsigned)nx &&
+                            (unsigned)iy < (unsigned)ny && (unsigned)iz < (unsigned)nz;
+                    idx[t] = (iz * ny + iy) * nx + ix;
+                }
+                if (fast) {
+                    const int d = (int)P.edt[idx[0]] + (int)P.edt[idx[1]] + (int)P.edt[idx[2]] + (int)P.edt[idx[3]];
+                    slo += d;
+                    shi += d;
+                } else {
+#pragma unroll
+                    for (int t = 0; t < 4; t++) {
+                        const int jj = j + t * G;
+                        const float4 p0 = W.MV[3 * jj], u = W.MV[3 * jj + 1], v = W.MV[3 * jj + 2];
+                        atom_cell_score(P, fmaf(s, v.x, fmaf(c, u.x, p0.x)), fmaf(s, v.y, fmaf(c, u.y, p0.y)),
+                                        fmaf(s, v.z, fmaf(c, u.z, p0.z)), lim, slo, shi, acc.oob);
+                    }
+                }
+            }
+            for (; j < sw.m; j += G) {
+                const float4 p0 = W.MV[3 * j], u = W.MV[3 * j + 1], v = W.MV[3 * j + 2];
+                atom_cell_score(P, fmaf(s, v.x, fmaf(c, u.x, p0.x)), fmaf(s, v.y, fmaf(c, u.y, p0.y)),
+                                fmaf(s, v.z, fmaf(c, u.z, p0.z)), lim, slo, shi, acc.oob);
             }
         }
-#pragma unroll
-        for (int o = NB; o < kWave; o <<= 1) {
-            slo += __shfl_xor(slo, o);
-            shi += __shfl_xor(shi, o);
-        }
+        // sum the groups of each angle through LDS
+        W.red[lane] = slo;
+        W.red[kWave + lane] = shi;
+        wave_sync();
         if (lane < NB && k < n) {
-            W.Slo[k] = slo;
-            W.Shi[k] = shi;
+            int a = 0, b = 0;
+#pragma unroll
+            for (int gg = 0; gg < G; gg++) {
+                a += W.red[lane + gg * NB];
+                b = min(b + W.red[kWave + lane + gg * NB], kOpenHi);
+            }
+            W.Slo[k] = a;
+            W.Shi[k] = b >= kOpenHi ? kOpenHi : b;
         }
+        wave_sync();
     }
 
-    // ---- bump pass: lanes = straddling pairs, loop over angles of a word
-    const double* ux = W.AD;
-    const double* uy = W.AD + lp;
-    const double* uz = W.AD + 2 * lp;
-    const double* ku = W.AD + 3 * lp;
-    const double* wx = W.AD + 4 * lp;
-    const double* wy = W.AD + 5 * lp;
-    const double* wz = W.AD + 6 * lp;
-    const double* uu = W.AD + 7 * lp;
+    // ---- bump pass: lanes = straddling pairs (the survivors of the prune),
+    // loop over the angles of a word of 64 candidates
     for (int w0 = 0; w0 < n; w0 += kWave) {
         const int nw = min(kWave, n - w0);
         float cl = 0.f, sl = 0.f;
@@ -226,37 +311,12 @@ __device__ int eval_candidates(const PocketDev& P, const BatchDev& B, const Swee
             sl = c_sin32[deg];
         }
         uint64_t cert = 0, maybe = 0;
-        for (int q0 = 0; q0 < sw.npairs; q0 += kWave * PPL) {
-            float A[PPL], Bc[PPL], Cs[PPL];
-#pragma unroll
-            for (int t = 0; t < PPL; t++) {
-                const int q = q0 + t * kWave + lane;
-                if (q < sw.npairs) {
-                    uint16_t pr = sw.pairs[q];
-                    int li = pr & 0xff, ri = pr >> 8;
-                    int m = sw.side == 0 ? li : ri, f = sw.side == 0 ? ri : li;
-                    double kk = ku[m] * ku[f];
-                    double uv = ux[m] * ux[f] + uy[m] * uy[f] + uz[m] * uz[f];
-                    double vw = ux[f] * wx[m] + uy[f] * wy[m] + uz[f] * wz[m];
-                    A[t] = (float)(uu[m] + uu[f] - 2.0 * kk);
-                    Bc[t] = (float)(-2.0 * (uv - kk));
-                    Cs[t] = (float)(-2.0 * vw);
-                } else {
-                    A[t] = 3.0e38f;
-                    Bc[t] = 0.f;
-                    Cs[t] = 0.f;
-                }
-            }
-            for (int k = 0; k < nw; k++) {
-                const float c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cl), k));
-                const float s = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sl), k));
-                float d = fmaf(Cs[0], s, fmaf(Bc[0], c, A[0]));
-#pragma unroll
-                for (int t = 1; t < PPL; t++) d = fminf(d, fmaf(Cs[t], s, fmaf(Bc[t], c, A[t])));
-                if (__ballot(d < sw.thr_lo)) cert |= 1ull << k;
-                if (__ballot(d < sw.thr_hi)) maybe |= 1ull << k;
-            }
-        }
+        const int nq = sw.pruned ? sw.nsurv : sw.npairs;
+        int q0 = 0;
+        if (PPL > 1)
+            for (; nq - q0 > kWave * (PPL - 1); q0 += kWave * PPL)
+                bump_block<PPL>(sw, W, q0, nq, nw, cl, sl, cert, maybe);
+        for (; q0 < nq; q0 += kWave) bump_block<1>(sw, W, q0, nq, nw, cl, sl, cert, maybe);
         if (lane < nw) W.st[w0 + lane] = (uint8_t)(((cert >> lane) & 1) | (((maybe >> lane) & 1) << 1));
     }
     wave_sync();
@@ -298,102 +358,153 @@ __device__ int eval_candidates(const PocketDev& P, const BatchDev& B, const Swee
     return best == ~0ull ? -1 : (int)(best & 0xffff);
 }
 
-// Prepare one fragment sweep: FP64 axis and pivot, per-atom pair data and the
-// FP32 moving-atom coefficients, plus the rounding guards of this sweep.
-__device__ void sweep_setup(const PocketDev& P, const BatchDev& B, const LigMeta& L, const RotInfo& ri, int side,
-                            const WaveLds& W, Sweep& sw) {
+// Axis k = (X_c - X_a)/|X_c - X_a| and pivot of one fragment sweep (FP64,
+// stored in W.SW), from the current master coordinates.
+__device__ __forceinline__ void sweep_axis(const WaveLds& W, int lp, int a, int c, int piv) {
+    if (lane_id() == 0) {
+        const double* Xx = W.X;
+        const double* Xy = W.X + lp;
+        const double* Xz = W.X + 2 * lp;
+        double ax = Xx[c] - Xx[a], ay = Xy[c] - Xy[a], az = Xz[c] - Xz[a];
+        double nrm = sqrt(ax * ax + ay * ay + az * az);
+        W.SW[0] = ax / nrm;
+        W.SW[1] = ay / nrm;
+        W.SW[2] = az / nrm;
+        W.SW[3] = Xx[piv];
+        W.SW[4] = Xy[piv];
+        W.SW[5] = Xz[piv];
+    }
+    wave_sync();
+}
+
+// Prepare one fragment sweep: axis and pivot, per-atom pair data, FP32
+// moving-atom coefficients, the rounding guards, and the pair prune.
+__device__ __forceinline__ void sweep_setup(const PocketDev& P, const BatchDev& B, const LigMeta& L,
+                                         const RotInfo& ri, int side, const WaveLds& W, Sweep& sw) {
     const int lane = lane_id();
     const int lp = lds_pitch(B.lmax);
     const double* Xx = W.X;
     const double* Xy = W.X + lp;
     const double* Xz = W.X + 2 * lp;
     sw.lp = lp;
-    sw.l = L.l;
     sw.side = side;
     sw.mvl = B.mv + ri.mv_off[side];
     sw.m = ri.n_mv[side];
     sw.pairs = B.pairs + ri.pair_off;
     sw.npairs = ri.n_pairs;
-    const int a = ri.a, c = ri.c;
-    double ax = Xx[c] - Xx[a], ay = Xy[c] - Xy[a], az = Xz[c] - Xz[a];
-    double nrm = sqrt(ax * ax + ay * ay + az * az);
-    sw.kx = ax / nrm;
-    sw.ky = ay / nrm;
-    sw.kz = az / nrm;
-    const int piv = side == 0 ? a : c;
-    sw.px = Xx[piv];
-    sw.py = Xy[piv];
-    sw.pz = Xz[piv];
-    wave_sync();
+    sweep_axis(W, lp, ri.a, ri.c, side == 0 ? ri.a : ri.c);
+    const double kx = uniform_d(W.SW[0]), ky = uniform_d(W.SW[1]), kz = uniform_d(W.SW[2]);
+    const double px = uniform_d(W.SW[3]), py = uniform_d(W.SW[4]), pz = uniform_d(W.SW[5]);
 
-    double r2max = 0.0;
+    float r2max = 0.f;
     for (int i = lane; i < L.l; i += kWave) {
-        double ux = Xx[i] - sw.px, uy = Xy[i] - sw.py, uz = Xz[i] - sw.pz;
-        double ku = sw.kx * ux + sw.ky * uy + sw.kz * uz;
+        double ux = Xx[i] - px, uy = Xy[i] - py, uz = Xz[i] - pz;
+        double ku = kx * ux + ky * uy + kz * uz;
         double uu = ux * ux + uy * uy + uz * uz;
-        W.AD[i] = ux;
-        W.AD[lp + i] = uy;
-        W.AD[2 * lp + i] = uz;
-        W.AD[3 * lp + i] = ku;
-        W.AD[4 * lp + i] = sw.ky * uz - sw.kz * uy;
-        W.AD[5 * lp + i] = sw.kz * ux - sw.kx * uz;
-        W.AD[6 * lp + i] = sw.kx * uy - sw.ky * ux;
-        W.AD[7 * lp + i] = uu;
-        r2max = fmax(r2max, uu);
+        W.AD[i] = (float)ux;
+        W.AD[lp + i] = (float)uy;
+        W.AD[2 * lp + i] = (float)uz;
+        W.AD[3 * lp + i] = (float)ku;
+        W.AD[4 * lp + i] = (float)(ky * uz - kz * uy);
+        W.AD[5 * lp + i] = (float)(kz * ux - kx * uz);
+        W.AD[6 * lp + i] = (float)(kx * uy - ky * ux);
+        W.AD[7 * lp + i] = (float)uu;
+        r2max = fmaxf(r2max, (float)uu);
     }
-    double amax = 0.0, umax = 0.0;
+    float amax = 0.f, umax = 0.f;
     const double ih = P.inv_h;
     for (int j = lane; j < sw.m; j += kWave) {
         int i = sw.mvl[j];
-        double ux = Xx[i] - sw.px, uy = Xy[i] - sw.py, uz = Xz[i] - sw.pz;
-        double ku = sw.kx * ux + sw.ky * uy + sw.kz * uz;
-        double ax0 = (sw.px + ku * sw.kx) * ih - (double)P.lo[0];
-        double ay0 = (sw.py + ku * sw.ky) * ih - (double)P.lo[1];
-        double az0 = (sw.pz + ku * sw.kz) * ih - (double)P.lo[2];
-        double Ux = (ux - ku * sw.kx) * ih, Uy = (uy - ku * sw.ky) * ih, Uz = (uz - ku * sw.kz) * ih;
-        double Vx = (sw.ky * uz - sw.kz * uy) * ih, Vy = (sw.kz * ux - sw.kx * uz) * ih,
-               Vz = (sw.kx * uy - sw.ky * ux) * ih;
-        float* mv = W.MV + j;
-        mv[0] = (float)ax0;
-        mv[lp] = (float)ay0;
-        mv[2 * lp] = (float)az0;
-        mv[3 * lp] = (float)Ux;
-        mv[4 * lp] = (float)Uy;
-        mv[5 * lp] = (float)Uz;
-        mv[6 * lp] = (float)Vx;
-        mv[7 * lp] = (float)Vy;
-        mv[8 * lp] = (float)Vz;
-        amax = fmax(amax, fmax(fabs(ax0), fmax(fabs(ay0), fabs(az0))));
-        umax = fmax(umax, fmax(fabs(Ux), fmax(fabs(Uy), fmax(fabs(Uz), fmax(fabs(Vx), fmax(fabs(Vy), fabs(Vz)))))));
+        double ux = Xx[i] - px, uy = Xy[i] - py, uz = Xz[i] - pz;
+        double ku = kx * ux + ky * uy + kz * uz;
+        double ax0 = (px + ku * kx) * ih - (double)P.lo[0];
+        double ay0 = (py + ku * ky) * ih - (double)P.lo[1];
+        double az0 = (pz + ku * kz) * ih - (double)P.lo[2];
+        double Ux = (ux - ku * kx) * ih, Uy = (uy - ku * ky) * ih, Uz = (uz - ku * kz) * ih;
+        double Vx = (ky * uz - kz * uy) * ih, Vy = (kz * ux - kx * uz) * ih, Vz = (kx * uy - ky * ux) * ih;
+        W.MV[3 * j] = make_float4((float)ax0, (float)ay0, (float)az0, 0.f);
+        W.MV[3 * j + 1] = make_float4((float)Ux, (float)Uy, (float)Uz, 0.f);
+        W.MV[3 * j + 2] = make_float4((float)Vx, (float)Vy, (float)Vz, 0.f);
+        amax = fmaxf(amax, (float)fmax(fabs(ax0), fmax(fabs(ay0), fabs(az0))));
+        umax = fmaxf(umax, (float)fmax(fmax(fabs(Ux), fmax(fabs(Uy), fabs(Uz))),
+                                       fmax(fabs(Vx), fmax(fabs(Vy), fabs(Vz)))));
     }
-    r2max = wave_max(r2max);
-    amax = wave_max(amax);
-    umax = wave_max(umax);
-    // FP32 error of Y = fma(s, V, fma(c, U, P0)) from FP64 P0, U, V:
-    //   <= u (3|P0| + 4|U| + 3|V|), u = 2^-24; doubled for safety.
+    r2max = wave_maxf(r2max);
+    amax = wave_maxf(amax);
+    umax = wave_maxf(umax);
+    // Rounding guards (u = 2^-24), each doubled for safety and with the maxima
+    // rounded up by 1 %:
+    //  cell: Y = fma(s, V, fma(c, U, P0)) from P0, U, V rounded once from FP64
+    //        deviates by <= u (3|P0| + 4|U| + 3|V|) cell units;
+    //  bump: A, B, C formed in FP32 from per-atom data rounded from FP64
+    //        (|u| <= R) carry <= 18, 20 and 10 u R^2; their evaluation adds
+    //        <= u (3|A| + 4|B| + 3|C|) <= 26 u R^2: 74 u R^2 in all.
     const double u32 = 1.0 / 16777216.0;
-    sw.gcell = (float)(2.0 * u32 * (3.0 * amax + 7.0 * umax) + 1e-6);
-    // FP32 error of d^2 = fma(C, s, fma(B, c, A)) with |A| <= 4R^2, |B|,|C| <= 2R^2
-    //   (A, B, C rounded from FP64): <= u (3|A| + 4|B| + 3|C|) as for Y above,
-    //   from the evaluation, i.e. <= 26 u R^2 in all; doubled for safety.
-    double gc = 2.0 * u32 * 26.0 * r2max + 1e-6;
+    sw.gcell = (float)(2.0 * u32 * (3.0 * 1.01 * amax + 7.0 * 1.01 * umax) + 1e-6);
+    const double gc = 2.0 * u32 * 74.0 * 1.01 * (double)r2max + 1e-6;
     sw.thr_lo = (float)(B.cd2 - gc);
     sw.thr_hi = (float)(B.cd2 + gc);
+    wave_sync();
+    // Prune: a pair whose smallest distance over a full turn, A - sqrt(B^2 +
+    // C^2), clears the bump distance by more than twice the guard never bumps.
+    const float* ux = W.AD;
+    const float* uy = W.AD + lp;
+    const float* uz = W.AD + 2 * lp;
+    const float* kuv = W.AD + 3 * lp;
+    const float* wx = W.AD + 4 * lp;
+    const float* wy = W.AD + 5 * lp;
+    const float* wz = W.AD + 6 * lp;
+    const float* uu = W.AD + 7 * lp;
+    const float T = (float)(B.cd2 + 2.0 * gc);
+    int nsurv = 0;
+    for (int q0 = 0; q0 < sw.npairs; q0 += 4 * kWave) {
+        uint16_t prs[4];
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+            const int q = q0 + t * kWave + lane;
+            prs[t] = q < sw.npairs ? sw.pairs[q] : (uint16_t)0;
+        }
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+            const int q = q0 + t * kWave + lane;
+            bool keep = false;
+            if (q < sw.npairs) {
+                const uint16_t pr = prs[t];
+                int li = pr & 0xff, ri2 = pr >> 8;
+                int m = side == 0 ? li : ri2, f = side == 0 ? ri2 : li;
+                float kk = kuv[m] * kuv[f];
+                float A = uu[m] + uu[f] - 2.f * kk;
+                float Bv = -2.f * (ux[m] * ux[f] + uy[m] * uy[f] + uz[m] * uz[f] - kk);
+                float Cv = -2.f * (ux[f] * wx[m] + uy[f] * wy[m] + uz[f] * wz[m]);
+                float Am = A - T;
+                keep = !(Am > 0.f && Am * Am > 1.0001f * (Bv * Bv + Cv * Cv));
+            }
+            const uint64_t mk = __ballot(keep);
+            const int pos =
+                nsurv + __builtin_amdgcn_mbcnt_hi((uint32_t)(mk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0));
+            if (keep && pos < kSurvCap) W.surv[pos] = prs[t];
+            nsurv += __popcll(mk);
+        }
+    }
+    sw.nsurv = nsurv;
+    sw.pruned = nsurv <= kSurvCap;
     wave_sync();
 }
 
 // Apply the chosen rotation to the moving fragment in FP64.
-__device__ void commit(const Sweep& sw, const WaveLds& W, int deg) {
+__device__ __forceinline__ void commit(const uint8_t* mvl, int m, const WaveLds& W, int lp, int deg) {
     if (deg == 0) return;
     const int lane = lane_id();
-    const Mat3 R = axis_angle(sw.kx, sw.ky, sw.kz, deg);
+    const double kx = uniform_d(W.SW[0]), ky = uniform_d(W.SW[1]), kz = uniform_d(W.SW[2]);
+    const double px = uniform_d(W.SW[3]), py = uniform_d(W.SW[4]), pz = uniform_d(W.SW[5]);
+    const Mat3 R = axis_angle(kx, ky, kz, deg);
     double* Xx = W.X;
-    double* Xy = W.X + sw.lp;
-    double* Xz = W.X + 2 * sw.lp;
-    for (int j = lane; j < sw.m; j += kWave) {
-        int i = sw.mvl[j];
+    double* Xy = W.X + lp;
+    double* Xz = W.X + 2 * lp;
+    for (int j = lane; j < m; j += kWave) {
+        int i = mvl[j];
         double ox, oy, oz;
-        rotate_about(sw.px, sw.py, sw.pz, R, Xx[i], Xy[i], Xz[i], ox, oy, oz);
+        rotate_about(px, py, pz, R, Xx[i], Xy[i], Xz[i], ox, oy, oz);
         Xx[i] = ox;
         Xy[i] = oy;
         Xz[i] = oz;
@@ -418,8 +529,8 @@ __device__ void place(const PocketDev& P, const BatchDev& B, const LigMeta& L, i
 }
 
 // Whole-ligand endpoint: exact S and bump flag from the FP64 pose.
-__device__ void endpoint(const PocketDev& P, const BatchDev& B, const LigMeta& L, const WaveLds& W, int& S,
-                         bool& clash, Acc& acc) {
+__device__ __forceinline__ void endpoint(const PocketDev& P, const BatchDev& B, const LigMeta& L, const WaveLds& W,
+                                      int& S, bool& clash, Acc& acc) {
     const int lane = lane_id();
     const int lp = lds_pitch(B.lmax);
     const double* Xx = W.X;
@@ -464,7 +575,7 @@ __device__ void dock_orientation(const PocketDev& P, const BatchDev& B, int lig,
                     int k = eval_candidates<NB, PPL>(P, B, sw, W, t * x, hp, x / hp, acc);
                     deg = k < 0 ? 0 : t * x + k * hp;
                 }
-                commit(sw, W, deg);
+                commit(sw.mvl, sw.m, W, sw.lp, deg);
                 acc.sweeps++;
                 if (lane_id() == 0) ang[(rep * L.nr + r) * 2 + side] = (uint16_t)deg;
             }
@@ -477,33 +588,41 @@ __device__ void dock_orientation(const PocketDev& P, const BatchDev& B, int lig,
         B.keys[L.key_off + o] = ((uint64_t)clash << 63) | ((uint64_t)(uint32_t)S << 32) | (uint64_t)(uint32_t)o;
 }
 
-__device__ void flush(const BatchDev& B, Acc& acc) {
+__device__ void flush(unsigned long long* counters, Acc& acc) {
     int oob = wave_sum(acc.oob);
-    if (lane_id() == 0 && B.counters) {
-        atomicAdd(B.counters + GD_CNT_POSES, (unsigned long long)acc.poses);
-        atomicAdd(B.counters + GD_CNT_FALLBACK, (unsigned long long)acc.fallback);
-        atomicAdd(B.counters + GD_CNT_OOB, (unsigned long long)oob);
-        atomicAdd(B.counters + GD_CNT_SWEEPS, (unsigned long long)acc.sweeps);
+    if (lane_id() == 0 && counters) {
+        atomicAdd(counters + GD_CNT_POSES, (unsigned long long)acc.poses);
+        atomicAdd(counters + GD_CNT_FALLBACK, (unsigned long long)acc.fallback);
+        atomicAdd(counters + GD_CNT_OOB, (unsigned long long)oob);
+        atomicAdd(counters + GD_CNT_SWEEPS, (unsigned long long)acc.sweeps);
     }
     acc = Acc();
 }
 
 // Per-ligand form: one launch per ligand, one wave per orientation.
 template <int NB, int PPL>
-__global__ void __launch_bounds__(512) dock_ligand_kernel(PocketDev P, BatchDev B, int lig, int nmax) {
+__global__ void __launch_bounds__(512) dock_ligand_kernel(const PocketDev* __restrict__ Pp,
+                                                          const BatchDev* __restrict__ Bp,
+                                                          unsigned long long* counters, int lig, int nmax) {
+    const PocketDev& P = *Pp;
+    const BatchDev& B = *Bp;
     extern __shared__ __align__(16) char smem[];
     const int wave = threadIdx.x / kWave;
     const WaveLds W = carve(smem + wave * wave_lds_bytes(B.lmax, nmax), B.lmax, nmax);
-    const int o = blockIdx.x * (blockDim.x / kWave) + wave;
+    const int o = uniform(blockIdx.x * (blockDim.x / kWave) + wave);
     Acc acc;
     if (o < B.n_orient) dock_orientation<NB, PPL>(P, B, lig, o, W, acc);
-    flush(B, acc);
+    flush(counters, acc);
 }
 
 // Batched form: a persistent grid; every wave pops (ligand, orientation
 // block) items from the device queue until it is empty.
 template <int NB, int PPL>
-__global__ void __launch_bounds__(512) dock_persistent_kernel(PocketDev P, BatchDev B, int nmax) {
+__global__ void __launch_bounds__(512) dock_persistent_kernel(const PocketDev* __restrict__ Pp,
+                                                              const BatchDev* __restrict__ Bp,
+                                                              unsigned long long* counters, int nmax) {
+    const PocketDev& P = *Pp;
+    const BatchDev& B = *Bp;
     extern __shared__ __align__(16) char smem[];
     const int wave = threadIdx.x / kWave;
     const WaveLds W = carve(smem + wave * wave_lds_bytes(B.lmax, nmax), B.lmax, nmax);
@@ -511,13 +630,13 @@ __global__ void __launch_bounds__(512) dock_persistent_kernel(PocketDev P, Batch
     for (;;) {
         int item = 0;
         if (lane_id() == 0) item = atomicAdd(B.head, 1);
-        item = __shfl(item, 0);
+        item = uniform(__shfl(item, 0));
         if (item >= B.n_items) break;
-        const int lig = B.items[2 * item], o0 = B.items[2 * item + 1];
+        const int lig = uniform(B.items[2 * item]), o0 = uniform(B.items[2 * item + 1]);
         const int o1 = min(o0 + B.orient_per_item, B.n_orient);
         for (int o = o0; o < o1; o++) dock_orientation<NB, PPL>(P, B, lig, o, W, acc);
     }
-    flush(B, acc);
+    flush(counters, acc);
 }
 
 __global__ void reset_kernel(int* head, unsigned long long* counters) {
@@ -589,7 +708,9 @@ __global__ void __launch_bounds__(256) replay_kernel(PocketDev P, BatchDev B, co
     if (idx >= B.n_lig * B.top_k) return;
     const int lig = idx / B.top_k;
     WaveLds W{};
+    const int lp = lds_pitch(B.lmax);
     W.X = (double*)(smem + wave * replay_lds_bytes(B.lmax));
+    W.SW = W.X + 3 * lp;
     const LigMeta L = B.lig[lig];
     const int o = recs[idx].orient;
     place(P, B, L, o, W);
@@ -599,29 +720,10 @@ __global__ void __launch_bounds__(256) replay_kernel(PocketDev P, BatchDev B, co
         for (int r = 0; r < L.nr; r++) {
             const RotInfo ri = B.rot[L.rot_off + r];
             for (int side = 0; side < 2; side++) {
-                Sweep sw;
-                const int lp = lds_pitch(B.lmax);
-                sw.lp = lp;
-                sw.side = side;
-                sw.mvl = B.mv + ri.mv_off[side];
-                sw.m = ri.n_mv[side];
-                const double* Xx = W.X;
-                const double* Xy = W.X + lp;
-                const double* Xz = W.X + 2 * lp;
-                double ax = Xx[ri.c] - Xx[ri.a], ay = Xy[ri.c] - Xy[ri.a], az = Xz[ri.c] - Xz[ri.a];
-                double nrm = sqrt(ax * ax + ay * ay + az * az);
-                sw.kx = ax / nrm;
-                sw.ky = ay / nrm;
-                sw.kz = az / nrm;
-                const int piv = side == 0 ? ri.a : ri.c;
-                sw.px = Xx[piv];
-                sw.py = Xy[piv];
-                sw.pz = Xz[piv];
-                wave_sync();
-                commit(sw, W, ang[(rep * L.nr + r) * 2 + side]);
+                sweep_axis(W, lp, ri.a, ri.c, side == 0 ? ri.a : ri.c);
+                commit(B.mv + ri.mv_off[side], ri.n_mv[side], W, lp, ang[(rep * L.nr + r) * 2 + side]);
             }
         }
-    const int lp = lds_pitch(B.lmax);
     float* dst = xyz + (size_t)idx * B.lmax * 3;
     for (int i = lane_id(); i < B.lmax; i += kWave) {
         bool in = i < L.l;
@@ -651,40 +753,6 @@ hipError_t upload_trig_tables() {
 
 size_t dock_lds_bytes(int lmax, int nmax, int waves) { return wave_lds_bytes(lmax, nmax) * waves; }
 
-template <int NB, int PPL>
-static hipError_t launch_dock_t(const PocketDev& P, const BatchDev& B, int nmax, int waves, bool persistent,
-                                int lig, int grid, hipStream_t s) {
-    size_t lds = dock_lds_bytes(B.lmax, nmax, waves);
-    if (persistent)
-        hipLaunchKernelGGL((dock_persistent_kernel<NB, PPL>), dim3(grid), dim3(waves * kWave), lds, s, P, B, nmax);
-    else
-        hipLaunchKernelGGL((dock_ligand_kernel<NB, PPL>), dim3(grid), dim3(waves * kWave), lds, s, P, B, lig, nmax);
-    return hipGetLastError();
-}
-
-template <int NB>
-static hipError_t launch_dock_nb(const PocketDev& P, const BatchDev& B, int nmax, const Tiling& t, bool persistent,
-                                 int lig, int grid, hipStream_t s) {
-    switch (t.pairs_per_lane) {
-        case 1: return launch_dock_t<NB, 1>(P, B, nmax, t.waves_per_block, persistent, lig, grid, s);
-        case 2: return launch_dock_t<NB, 2>(P, B, nmax, t.waves_per_block, persistent, lig, grid, s);
-        case 4: return launch_dock_t<NB, 4>(P, B, nmax, t.waves_per_block, persistent, lig, grid, s);
-        case 8: return launch_dock_t<NB, 8>(P, B, nmax, t.waves_per_block, persistent, lig, grid, s);
-        default: return hipErrorInvalidValue;
-    }
-}
-
-hipError_t launch_dock(const PocketDev& P, const BatchDev& B, int nmax, const Tiling& t, bool persistent, int lig,
-                       int grid, hipStream_t s) {
-    switch (t.angle_block) {
-        case 4: return launch_dock_nb<4>(P, B, nmax, t, persistent, lig, grid, s);
-        case 8: return launch_dock_nb<8>(P, B, nmax, t, persistent, lig, grid, s);
-        case 16: return launch_dock_nb<16>(P, B, nmax, t, persistent, lig, grid, s);
-        case 32: return launch_dock_nb<32>(P, B, nmax, t, persistent, lig, grid, s);
-        default: return hipErrorInvalidValue;
-    }
-}
-
 size_t lds_limit_per_block() {
     static size_t lim = 0;
     if (!lim) {
@@ -695,6 +763,40 @@ size_t lds_limit_per_block() {
         if (!lim) lim = 64 * 1024;
     }
     return lim;
+}
+
+template <int NB, int PPL>
+static hipError_t launch_dock_t(const DockLaunch& L, int waves, bool persistent, int lig, int grid, hipStream_t s) {
+    size_t lds = dock_lds_bytes(L.lmax, L.nmax, waves);
+    if (persistent)
+        hipLaunchKernelGGL((dock_persistent_kernel<NB, PPL>), dim3(grid), dim3(waves * kWave), lds, s, L.P, L.B,
+                           L.counters, L.nmax);
+    else
+        hipLaunchKernelGGL((dock_ligand_kernel<NB, PPL>), dim3(grid), dim3(waves * kWave), lds, s, L.P, L.B,
+                           L.counters, lig, L.nmax);
+    return hipGetLastError();
+}
+
+template <int NB>
+static hipError_t launch_dock_nb(const DockLaunch& L, const Tiling& t, bool persistent, int lig, int grid,
+                                 hipStream_t s) {
+    switch (t.pairs_per_lane) {
+        case 1: return launch_dock_t<NB, 1>(L, t.waves_per_block, persistent, lig, grid, s);
+        case 2: return launch_dock_t<NB, 2>(L, t.waves_per_block, persistent, lig, grid, s);
+        case 4: return launch_dock_t<NB, 4>(L, t.waves_per_block, persistent, lig, grid, s);
+        case 8: return launch_dock_t<NB, 8>(L, t.waves_per_block, persistent, lig, grid, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_dock(const DockLaunch& L, const Tiling& t, bool persistent, int lig, int grid, hipStream_t s) {
+    switch (t.angle_block) {
+        case 4: return launch_dock_nb<4>(L, t, persistent, lig, grid, s);
+        case 8: return launch_dock_nb<8>(L, t, persistent, lig, grid, s);
+        case 16: return launch_dock_nb<16>(L, t, persistent, lig, grid, s);
+        case 32: return launch_dock_nb<32>(L, t, persistent, lig, grid, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 int persistent_grid(const Tiling& t, int lmax, int nmax, int n_items) {

@@ -133,8 +133,14 @@ namespace gd {
 hipError_t upload_trig_tables();
 size_t dock_lds_bytes(int lmax, int nmax, int waves);
 size_t lds_limit_per_block();
-hipError_t launch_dock(const PocketDev& P, const BatchDev& B, int nmax, const Tiling& t, bool persistent, int lig,
-                       int grid, hipStream_t s);
+// Device copies of the pocket and batch views plus what the host needs to size a launch.
+struct DockLaunch {
+    const PocketDev* P;
+    const BatchDev* B;
+    unsigned long long* counters;
+    int lmax, nmax;
+};
+hipError_t launch_dock(const DockLaunch& L, const Tiling& t, bool persistent, int lig, int grid, hipStream_t s);
 int persistent_grid(const Tiling& t, int lmax, int nmax, int n_items);
 hipError_t launch_reset(int* head, unsigned long long* counters, hipStream_t s);
 hipError_t launch_topk(const BatchDev& B, gd_pose_rec* out, uint16_t* ang_out, double h, hipStream_t s);

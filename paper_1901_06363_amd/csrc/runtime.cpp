@@ -278,6 +278,7 @@ gd_status create_pocket(const gd_pocket_desc* desc, hipStream_t stream, gd_pocke
         D.inv_bh = (float)(1.0 / bh);
         P->blur_h = bh;
     }
+    if ((e = P->devcopy.upload(&P->dev, sizeof(PocketDev), stream)) != hipSuccess) return hip_fail(e, "gd_create_pocket");
     *out = P.release();
     return GD_OK;
 }
@@ -740,6 +741,7 @@ gd_status prepare_batch(const gd_pocket* pocket, const gd_ligands* L, const gd_k
     while (B->tiling.waves_per_block > 1 &&
            dock_lds_bytes(lmax, nmax, B->tiling.waves_per_block) > lds_limit_per_block())
         B->tiling.waves_per_block /= 2;
+    if ((e = B->devcopy.upload(&B->dev, sizeof(BatchDev), stream)) != hipSuccess) return hip_fail(e, "gd_prepare_batch");
     if (const char* env = getenv("GD_TILING")) {
         int w, nb, ppl;
         if (sscanf(env, "%d,%d,%d", &w, &nb, &ppl) == 3) {
@@ -755,18 +757,19 @@ gd_status prepare_batch(const gd_pocket* pocket, const gd_ligands* L, const gd_k
 // The two stages of a docking call: queue reset + docking kernel, then top-k
 // and pose replay.
 static hipError_t enqueue_dock_stage(const gd_pocket* P, gd_batch* B, gd_mode mode, hipStream_t s, int64_t* counters) {
-    BatchDev D = B->dev;
-    if (counters) D.counters = (unsigned long long*)counters;
+    const BatchDev& D = B->dev;
+    DockLaunch L{(const PocketDev*)P->devcopy.ptr, (const BatchDev*)B->devcopy.ptr,
+                 counters ? (unsigned long long*)counters : D.counters, D.lmax, B->nmax};
     hipError_t e;
-    if ((e = launch_reset(D.head, D.counters, s)) != hipSuccess) return e;
+    if ((e = launch_reset(D.head, L.counters, s)) != hipSuccess) return e;
     if (mode == GD_BATCHED) {
         int grid = persistent_grid(B->tiling, D.lmax, B->nmax, D.n_items);
-        return launch_dock(P->dev, D, B->nmax, B->tiling, true, 0, grid, s);
+        return launch_dock(L, B->tiling, true, 0, grid, s);
     }
     const int w = B->tiling.waves_per_block;
     const int grid = (D.n_orient + w - 1) / w;
     for (int i = 0; i < D.n_lig; i++)
-        if ((e = launch_dock(P->dev, D, B->nmax, B->tiling, false, i, grid, s)) != hipSuccess) return e;
+        if ((e = launch_dock(L, B->tiling, false, i, grid, s)) != hipSuccess) return e;
     return hipSuccess;
 }
 

@@ -93,14 +93,14 @@ gd_status pose_layout(const gd_ligands* topo, int32_t n_poses, const int32_t* po
 
 struct gd_pocket {
     gd::PocketDev dev{};
-    gd::DevBuf edt, occ, rho;
+    gd::DevBuf edt, occ, rho, devcopy;
     double centroid[3] = {0, 0, 0};
     double blur_h = 0;
 };
 
 struct gd_batch {
     gd::BatchDev dev{};
-    gd::DevBuf lig, rot, x, y, z, pairs, mv, efar, qmat, items, keys, ang, head, counters;
+    gd::DevBuf lig, rot, x, y, z, pairs, mv, efar, qmat, items, keys, ang, head, counters, devcopy;
     gd_batch_info info{};
     gd::Tiling tiling;
     int nmax = 1;

@@ -55,6 +55,7 @@ class Workload:
     top_k: int = 10
     quat_seed: int = 77
     chunk: int = 0
+    pad: float = 12.0  # distance-grid margin (A): a speed setting, results do not depend on it
     extra: dict = field(default_factory=dict)
 
     def ligands(self, first=0, count=None):
@@ -77,7 +78,7 @@ SINGLE = Workload("single", lig_seed=0, n_ligands=1, lmin=32, lmax=32, bmin=4, b
                   pockets=[(1000, 1000, (8.0, 6.0, 5.0))], n_orient=256, hp=10, top_k=10)
 
 SCREEN = Workload("screen", lig_seed=2, n_ligands=10_000, lmin=20, lmax=80, bmin=2, bmax=12, ring_frac=0.0,
-                  pockets=[(1001, 4000, (12.0, 9.0, 7.0))], n_orient=512, hp=15, top_k=8)
+                  pockets=[(1001, 4000, (12.0, 9.0, 7.0))], n_orient=512, hp=15, top_k=8, pad=20.0)
 
 _GRID_MAJOR = (6.0, 8.0 + 2.0 / 3.0, 11.0 + 1.0 / 3.0, 14.0)
 GRID = Workload("grid", lig_seed=2, n_ligands=100_000, lmin=20, lmax=80, bmin=2, bmax=12, ring_frac=0.0,
@@ -91,7 +92,7 @@ REFINE = Workload("refine", lig_seed=4, n_ligands=4096, lmin=20, lmax=80, bmin=2
                              max_dtau=0.05))
 
 LARGE = Workload("large", lig_seed=5, n_ligands=1_000_000, lmin=15, lmax=120, bmin=0, bmax=16, ring_frac=0.05,
-                 pockets=[(1010, 10_000, (16.0, 12.0, 9.0))], n_orient=1024, hp=10, top_k=8, chunk=65_536)
+                 pockets=[(1010, 10_000, (16.0, 12.0, 9.0))], n_orient=1024, hp=10, top_k=8, chunk=65_536, pad=20.0)
 
 ALL = {w.name: w for w in (SINGLE, SCREEN, GRID, REFINE, LARGE)}
 
