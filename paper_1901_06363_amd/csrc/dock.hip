@@ -62,12 +62,12 @@ __device__ __forceinline__ void rotate_about(double px, double py, double pz, co
 // --------------------------------------------------------------------------
 // per-wave LDS
 
-constexpr int kSurvCap = 512;  // straddling pairs that can still bump in one sweep
+constexpr int kSurvCap = 256;  // straddling pairs that can still bump in one sweep
 
 struct WaveLds {
     double* X;       // [3][lp] FP64 master coordinates (x, y, z planes)
     double* SW;      // [8] FP64 axis k (3) and pivot p (3) of the sweep in progress
-    float* AD;       // [8][lp] per-atom sweep data: u (3), k.u, k x u (3), |u|^2
+    float4* AD;      // [lp][2] per-atom sweep data: (u, k.u), (k x u, |u|^2), u = X - p (A)
     float4* MV;      // [lp][3] moving atoms: P0, U, V in cell units (w unused)
     int* Slo;        // [nmax] lower bound of each candidate's S over the moving atoms
     int* Shi;        // [nmax] upper bound
@@ -76,11 +76,12 @@ struct WaveLds {
     int* red;        // [128] transpose buffer of the score reduction
 };
 
-__host__ __device__ inline int lds_pitch(int lmax) { return (lmax + 3) & ~3; }
+__host__ __device__ inline int lds_pitch(int lmax) { return (lmax + 15) & ~15; }
 __host__ __device__ inline size_t wave_lds_bytes(int lmax, int nmax) {
     int lp = lds_pitch(lmax);
-    size_t b = sizeof(double) * 3 * lp + sizeof(double) * 8 + sizeof(float) * 8 * lp + sizeof(float4) * 3 * lp +
-               sizeof(int) * 2 * nmax + ((nmax + 15) & ~15) + sizeof(uint16_t) * kSurvCap + sizeof(int) * 128;
+    int np = (nmax + 15) & ~15;
+    size_t b = sizeof(double) * 3 * lp + sizeof(double) * 8 + sizeof(float4) * 5 * lp + sizeof(int) * 2 * np + np +
+               sizeof(uint16_t) * kSurvCap + sizeof(int) * 128;
     return (b + 15) & ~(size_t)15;
 }
 __host__ __device__ inline size_t replay_lds_bytes(int lmax) {
@@ -89,16 +90,17 @@ __host__ __device__ inline size_t replay_lds_bytes(int lmax) {
 
 __device__ inline WaveLds carve(char* base, int lmax, int nmax) {
     int lp = lds_pitch(lmax);
+    int np = (nmax + 15) & ~15;
     WaveLds W;
     W.X = (double*)base;
     W.SW = W.X + 3 * lp;
-    W.AD = (float*)(W.SW + 8);
-    W.MV = (float4*)(W.AD + 8 * lp);
+    W.AD = (float4*)(W.SW + 8);
+    W.MV = W.AD + 2 * lp;
     W.Slo = (int*)(W.MV + 3 * lp);
-    W.Shi = W.Slo + nmax;
-    W.st = (uint8_t*)(W.Shi + nmax);
-    W.surv = (uint16_t*)(W.st + ((nmax + 15) & ~15));
-    W.red = (int*)(W.surv + kSurvCap);
+    W.Shi = W.Slo + np;
+    W.red = W.Shi + np;
+    W.surv = (uint16_t*)(W.red + 128);
+    W.st = (uint8_t*)(W.surv + kSurvCap);
     return W;
 }
 
@@ -184,15 +186,6 @@ template <int K>
 __device__ __forceinline__ void bump_block(const Sweep& sw, const WaveLds& W, int q0, int nq, int nw, float cl,
                                            float sl, uint64_t& cert, uint64_t& maybe) {
     const int lane = lane_id();
-    const int lp = sw.lp;
-    const float* ux = W.AD;
-    const float* uy = W.AD + lp;
-    const float* uz = W.AD + 2 * lp;
-    const float* ku = W.AD + 3 * lp;
-    const float* wx = W.AD + 4 * lp;
-    const float* wy = W.AD + 5 * lp;
-    const float* wz = W.AD + 6 * lp;
-    const float* uu = W.AD + 7 * lp;
     float A[K], Bc[K], Cs[K];
 #pragma unroll
     for (int t = 0; t < K; t++) {
@@ -201,10 +194,11 @@ __device__ __forceinline__ void bump_block(const Sweep& sw, const WaveLds& W, in
             uint16_t pr = sw.pruned ? W.surv[q] : sw.pairs[q];
             int li = pr & 0xff, ri = pr >> 8;
             int m = sw.side == 0 ? li : ri, f = sw.side == 0 ? ri : li;
-            float kk = ku[m] * ku[f];
-            float uv = ux[m] * ux[f] + uy[m] * uy[f] + uz[m] * uz[f];
-            float vw = ux[f] * wx[m] + uy[f] * wy[m] + uz[f] * wz[m];
-            A[t] = uu[m] + uu[f] - 2.f * kk;
+            const float4 um = W.AD[2 * m], wm = W.AD[2 * m + 1], uf = W.AD[2 * f], wf = W.AD[2 * f + 1];
+            float kk = um.w * uf.w;
+            float uv = um.x * uf.x + um.y * uf.y + um.z * uf.z;
+            float vw = uf.x * wm.x + uf.y * wm.y + uf.z * wm.z;
+            A[t] = wm.w + wf.w - 2.f * kk;
             Bc[t] = -2.f * (uv - kk);
             Cs[t] = -2.f * vw;
         } else {
@@ -228,8 +222,8 @@ __device__ __forceinline__ void bump_block(const Sweep& sw, const WaveLds& W, in
 // returns the winning position (lowest S among feasible candidates, earliest
 // on ties) or -1 when none is feasible.
 template <int NB, int PPL>
-__device__ int eval_candidates(const PocketDev& P, const BatchDev& B, const Sweep& sw, const WaveLds& W, int base,
-                               int stride, int n, Acc& acc) {
+__device__ int eval_candidates(const PocketDev& P, const BatchDev& B, const Sweep& sw, const WaveLds& W,
+                               const float* trig, int base, int stride, int n, Acc& acc) {
     const int lane = lane_id();
     constexpr int G = kWave / NB;
     acc.poses += n;
@@ -244,7 +238,7 @@ __device__ int eval_candidates(const PocketDev& P, const BatchDev& B, const Swee
         int slo = 0, shi = 0;
         if (k < n) {
             const int deg = base + k * stride;
-            const float c = c_cos32[deg], s = c_sin32[deg];
+            const float c = trig[deg], s = trig[360 + deg];
             int j = g;
             for (; j + 3 * G < sw.m; j += 4 * G) {
                 int idx[4];
@@ -307,8 +301,8 @@ __device__ int eval_candidates(const PocketDev& P, const BatchDev& B, const Swee
         float cl = 0.f, sl = 0.f;
         if (lane < nw) {
             int deg = base + (w0 + lane) * stride;
-            cl = c_cos32[deg];
-            sl = c_sin32[deg];
+            cl = trig[deg];
+            sl = trig[360 + deg];
         }
         uint64_t cert = 0, maybe = 0;
         const int nq = sw.pruned ? sw.nsurv : sw.npairs;
@@ -401,14 +395,9 @@ __device__ __forceinline__ void sweep_setup(const PocketDev& P, const BatchDev& 
         double ux = Xx[i] - px, uy = Xy[i] - py, uz = Xz[i] - pz;
         double ku = kx * ux + ky * uy + kz * uz;
         double uu = ux * ux + uy * uy + uz * uz;
-        W.AD[i] = (float)ux;
-        W.AD[lp + i] = (float)uy;
-        W.AD[2 * lp + i] = (float)uz;
-        W.AD[3 * lp + i] = (float)ku;
-        W.AD[4 * lp + i] = (float)(ky * uz - kz * uy);
-        W.AD[5 * lp + i] = (float)(kz * ux - kx * uz);
-        W.AD[6 * lp + i] = (float)(kx * uy - ky * ux);
-        W.AD[7 * lp + i] = (float)uu;
+        W.AD[2 * i] = make_float4((float)ux, (float)uy, (float)uz, (float)ku);
+        W.AD[2 * i + 1] = make_float4((float)(ky * uz - kz * uy), (float)(kz * ux - kx * uz),
+                                      (float)(kx * uy - ky * ux), (float)uu);
         r2max = fmaxf(r2max, (float)uu);
     }
     float amax = 0.f, umax = 0.f;
@@ -447,14 +436,6 @@ __device__ __forceinline__ void sweep_setup(const PocketDev& P, const BatchDev& 
     wave_sync();
     // Prune: a pair whose smallest distance over a full turn, A - sqrt(B^2 +
     // C^2), clears the bump distance by more than twice the guard never bumps.
-    const float* ux = W.AD;
-    const float* uy = W.AD + lp;
-    const float* uz = W.AD + 2 * lp;
-    const float* kuv = W.AD + 3 * lp;
-    const float* wx = W.AD + 4 * lp;
-    const float* wy = W.AD + 5 * lp;
-    const float* wz = W.AD + 6 * lp;
-    const float* uu = W.AD + 7 * lp;
     const float T = (float)(B.cd2 + 2.0 * gc);
     int nsurv = 0;
     for (int q0 = 0; q0 < sw.npairs; q0 += 4 * kWave) {
@@ -472,10 +453,11 @@ __device__ __forceinline__ void sweep_setup(const PocketDev& P, const BatchDev& 
                 const uint16_t pr = prs[t];
                 int li = pr & 0xff, ri2 = pr >> 8;
                 int m = side == 0 ? li : ri2, f = side == 0 ? ri2 : li;
-                float kk = kuv[m] * kuv[f];
-                float A = uu[m] + uu[f] - 2.f * kk;
-                float Bv = -2.f * (ux[m] * ux[f] + uy[m] * uy[f] + uz[m] * uz[f] - kk);
-                float Cv = -2.f * (ux[f] * wx[m] + uy[f] * wy[m] + uz[f] * wz[m]);
+                const float4 um = W.AD[2 * m], wm = W.AD[2 * m + 1], uf = W.AD[2 * f], wf = W.AD[2 * f + 1];
+                float kk = um.w * uf.w;
+                float A = wm.w + wf.w - 2.f * kk;
+                float Bv = -2.f * (um.x * uf.x + um.y * uf.y + um.z * uf.z - kk);
+                float Cv = -2.f * (uf.x * wm.x + uf.y * wm.y + uf.z * wm.z);
                 float Am = A - T;
                 keep = !(Am > 0.f && Am * Am > 1.0001f * (Bv * Bv + Cv * Cv));
             }
@@ -552,7 +534,8 @@ __device__ __forceinline__ void endpoint(const PocketDev& P, const BatchDev& B, 
 
 // The greedy sweep of one orientation (Alg. 2).
 template <int NB, int PPL>
-__device__ void dock_orientation(const PocketDev& P, const BatchDev& B, int lig, int o, const WaveLds& W, Acc& acc) {
+__device__ void dock_orientation(const PocketDev& P, const BatchDev& B, int lig, int o, const WaveLds& W,
+                                 const float* trig, Acc& acc) {
     const LigMeta L = B.lig[lig];
     place(P, B, L, o, W);
     const int nrec = B.reps * L.nr * 2;
@@ -566,13 +549,13 @@ __device__ void dock_orientation(const PocketDev& P, const BatchDev& B, int lig,
                 int deg;
                 if (ri.mode[side] == kFlat) {
                     const int st = ri.step[side];
-                    int k = eval_candidates<NB, PPL>(P, B, sw, W, 0, st, 360 / st, acc);
+                    int k = eval_candidates<NB, PPL>(P, B, sw, W, trig, 0, st, 360 / st, acc);
                     deg = k < 0 ? 0 : k * st;
                 } else {
                     const int hp = ri.step[side], x = ri.tile[side];
-                    int t = eval_candidates<NB, PPL>(P, B, sw, W, ri.off[side], x, 360 / x, acc);
+                    int t = eval_candidates<NB, PPL>(P, B, sw, W, trig, ri.off[side], x, 360 / x, acc);
                     if (t < 0) t = 0;
-                    int k = eval_candidates<NB, PPL>(P, B, sw, W, t * x, hp, x / hp, acc);
+                    int k = eval_candidates<NB, PPL>(P, B, sw, W, trig, t * x, hp, x / hp, acc);
                     deg = k < 0 ? 0 : t * x + k * hp;
                 }
                 commit(sw.mvl, sw.m, W, sw.lp, deg);
@@ -607,11 +590,17 @@ __global__ void __launch_bounds__(512) dock_ligand_kernel(const PocketDev* __res
     const PocketDev& P = *Pp;
     const BatchDev& B = *Bp;
     extern __shared__ __align__(16) char smem[];
+    __shared__ float trig[720];  // FP32 cos, then sin, of integer degrees
+    for (int d = threadIdx.x; d < 360; d += blockDim.x) {
+        trig[d] = c_cos32[d];
+        trig[360 + d] = c_sin32[d];
+    }
+    __syncthreads();
     const int wave = threadIdx.x / kWave;
     const WaveLds W = carve(smem + wave * wave_lds_bytes(B.lmax, nmax), B.lmax, nmax);
     const int o = uniform(blockIdx.x * (blockDim.x / kWave) + wave);
     Acc acc;
-    if (o < B.n_orient) dock_orientation<NB, PPL>(P, B, lig, o, W, acc);
+    if (o < B.n_orient) dock_orientation<NB, PPL>(P, B, lig, o, W, trig, acc);
     flush(counters, acc);
 }
 
@@ -624,6 +613,12 @@ __global__ void __launch_bounds__(512) dock_persistent_kernel(const PocketDev* _
     const PocketDev& P = *Pp;
     const BatchDev& B = *Bp;
     extern __shared__ __align__(16) char smem[];
+    __shared__ float trig[720];  // FP32 cos, then sin, of integer degrees
+    for (int d = threadIdx.x; d < 360; d += blockDim.x) {
+        trig[d] = c_cos32[d];
+        trig[360 + d] = c_sin32[d];
+    }
+    __syncthreads();
     const int wave = threadIdx.x / kWave;
     const WaveLds W = carve(smem + wave * wave_lds_bytes(B.lmax, nmax), B.lmax, nmax);
     Acc acc;
@@ -634,7 +629,7 @@ __global__ void __launch_bounds__(512) dock_persistent_kernel(const PocketDev* _
         if (item >= B.n_items) break;
         const int lig = uniform(B.items[2 * item]), o0 = uniform(B.items[2 * item + 1]);
         const int o1 = min(o0 + B.orient_per_item, B.n_orient);
-        for (int o = o0; o < o1; o++) dock_orientation<NB, PPL>(P, B, lig, o, W, acc);
+        for (int o = o0; o < o1; o++) dock_orientation<NB, PPL>(P, B, lig, o, W, trig, acc);
     }
     flush(counters, acc);
 }
