@@ -63,6 +63,8 @@ def main():
     ap.add_argument("--tiling", type=str, default="")
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--n-ligands", type=int, default=0, help="override the ligand count (testing only)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (the reference kernel for HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -77,6 +79,17 @@ def main():
     from synth import configs
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        # One elementwise kernel that reads and writes exactly n bytes each; the
+        # counters it produces convert FETCH_SIZE / WRITE_SIZE readings into bytes.
+        n = args.copy_calibration << 20
+        a = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        torch.neg(a, out=b)
+        torch.cuda.synchronize()
+        log("copy calibration: read %d B, wrote %d B" % (n, n))
+        return
     w = configs.SCREEN
     n_lig = args.n_ligands or w.n_ligands
     t = time.perf_counter()

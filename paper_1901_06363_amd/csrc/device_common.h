@@ -75,6 +75,15 @@ __device__ __forceinline__ double uniform_d(double v) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
+// Load through a global-address-space pointer.  Pointers read out of the
+// device descriptors are generic to the compiler, and generic (flat) loads
+// also hold the LDS wait counter, so every LDS access after a gather would
+// wait for the gather; the cast gives plain global loads.
+template <class T>
+__device__ __forceinline__ T ldg(const T* p) {
+    return *(const __attribute__((address_space(1))) T*)p;
+}
+
 // --------------------------------------------------------------------------
 // exact distance field lookups
 
@@ -82,7 +91,7 @@ __device__ __forceinline__ double uniform_d(double v) {
 static __device__ int D_brute(const PocketDev& P, int cx, int cy, int cz) {
     int best = 0x7fffffff;
     for (int i = 0; i < P.n_occ; i++) {
-        int dx = cx - P.occ[3 * i], dy = cy - P.occ[3 * i + 1], dz = cz - P.occ[3 * i + 2];
+        int dx = cx - ldg(P.occ + 3 * i), dy = cy - ldg(P.occ + 3 * i + 1), dz = cz - ldg(P.occ + 3 * i + 2);
         int d = dx * dx + dy * dy + dz * dz;
         best = d < best ? d : best;
     }
@@ -92,7 +101,7 @@ static __device__ int D_brute(const PocketDev& P, int cx, int cy, int cz) {
 // D of a box-relative cell; outside the box falls back to brute force.
 __device__ __forceinline__ int D_box(const PocketDev& P, int ix, int iy, int iz, int& oob) {
     if ((unsigned)ix < (unsigned)P.dim[0] && (unsigned)iy < (unsigned)P.dim[1] && (unsigned)iz < (unsigned)P.dim[2])
-        return P.edt[((size_t)iz * P.dim[1] + iy) * P.dim[0] + ix];
+        return ldg(P.edt + ((size_t)iz * P.dim[1] + iy) * P.dim[0] + ix);
     oob++;
     return D_brute(P, ix + P.lo[0], iy + P.lo[1], iz + P.lo[2]);
 }

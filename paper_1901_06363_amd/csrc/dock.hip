@@ -124,60 +124,69 @@ struct Sweep {
 // FP64 evaluation of one candidate of the current sweep: S over the moving
 // atoms and feasibility over the straddling far pairs.
 
-__device__ __noinline__ bool eval_fp64(const PocketDev& P, const BatchDev& B, const Sweep& sw, const WaveLds& W,
-                                       int deg, int& S_out, Acc& acc) {
+// Kept out of line (it runs for a small fraction of candidates); every
+// argument is a value or a pointer so that nothing of the caller's state has
+// to live in scratch memory.  Returns S in the low 32 bits, feasibility in
+// bit 32 and this lane's count of out-of-box lookups from bit 40.
+__device__ __noinline__ uint64_t eval_fp64(const PocketDev* Pp, const double* X, const double* SWp, int lp,
+                                           const uint8_t* mvl, int m, const uint16_t* pairs, int npairs, int side,
+                                           double cd2, int deg) {
+    const PocketDev& P = *Pp;
     const int lane = lane_id();
-    const double kx = uniform_d(W.SW[0]), ky = uniform_d(W.SW[1]), kz = uniform_d(W.SW[2]);
-    const double px = uniform_d(W.SW[3]), py = uniform_d(W.SW[4]), pz = uniform_d(W.SW[5]);
+    const double kx = uniform_d(SWp[0]), ky = uniform_d(SWp[1]), kz = uniform_d(SWp[2]);
+    const double px = uniform_d(SWp[3]), py = uniform_d(SWp[4]), pz = uniform_d(SWp[5]);
     const Mat3 R = axis_angle(kx, ky, kz, deg);
-    const double* Xx = W.X;
-    const double* Xy = W.X + sw.lp;
-    const double* Xz = W.X + 2 * sw.lp;
-    int S = 0;
-    for (int j = lane; j < sw.m; j += kWave) {
-        int i = sw.mvl[j];
+    const double* Xx = X;
+    const double* Xy = X + lp;
+    const double* Xz = X + 2 * lp;
+    int S = 0, oob = 0;
+    for (int j = lane; j < m; j += kWave) {
+        int i = ldg(mvl + j);
         double yx, yy, yz;
         rotate_about(px, py, pz, R, Xx[i], Xy[i], Xz[i], yx, yy, yz);
-        S += D_exact(P, yx, yy, yz, acc.oob);
+        S += D_exact(P, yx, yy, yz, oob);
     }
     S = wave_sum(S);
     bool clash = false;
-    for (int q = lane; q < sw.npairs; q += kWave) {
-        uint16_t pr = sw.pairs[q];
+    for (int q = lane; q < npairs; q += kWave) {
+        uint16_t pr = ldg(pairs + q);
         int li = pr & 0xff, ri = pr >> 8;
-        int mv = sw.side == 0 ? li : ri, fx = sw.side == 0 ? ri : li;
+        int mv = side == 0 ? li : ri, fx = side == 0 ? ri : li;
         double yx, yy, yz;
         rotate_about(px, py, pz, R, Xx[mv], Xy[mv], Xz[mv], yx, yy, yz);
-        clash |= dist2(yx, yy, yz, Xx[fx], Xy[fx], Xz[fx]) < B.cd2;
+        clash |= dist2(yx, yy, yz, Xx[fx], Xy[fx], Xz[fx]) < cd2;
     }
     clash = __ballot(clash) != 0;
-    S_out = S;
-    acc.fallback++;
-    return !clash;
+    return (uint64_t)(uint32_t)S | ((uint64_t)(!clash) << 32) | ((uint64_t)(uint32_t)oob << 40);
 }
 
-// FP32 contribution of one candidate atom.  An atom within the guard of a
-// cell face, or outside the tabulated grid, widens the candidate's S range to
-// [S of the other atoms, unbounded]; such a candidate is re-evaluated in FP64
-// if it can still win its sweep.
+// FP32 cell of one candidate atom.  An atom within the guard of a cell face,
+// or outside the tabulated grid, widens the candidate's S range to [S of the
+// other atoms, unbounded]; such a candidate is re-evaluated in FP64 if it can
+// still win its sweep.  Branch-free: an uncertain atom reads cell 0 and
+// discards it, so the per-lane sums stay in registers.
 constexpr int kOpenHi = 0x20000000;
 
-__device__ __forceinline__ void atom_cell_score(const PocketDev& P, float yx, float yy, float yz, float lim, int& slo,
-                                                int& shi, int& oob) {
+struct CellRef {
+    int idx;  // linear cell index, 0 when not certain
+    bool ok;  // certain cell inside the grid
+    bool in;  // inside the grid
+};
+
+__device__ __forceinline__ CellRef cell_ref(float yx, float yy, float yz, float lim, int nx, int ny, int nz) {
     const float fx = floorf(yx), fy = floorf(yy), fz = floorf(yz);
     const int ix = (int)fx, iy = (int)fy, iz = (int)fz;
-    const bool sure = fabsf(yx - fx - 0.5f) <= lim && fabsf(yy - fy - 0.5f) <= lim && fabsf(yz - fz - 0.5f) <= lim &&
-                      (unsigned)ix < (unsigned)P.dim[0] && (unsigned)iy < (unsigned)P.dim[1] &&
-                      (unsigned)iz < (unsigned)P.dim[2];
-    if (sure) {
-        const int d = P.edt[(iz * P.dim[1] + iy) * P.dim[0] + ix];
-        slo += d;
-        shi += d;
-    } else {
-        shi = kOpenHi;
-        oob += !((unsigned)ix < (unsigned)P.dim[0] && (unsigned)iy < (unsigned)P.dim[1] &&
-                 (unsigned)iz < (unsigned)P.dim[2]);
-    }
+    CellRef r;
+    r.in = (unsigned)ix < (unsigned)nx && (unsigned)iy < (unsigned)ny && (unsigned)iz < (unsigned)nz;
+    r.ok = r.in && fabsf(yx - fx - 0.5f) <= lim && fabsf(yy - fy - 0.5f) <= lim && fabsf(yz - fz - 0.5f) <= lim;
+    r.idx = r.ok ? (iz * ny + iy) * nx + ix : 0;
+    return r;
+}
+
+__device__ __forceinline__ void cell_acc(const CellRef& r, int d, int& slo, int& shi, int& oob) {
+    slo += r.ok ? d : 0;
+    shi = r.ok ? shi + d : kOpenHi;
+    oob += r.in ? 0 : 1;
 }
 
 // K pairs per lane starting at q0: FP32 A, B, C from the per-atom data, then
@@ -191,7 +200,7 @@ __device__ __forceinline__ void bump_block(const Sweep& sw, const WaveLds& W, in
     for (int t = 0; t < K; t++) {
         const int q = q0 + t * kWave + lane;
         if (q < nq) {
-            uint16_t pr = sw.pruned ? W.surv[q] : sw.pairs[q];
+            uint16_t pr = sw.pruned ? W.surv[q] : ldg(sw.pairs + q);
             int li = pr & 0xff, ri = pr >> 8;
             int m = sw.side == 0 ? li : ri, f = sw.side == 0 ? ri : li;
             const float4 um = W.AD[2 * m], wm = W.AD[2 * m + 1], uf = W.AD[2 * f], wf = W.AD[2 * f + 1];
@@ -241,40 +250,25 @@ __device__ int eval_candidates(const PocketDev& P, const BatchDev& B, const Swee
             const float c = trig[deg], s = trig[360 + deg];
             int j = g;
             for (; j + 3 * G < sw.m; j += 4 * G) {
-                int idx[4];
-                bool fast = true;
+                CellRef r[4];
 #pragma unroll
                 for (int t = 0; t < 4; t++) {
                     const int jj = j + t * G;
                     const float4 p0 = W.MV[3 * jj], u = W.MV[3 * jj + 1], v = W.MV[3 * jj + 2];
-                    const float yx = fmaf(s, v.x, fmaf(c, u.x, p0.x));
-                    const float yy = fmaf(s, v.y, fmaf(c, u.y, p0.y));
-                    const float yz = fmaf(s, v.z, fmaf(c, u.z, p0.z));
-                    const float fx = floorf(yx), fy = floorf(yy), fz = floorf(yz);
-                    const int ix = (int)fx, iy = (int)fy, iz = (int)fz;
-                    fast &= fabsf(yx - fx - 0.5f) <= lim && fabsf(yy - fy - 0.5f) <= lim &&
-                            fabsf(yz - fz - 0.5f) <= lim && (unsigned)ix < (unsigned)nx &&
-                            (unsigned)iy < (unsigned)ny && (unsigned)iz < (unsigned)nz;
-                    idx[t] = (iz * ny + iy) * nx + ix;
+                    r[t] = cell_ref(fmaf(s, v.x, fmaf(c, u.x, p0.x)), fmaf(s, v.y, fmaf(c, u.y, p0.y)),
+                                    fmaf(s, v.z, fmaf(c, u.z, p0.z)), lim, nx, ny, nz);
                 }
-                if (fast) {
-                    const int d = (int)P.edt[idx[0]] + (int)P.edt[idx[1]] + (int)P.edt[idx[2]] + (int)P.edt[idx[3]];
-                    slo += d;
-                    shi += d;
-                } else {
+                int d[4];
 #pragma unroll
-                    for (int t = 0; t < 4; t++) {
-                        const int jj = j + t * G;
-                        const float4 p0 = W.MV[3 * jj], u = W.MV[3 * jj + 1], v = W.MV[3 * jj + 2];
-                        atom_cell_score(P, fmaf(s, v.x, fmaf(c, u.x, p0.x)), fmaf(s, v.y, fmaf(c, u.y, p0.y)),
-                                        fmaf(s, v.z, fmaf(c, u.z, p0.z)), lim, slo, shi, acc.oob);
-                    }
-                }
+                for (int t = 0; t < 4; t++) d[t] = ldg(P.edt + r[t].idx);
+#pragma unroll
+                for (int t = 0; t < 4; t++) cell_acc(r[t], d[t], slo, shi, acc.oob);
             }
             for (; j < sw.m; j += G) {
                 const float4 p0 = W.MV[3 * j], u = W.MV[3 * j + 1], v = W.MV[3 * j + 2];
-                atom_cell_score(P, fmaf(s, v.x, fmaf(c, u.x, p0.x)), fmaf(s, v.y, fmaf(c, u.y, p0.y)),
-                                fmaf(s, v.z, fmaf(c, u.z, p0.z)), lim, slo, shi, acc.oob);
+                const CellRef r = cell_ref(fmaf(s, v.x, fmaf(c, u.x, p0.x)), fmaf(s, v.y, fmaf(c, u.y, p0.y)),
+                                           fmaf(s, v.z, fmaf(c, u.z, p0.z)), lim, nx, ny, nz);
+                cell_acc(r, ldg(P.edt + r.idx), slo, shi, acc.oob);
             }
         }
         // sum the groups of each angle through LDS
@@ -341,8 +335,12 @@ __device__ int eval_candidates(const PocketDev& P, const BatchDev& B, const Swee
             const int bit = __builtin_ctzll(mask);
             mask &= mask - 1;
             const int kk = k0 + bit;
-            int S;
-            if (eval_fp64(P, B, sw, W, base + kk * stride, S, acc)) {
+            const uint64_t r = eval_fp64(&P, W.X, W.SW, sw.lp, sw.mvl, sw.m, sw.pairs, sw.npairs, sw.side, B.cd2,
+                                         base + kk * stride);
+            acc.fallback++;
+            acc.oob += (int)(r >> 40);
+            if ((r >> 32) & 1) {
+                const int S = (int)(uint32_t)r;
                 uint64_t key = ((uint64_t)(uint32_t)S << 16) | (uint64_t)kk;
                 best = key < best ? key : best;
             }
@@ -373,8 +371,30 @@ __device__ __forceinline__ void sweep_axis(const WaveLds& W, int lp, int a, int 
 
 // Prepare one fragment sweep: axis and pivot, per-atom pair data, FP32
 // moving-atom coefficients, the rounding guards, and the pair prune.
+// One side of a rotamer, read field by field so that no copy of the record
+// is indexed by the side number (which would place it in scratch memory).
+struct SideInfo {
+    int a, c, piv, pair_off, n_pairs, mv_off, n_mv, mode, step, tile, off;
+};
+
+__device__ __forceinline__ SideInfo side_info(const RotInfo* rp, int side) {
+    SideInfo si;
+    si.a = ldg(&rp->a);
+    si.c = ldg(&rp->c);
+    si.piv = side == 0 ? si.a : si.c;
+    si.pair_off = ldg(&rp->pair_off);
+    si.n_pairs = ldg(&rp->n_pairs);
+    si.mv_off = ldg(rp->mv_off + side);
+    si.n_mv = ldg(rp->n_mv + side);
+    si.mode = ldg(rp->mode + side);
+    si.step = ldg(rp->step + side);
+    si.tile = ldg(rp->tile + side);
+    si.off = ldg(rp->off + side);
+    return si;
+}
+
 __device__ __forceinline__ void sweep_setup(const PocketDev& P, const BatchDev& B, const LigMeta& L,
-                                         const RotInfo& ri, int side, const WaveLds& W, Sweep& sw) {
+                                         const SideInfo& ri, int side, const WaveLds& W, Sweep& sw) {
     const int lane = lane_id();
     const int lp = lds_pitch(B.lmax);
     const double* Xx = W.X;
@@ -382,11 +402,11 @@ __device__ __forceinline__ void sweep_setup(const PocketDev& P, const BatchDev& 
     const double* Xz = W.X + 2 * lp;
     sw.lp = lp;
     sw.side = side;
-    sw.mvl = B.mv + ri.mv_off[side];
-    sw.m = ri.n_mv[side];
+    sw.mvl = B.mv + ri.mv_off;
+    sw.m = ri.n_mv;
     sw.pairs = B.pairs + ri.pair_off;
     sw.npairs = ri.n_pairs;
-    sweep_axis(W, lp, ri.a, ri.c, side == 0 ? ri.a : ri.c);
+    sweep_axis(W, lp, ri.a, ri.c, ri.piv);
     const double kx = uniform_d(W.SW[0]), ky = uniform_d(W.SW[1]), kz = uniform_d(W.SW[2]);
     const double px = uniform_d(W.SW[3]), py = uniform_d(W.SW[4]), pz = uniform_d(W.SW[5]);
 
@@ -403,7 +423,7 @@ __device__ __forceinline__ void sweep_setup(const PocketDev& P, const BatchDev& 
     float amax = 0.f, umax = 0.f;
     const double ih = P.inv_h;
     for (int j = lane; j < sw.m; j += kWave) {
-        int i = sw.mvl[j];
+        int i = ldg(sw.mvl + j);
         double ux = Xx[i] - px, uy = Xy[i] - py, uz = Xz[i] - pz;
         double ku = kx * ux + ky * uy + kz * uz;
         double ax0 = (px + ku * kx) * ih - (double)P.lo[0];
@@ -443,7 +463,7 @@ __device__ __forceinline__ void sweep_setup(const PocketDev& P, const BatchDev& 
 #pragma unroll
         for (int t = 0; t < 4; t++) {
             const int q = q0 + t * kWave + lane;
-            prs[t] = q < sw.npairs ? sw.pairs[q] : (uint16_t)0;
+            prs[t] = q < sw.npairs ? ldg(sw.pairs + q) : (uint16_t)0;
         }
 #pragma unroll
         for (int t = 0; t < 4; t++) {
@@ -500,9 +520,9 @@ __device__ void place(const PocketDev& P, const BatchDev& B, const LigMeta& L, i
     const int lp = lds_pitch(B.lmax);
     const double* R = B.qmat + 9 * (size_t)o;
     for (int i = lane; i < L.l; i += kWave) {
-        double d0 = (double)B.x[L.atom_off + i] - L.cL[0];
-        double d1 = (double)B.y[L.atom_off + i] - L.cL[1];
-        double d2 = (double)B.z[L.atom_off + i] - L.cL[2];
+        double d0 = (double)ldg(B.x + L.atom_off + i) - L.cL[0];
+        double d1 = (double)ldg(B.y + L.atom_off + i) - L.cL[1];
+        double d2 = (double)ldg(B.z + L.atom_off + i) - L.cL[2];
         W.X[i] = (R[0] * d0 + R[1] * d1 + R[2] * d2) + P.cP[0];
         W.X[lp + i] = (R[3] * d0 + R[4] * d1 + R[5] * d2) + P.cP[1];
         W.X[2 * lp + i] = (R[6] * d0 + R[7] * d1 + R[8] * d2) + P.cP[2];
@@ -542,18 +562,19 @@ __device__ void dock_orientation(const PocketDev& P, const BatchDev& B, int lig,
     uint16_t* ang = B.ang + L.ang_off + (size_t)o * nrec;
     for (int rep = 0; rep < B.reps; rep++) {
         for (int r = 0; r < L.nr; r++) {
-            const RotInfo ri = B.rot[L.rot_off + r];
+            const RotInfo* rp = B.rot + L.rot_off + r;
             for (int side = 0; side < 2; side++) {
+                const SideInfo ri = side_info(rp, side);
                 Sweep sw;
                 sweep_setup(P, B, L, ri, side, W, sw);
                 int deg;
-                if (ri.mode[side] == kFlat) {
-                    const int st = ri.step[side];
+                if (ri.mode == kFlat) {
+                    const int st = ri.step;
                     int k = eval_candidates<NB, PPL>(P, B, sw, W, trig, 0, st, 360 / st, acc);
                     deg = k < 0 ? 0 : k * st;
                 } else {
-                    const int hp = ri.step[side], x = ri.tile[side];
-                    int t = eval_candidates<NB, PPL>(P, B, sw, W, trig, ri.off[side], x, 360 / x, acc);
+                    const int hp = ri.step, x = ri.tile;
+                    int t = eval_candidates<NB, PPL>(P, B, sw, W, trig, ri.off, x, 360 / x, acc);
                     if (t < 0) t = 0;
                     int k = eval_candidates<NB, PPL>(P, B, sw, W, trig, t * x, hp, x / hp, acc);
                     deg = k < 0 ? 0 : t * x + k * hp;
@@ -713,10 +734,11 @@ __global__ void __launch_bounds__(256) replay_kernel(PocketDev P, BatchDev B, co
     const uint16_t* ang = B.ang + L.ang_off + (size_t)o * nrec;
     for (int rep = 0; rep < B.reps; rep++)
         for (int r = 0; r < L.nr; r++) {
-            const RotInfo ri = B.rot[L.rot_off + r];
+            const RotInfo* rp = B.rot + L.rot_off + r;
             for (int side = 0; side < 2; side++) {
-                sweep_axis(W, lp, ri.a, ri.c, side == 0 ? ri.a : ri.c);
-                commit(B.mv + ri.mv_off[side], ri.n_mv[side], W, lp, ang[(rep * L.nr + r) * 2 + side]);
+                const SideInfo ri = side_info(rp, side);
+                sweep_axis(W, lp, ri.a, ri.c, ri.piv);
+                commit(B.mv + ri.mv_off, ri.n_mv, W, lp, ang[(rep * L.nr + r) * 2 + side]);
             }
         }
     float* dst = xyz + (size_t)idx * B.lmax * 3;
