@@ -52,6 +52,49 @@ def cpu_baseline(w, ligs, q, n_sample):
                        % (n_sample, len(q), poses, dt))
 
 
+def refine_leg(gd, torch, np, n_lig):
+    """The refinement workload: top-64 docked poses of n_lig ligands, 50 ascent
+    steps on the blurred-density surrogate, exact rescoring and acceptance."""
+    from synth import configs
+    w = configs.REFINE
+    e = w.extra
+    ligs = w.ligands(0, n_lig)
+    P = gd.Pocket(w.pocket_points(), 0.5, w.pad, blur_sigma=e["blur_sigma"], blur_h=e["blur_h"])
+    B = gd.Batch(P, ligs, w.quaternions(), hp=w.hp, top_k=w.top_k)
+    r = B.dock(gd.BATCHED)
+    k, lmax = w.top_k, r.xyz.shape[2]
+    nat = np.diff(ligs.atom_off).astype(np.int64)
+    pose_lig = np.repeat(np.arange(n_lig), k)
+    pa = nat[pose_lig]
+    first = np.concatenate([[0], np.cumsum(pa)[:-1]])
+    idx = np.repeat(np.arange(len(pose_lig)) * lmax - first, pa) + np.arange(pa.sum())
+    X = r.xyz.reshape(-1, 3).index_select(0, torch.from_numpy(idx).cuda())
+    kw = dict(steps=e["steps"], lr_t=e["lr_t"], lr_q=e["lr_q"], lr_tau=e["lr_tau"], max_dt=e["max_dt"],
+              max_dtau=e["max_dtau"])
+    # warm-up on a slice, then the timed call over every pose
+    m = min(len(pose_lig), 4096)
+    n_warm = int(pa[:m].sum())
+    gd.refine(P, ligs, pose_lig[:m], X[:n_warm, 0].contiguous(), X[:n_warm, 1].contiguous(),
+              X[:n_warm, 2].contiguous(), **kw)
+    px, py, pz = (X[:, a].contiguous() for a in range(3))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = gd.refine(P, ligs, pose_lig, px, py, pz, time_kernel=True, **kw)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kms = out["kernel_ms"]
+    atoms = int(pa.sum())
+    passes = e["steps"] + 1
+    gather_bytes = atoms * passes * 8 * 4  # 8 trilinear corners of 4 B per atom per pass
+    return dict(workload="refine: %d ligands x top-%d poses (%d poses, %d atoms), %d ascent steps, sigma %.2f A on a "
+                         "%.3f A lattice" % (n_lig, k, len(pose_lig), atoms, e["steps"], e["blur_sigma"], e["blur_h"]),
+                poses=len(pose_lig), steps=e["steps"], kernel="refine_kernel", kernel_ms=kms,
+                pose_steps_per_s=len(pose_lig) * e["steps"] / (kms * 1e-3),
+                refined_poses_per_s_end_to_end=len(pose_lig) / wall,
+                accepted=int(out["accepted"].sum().item()),
+                gather_GBps=gather_bytes / (kms * 1e-3) / 1e9)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -62,6 +105,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=48)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-ligand", action="store_true")
+    ap.add_argument("--no-refine", action="store_true")
+    ap.add_argument("--refine-ligands", type=int, default=4096)
     ap.add_argument("--tiling", type=str, default="")
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--n-ligands", type=int, default=0, help="override the ligand count (testing only)")
@@ -166,6 +211,11 @@ def main():
         log("per-ligand launches:", per_lig)
         del rp, hp_
 
+    ref = None
+    if not args.no_refine and args.refine_ligands > 0:
+        ref = refine_leg(gd, torch, np, args.refine_ligands)
+        log("refinement:", ref)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, ligs, q, min(args.cpu_sample, n_lig))
@@ -203,6 +253,7 @@ def main():
         "prep_s": prep_s,
         "end_to_end_poses_per_s_incl_prep": B.poses_expected / (prep_s + dt / args.steps),
         "per_ligand": per_lig,
+        "refine": ref,
         "roofline": {
             "bound": "alu",
             "achieved": achieved,

@@ -272,6 +272,9 @@ typedef struct {
     float lr_tau;       /* torsion step (radians per unit gradient)               */
     float max_dt;       /* cap on |delta t| per step (A)                          */
     float max_dtau;     /* cap on |delta tau_b| per step (radians)                */
+    float* kernel_ms;   /* host, may be NULL: when set, gd_refine times the ascent
+                           kernel with HIP events on `stream`, waits for it and
+                           stores its duration (ms) here                          */
 } gd_refine_opts;
 
 gd_status gd_surrogate_fwd(const gd_pocket* pocket, const gd_ligands* topo, int32_t n_poses, const int32_t* pose_lig,

@@ -85,14 +85,18 @@ def surrogate_bwd(pocket, ligands, pose_lig, px, py, pz, t, q, tau, dF, stream=N
 
 
 def refine(pocket, ligands, pose_lig, px, py, pz, steps=50, lr_t=0.002, lr_q=1e-5, lr_tau=5e-4, max_dt=0.1,
-           max_dtau=0.05, clash_dist=2.0, clash_min_bonds=4, stream=None, want_iterate=False):
+           max_dtau=0.05, clash_dist=2.0, clash_min_bonds=4, stream=None, want_iterate=False, time_kernel=False):
     """Gradient ascent on the surrogate, then exact rescoring; px/py/pz are
-    overwritten with the refined pose where it is accepted."""
+    overwritten with the refined pose where it is accepted.  With time_kernel
+    the call waits for the ascent kernel and returns its duration (ms) as
+    out["kernel_ms"]."""
     torch = _torch()
     lg = _lig_desc(ligands)
     pl = np.ascontiguousarray(pose_lig, dtype=np.int32)
     n = len(pl)
-    opts = _abi.RefineOpts(int(steps), float(lr_t), float(lr_q), float(lr_tau), float(max_dt), float(max_dtau))
+    kms = ctypes.c_float(0.0)
+    opts = _abi.RefineOpts(int(steps), float(lr_t), float(lr_q), float(lr_tau), float(max_dt), float(max_dtau),
+                           ctypes.pointer(kms) if time_kernel else None)
     F = torch.empty(n, dtype=torch.float32, device="cuda")
     S = torch.empty(n, dtype=torch.int32, device="cuda")
     clash = torch.empty(n, dtype=torch.uint8, device="cuda")
@@ -103,6 +107,8 @@ def refine(pocket, ligands, pose_lig, px, py, pz, steps=50, lr_t=0.002, lr_q=1e-
                                      int(clash_min_bonds), _stream_ptr(stream), _dp(F), _dp(S), _dp(clash), _dp(acc),
                                      _dp(it[0]), _dp(it[1]), _dp(it[2])))
     out = dict(F=F, S=S, clash=clash, accepted=acc)
+    if time_kernel:
+        out["kernel_ms"] = kms.value
     if want_iterate:
         out["iterate"] = it
     return out

@@ -150,8 +150,9 @@ __device__ void pose_forward(const TreeDev& T, const PoseState& S, const float* 
     }
 }
 
-// F and (optionally) dF/d(t, q, tau) at the given parameters.  gtau is indexed
-// by rotamer (list order); only lane-uniform values are returned.
+// F and (optionally) dF/d(t, q, tau) at the given parameters.  tau and gtau
+// are this wave's LDS arrays indexed by rotamer (list order); only
+// lane-uniform values are returned.
 template <bool GRAD>
 __device__ float surrogate_eval(const PocketDev& P, const TreeDev& T, const PoseState& S, const float* t,
                                 const float* q, const float* tau, float* lds, float* gt, float* gq, float* gtau,
@@ -240,7 +241,7 @@ __device__ float surrogate_eval(const PocketDev& P, const TreeDev& T, const Pose
         float tx = sxg[0] - (ay * sg[2] - az * sg[1]);
         float ty = sxg[1] - (az * sg[0] - ax * sg[2]);
         float tz = sxg[2] - (ax * sg[1] - ay * sg[0]);
-        gtau[te.z] = (kx * tx + ky * ty + kz * tz) * inv;
+        if (lane == 0) gtau[te.z] = (kx * tx + ky * ty + kz * tz) * inv;
     }
     wave_sync();
     return F;
@@ -253,30 +254,38 @@ __global__ void __launch_bounds__(256) surrogate_kernel(PocketDev P, TreeDev T, 
                                                         int tau_stride, const float* dF, float* F_out, float* dt_out,
                                                         float* dq_out, float* dtau_out) {
     __shared__ float lds_all[4][3 * kMaxAtoms];
+    __shared__ float tau_all[4][kMaxRot], gtau_all[4][kMaxRot];
     const int wave = threadIdx.x / kWave;
     const int pose = blockIdx.x * 4 + wave;
     if (pose >= n_poses) return;
+    const int lane = lane_id();
     float* lds = lds_all[wave];
+    float* tau_l = tau_all[wave];
+    float* gtau = gtau_all[wave];
     PoseState S;
     load_pose(T, X, pose, S);
     const float* tp = t + 3 * (size_t)pose;
     const float* qp = q + 4 * (size_t)pose;
-    const float* taup = tau + (size_t)tau_stride * pose;
+    for (int r = lane; r < kMaxRot; r += kWave) {
+        tau_l[r] = r < S.nr ? tau[(size_t)tau_stride * pose + r] : 0.f;
+        gtau[r] = 0.f;
+    }
+    wave_sync();
     if (!dF) {
-        float F = surrogate_eval<false>(P, T, S, tp, qp, taup, lds, nullptr, nullptr, nullptr, nullptr);
-        if (lane_id() == 0) F_out[pose] = F;
+        float F = surrogate_eval<false>(P, T, S, tp, qp, tau_l, lds, nullptr, nullptr, nullptr, nullptr);
+        if (lane == 0) F_out[pose] = F;
         return;
     }
-    float gt[3], gq[4], gtau[kMaxRot];
-    for (int r = 0; r < kMaxRot; r++) gtau[r] = 0.f;
-    float F = surrogate_eval<true>(P, T, S, tp, qp, taup, lds, gt, gq, gtau, nullptr);
+    float gt[3], gq[4];
+    float F = surrogate_eval<true>(P, T, S, tp, qp, tau_l, lds, gt, gq, gtau, nullptr);
     const float up = dF[pose];
-    if (lane_id() == 0) {
+    if (lane == 0) {
         if (F_out) F_out[pose] = F;
         for (int a = 0; a < 3; a++) dt_out[3 * (size_t)pose + a] = up * gt[a];
         for (int a = 0; a < 4; a++) dq_out[4 * (size_t)pose + a] = up * gq[a];
-        for (int r = 0; r < tau_stride; r++) dtau_out[(size_t)tau_stride * pose + r] = r < S.nr ? up * gtau[r] : 0.f;
     }
+    for (int r = lane; r < tau_stride; r += kWave)
+        dtau_out[(size_t)tau_stride * pose + r] = r < S.nr ? up * gtau[r] : 0.f;
 }
 
 // The whole ascent of one pose in one wavefront: parameters stay in
@@ -284,15 +293,20 @@ __global__ void __launch_bounds__(256) surrogate_kernel(PocketDev P, TreeDev T, 
 __global__ void __launch_bounds__(256) refine_kernel(PocketDev P, TreeDev T, PoseDev X, int n_poses, RefineParams rp,
                                                      float* rx, float* ry, float* rz, float* F_out) {
     __shared__ float lds_all[4][3 * kMaxAtoms];
+    __shared__ float tau_all[4][kMaxRot], gtau_all[4][kMaxRot];
     const int wave = threadIdx.x / kWave;
     const int pose = blockIdx.x * 4 + wave;
     if (pose >= n_poses) return;
+    const int lane = lane_id();
     float* lds = lds_all[wave];
+    float* tau = tau_all[wave];
+    float* gtau = gtau_all[wave];
     PoseState S;
     load_pose(T, X, pose, S);
-    float t[3] = {0.f, 0.f, 0.f}, q[4] = {1.f, 0.f, 0.f, 0.f}, tau[kMaxRot];
-    float gt[3], gq[4], gtau[kMaxRot];
-    for (int r = 0; r < kMaxRot; r++) tau[r] = gtau[r] = 0.f;
+    float t[3] = {0.f, 0.f, 0.f}, q[4] = {1.f, 0.f, 0.f, 0.f};
+    float gt[3], gq[4];
+    for (int r = lane; r < kMaxRot; r += kWave) tau[r] = gtau[r] = 0.f;
+    wave_sync();
     for (int s = 0; s < rp.steps; s++) {
         surrogate_eval<true>(P, T, S, t, q, tau, lds, gt, gq, gtau, nullptr);
         float dt[3] = {rp.lr_t * gt[0], rp.lr_t * gt[1], rp.lr_t * gt[2]};
@@ -306,7 +320,9 @@ __global__ void __launch_bounds__(256) refine_kernel(PocketDev P, TreeDev T, Pos
         }
         qn = sqrtf(qn);
         for (int a = 0; a < 4; a++) q[a] /= qn;
-        for (int r = 0; r < S.nr; r++) tau[r] += fminf(fmaxf(rp.lr_tau * gtau[r], -rp.max_dtau), rp.max_dtau);
+        for (int r = lane; r < S.nr; r += kWave)
+            tau[r] += fminf(fmaxf(rp.lr_tau * gtau[r], -rp.max_dtau), rp.max_dtau);
+        wave_sync();
     }
     float Xf[kSlots][3];
     float F = surrogate_eval<false>(P, T, S, t, q, tau, lds, nullptr, nullptr, nullptr, Xf);

@@ -108,9 +108,19 @@ gd_status refine(const gd_pocket* P, const gd_ligands* topo, int32_t n_poses, co
     if ((e = launch_score(P->dev, SD, n_poses, cd * cd, (int32_t*)S_in, (uint8_t*)c_in, s)) != hipSuccess)
         return hip_fail(e, who);
     RefineParams rp{o->steps, o->lr_t, o->lr_q, o->lr_tau, o->max_dt, o->max_dtau};
-    if ((e = launch_refine(P->dev, C.T, C.X, n_poses, rp, (float*)rx, (float*)ry, (float*)rz, F_out, C.lmax, s)) !=
-        hipSuccess)
+    struct Events {  // optional timing of the ascent kernel
+        hipEvent_t ev[2] = {nullptr, nullptr};
+        ~Events() {
+            for (hipEvent_t x : ev)
+                if (x) (void)hipEventDestroy(x);
+        }
+    } T;
+    if (o->kernel_ms && ((e = hipEventCreate(&T.ev[0])) != hipSuccess || (e = hipEventCreate(&T.ev[1])) != hipSuccess ||
+                         (e = hipEventRecord(T.ev[0], s)) != hipSuccess))
         return hip_fail(e, who);
+    e = launch_refine(P->dev, C.T, C.X, n_poses, rp, (float*)rx, (float*)ry, (float*)rz, F_out, C.lmax, s);
+    if (e == hipSuccess && o->kernel_ms) e = hipEventRecord(T.ev[1], s);
+    if (e != hipSuccess) return hip_fail(e, who);
     // exact score of the refined poses, then acceptance
     SD.px = (const float*)rx;
     SD.py = (const float*)ry;
@@ -121,6 +131,12 @@ gd_status refine(const gd_pocket* P, const gd_ligands* topo, int32_t n_poses, co
                            (const int32_t*)S_in, (const int32_t*)S_ref, (const uint8_t*)c_ref, px, py, pz, S_out,
                            clash_out, accepted_out, (const uint8_t*)c_in, s)) != hipSuccess)
         return hip_fail(e, who);
+    if (o->kernel_ms) {
+        float ms = 0.f;
+        if ((e = hipEventSynchronize(T.ev[1])) == hipSuccess) e = hipEventElapsedTime(&ms, T.ev[0], T.ev[1]);
+        if (e != hipSuccess) return hip_fail(e, who);
+        *o->kernel_ms = ms;
+    }
     return GD_OK;
 }
 
