@@ -79,7 +79,8 @@ typedef struct {
  * padded box (uint16), the pocket centroid (FP64, points summed in input
  * order), and optionally the blurred density grid.  Synchronous.
  * Errors: GD_ERR_ARG (null, n_points < 1, h not a power of two, negative pad),
- * GD_ERR_CAPACITY (more than 512 cells per axis, or D would exceed 65535).
+ * GD_ERR_CAPACITY (more than 512 cells per axis or 2^24 cells in all, or D would
+ * exceed 65535).
  */
 gd_status gd_create_pocket(const gd_pocket_desc* desc, void* stream, gd_pocket** out);
 gd_status gd_destroy_pocket(gd_pocket* pocket);
@@ -158,7 +159,7 @@ typedef enum {
 enum {
     GD_CNT_POSES = 0,      /* candidate poses scored (knob-determined)          */
     GD_CNT_FALLBACK = 1,   /* candidates re-evaluated in FP64 near a boundary   */
-    GD_CNT_OOB = 2,        /* atom evaluations outside the tabulated grid box   */
+    GD_CNT_OOB = 2,        /* exact (FP64) atom lookups outside the grid box    */
     GD_CNT_SWEEPS = 3,     /* fragment sweeps performed                         */
     GD_N_COUNTERS = 4
 };

@@ -130,7 +130,7 @@ gd_status autotune(const gd_pocket* P, gd_batch* B, hipStream_t s, int reps, con
         (void)hipEventCreate(&e1);
         float best_ms = 1e30f;
         for (int w : {2, 4, 8})
-            for (int nb : {4, 8, 16})
+            for (int nb : {8, 16, 32})
                 for (int ppl : {2, 4, 8}) {
                     Tiling t;
                     t.waves_per_block = w;

@@ -63,6 +63,8 @@ __device__ __forceinline__ void rotate_about(double px, double py, double pz, co
 // per-wave LDS
 
 constexpr int kSurvCap = 256;  // straddling pairs that can still bump in one sweep
+constexpr int kAng = 1;        // angle blocks scored together by one lane (score pass)
+constexpr int kAtU = 4;        // atoms per lane per step of the score pass
 
 struct WaveLds {
     double* X;       // [3][lp] FP64 master coordinates (x, y, z planes)
@@ -73,7 +75,7 @@ struct WaveLds {
     int* Shi;        // [nmax] upper bound
     uint8_t* st;     // [nmax] bit0: certain bump, bit1: possible bump
     uint16_t* surv;  // [kSurvCap] the pairs that survive the sweep's prune
-    int* red;        // [128] transpose buffer of the score reduction
+    int* red;        // [kAng * 64] transpose buffer of the score reduction
 };
 
 __host__ __device__ inline int lds_pitch(int lmax) { return (lmax + 15) & ~15; }
@@ -81,7 +83,7 @@ __host__ __device__ inline size_t wave_lds_bytes(int lmax, int nmax) {
     int lp = lds_pitch(lmax);
     int np = (nmax + 15) & ~15;
     size_t b = sizeof(double) * 3 * lp + sizeof(double) * 8 + sizeof(float4) * 5 * lp + sizeof(int) * 2 * np + np +
-               sizeof(uint16_t) * kSurvCap + sizeof(int) * 128;
+               sizeof(uint16_t) * kSurvCap + sizeof(int) * kAng * kWave;
     return (b + 15) & ~(size_t)15;
 }
 __host__ __device__ inline size_t replay_lds_bytes(int lmax) {
@@ -99,7 +101,7 @@ __device__ inline WaveLds carve(char* base, int lmax, int nmax) {
     W.Slo = (int*)(W.MV + 3 * lp);
     W.Shi = W.Slo + np;
     W.red = W.Shi + np;
-    W.surv = (uint16_t*)(W.red + 128);
+    W.surv = (uint16_t*)(W.red + kAng * kWave);
     W.st = (uint8_t*)(W.surv + kSurvCap);
     return W;
 }
@@ -118,6 +120,7 @@ struct Sweep {
     float thr_lo, thr_hi;     // bump thresholds on FP32 d^2
     int nsurv;                // pairs that can bump at some angle of this sweep
     bool pruned;              // survivors listed in LDS (else test every pair)
+    bool inside;              // every moving atom stays inside the grid box at every angle
 };
 
 // --------------------------------------------------------------------------
@@ -160,34 +163,10 @@ __device__ __noinline__ uint64_t eval_fp64(const PocketDev* Pp, const double* X,
     return (uint64_t)(uint32_t)S | ((uint64_t)(!clash) << 32) | ((uint64_t)(uint32_t)oob << 40);
 }
 
-// FP32 cell of one candidate atom.  An atom within the guard of a cell face,
-// or outside the tabulated grid, widens the candidate's S range to [S of the
-// other atoms, unbounded]; such a candidate is re-evaluated in FP64 if it can
-// still win its sweep.  Branch-free: an uncertain atom reads cell 0 and
-// discards it, so the per-lane sums stay in registers.
+// An atom within the guard of a cell face, or outside the tabulated grid,
+// widens its candidate's S range to [S of the other atoms, unbounded]; such a
+// candidate is re-evaluated in FP64 if it can still win its sweep.
 constexpr int kOpenHi = 0x20000000;
-
-struct CellRef {
-    int idx;  // linear cell index, 0 when not certain
-    bool ok;  // certain cell inside the grid
-    bool in;  // inside the grid
-};
-
-__device__ __forceinline__ CellRef cell_ref(float yx, float yy, float yz, float lim, int nx, int ny, int nz) {
-    const float fx = floorf(yx), fy = floorf(yy), fz = floorf(yz);
-    const int ix = (int)fx, iy = (int)fy, iz = (int)fz;
-    CellRef r;
-    r.in = (unsigned)ix < (unsigned)nx && (unsigned)iy < (unsigned)ny && (unsigned)iz < (unsigned)nz;
-    r.ok = r.in && fabsf(yx - fx - 0.5f) <= lim && fabsf(yy - fy - 0.5f) <= lim && fabsf(yz - fz - 0.5f) <= lim;
-    r.idx = r.ok ? (iz * ny + iy) * nx + ix : 0;
-    return r;
-}
-
-__device__ __forceinline__ void cell_acc(const CellRef& r, int d, int& slo, int& shi, int& oob) {
-    slo += r.ok ? d : 0;
-    shi = r.ok ? shi + d : kOpenHi;
-    oob += r.in ? 0 : 1;
-}
 
 // K pairs per lane starting at q0: FP32 A, B, C from the per-atom data, then
 // for each of the nw angles of the word a certain / possible bump bit.
@@ -227,6 +206,120 @@ __device__ __forceinline__ void bump_block(const Sweep& sw, const WaveLds& W, in
     }
 }
 
+// Score pass over the candidate angles base + k*stride (k < n).  Lanes are
+// (k0 < NB, atom group g < 64/NB); a super-block covers up to kAng blocks of
+// NB angles, and a lane scores the angles k0 + NB*a (a < kAng) of its atoms,
+// so each atom's coefficients are read from LDS once for up to kAng angles
+// and up to kAtU*kAng distance-grid gathers are in flight.  Atoms past the end of
+// the moving list, and atoms whose cell is not certain, read the zero sentinel
+// cell.  The cell test is branch-free; with BOX the grid bounds are tested
+// per atom, otherwise the sweep set-up has proven that every moving atom stays
+// inside the box.  Writes W.Slo / W.Shi per candidate.
+template <int NB>
+__device__ __forceinline__ uint32_t fold_groups(uint64_t m) {
+    // OR together the bits of lanes k0 + NB*g over g: result bit k0
+#pragma unroll
+    for (int sh = 32; sh >= NB; sh >>= 1) m |= m >> sh;
+    return (uint32_t)m & (uint32_t)((1ull << NB) - 1);
+}
+
+template <int NB, bool BOX>
+__device__ __forceinline__ void score_pass(const PocketDev& P, const Sweep& sw, const WaveLds& W, const float* trig,
+                                           int base, int stride, int n) {
+    const int lane = lane_id();
+    constexpr int G = kWave / NB;
+    const int k0 = lane & (NB - 1), g = lane / NB;
+    const float fnx = (float)P.dim[0], fny = (float)P.dim[1], fnz = (float)P.dim[2];
+    const float fsy = fnx, fsz = fnx * fny;  // exact: the box holds fewer than 2^24 cells
+    const float fsent = (float)P.n_cells;
+    const float glo = sw.gcell, ghi = 1.f - sw.gcell;
+    const int m = sw.m;
+    for (int kb = 0; kb < n; kb += NB * kAng) {
+        const int A = min(kAng, (n - kb + NB - 1) / NB);
+        float c[kAng], s[kAng];
+        bool av[kAng];
+#pragma unroll
+        for (int a = 0; a < kAng; a++) {
+            const int k = kb + k0 + NB * a;
+            av[a] = (a < A) & (k < n);
+            const int deg = base + (av[a] ? k : 0) * stride;
+            c[a] = trig[deg];
+            s[a] = trig[360 + deg];
+        }
+        int sum[kAng];
+        bool bad[kAng];
+#pragma unroll
+        for (int a = 0; a < kAng; a++) {
+            sum[a] = 0;
+            bad[a] = false;
+        }
+        for (int j = g; j < m; j += kAtU * G) {
+            uint32_t off[kAtU][kAng];
+#pragma unroll
+            for (int t = 0; t < kAtU; t++) {
+                const int jj = j + t * G;
+                const bool live = jj < m;
+                const int ja = live ? jj : j;
+                const float4 p0 = W.MV[3 * ja], u = W.MV[3 * ja + 1], v = W.MV[3 * ja + 2];
+#pragma unroll
+                for (int a = 0; a < kAng; a++) {
+                    off[t][a] = (uint32_t)fsent;
+                    if (a < A) {
+                        const float yx = fmaf(s[a], v.x, fmaf(c[a], u.x, p0.x));
+                        const float yy = fmaf(s[a], v.y, fmaf(c[a], u.y, p0.y));
+                        const float yz = fmaf(s[a], v.z, fmaf(c[a], u.z, p0.z));
+                        const float fx = floorf(yx), fy = floorf(yy), fz = floorf(yz);
+                        const float rx = __builtin_amdgcn_fractf(yx), ry = __builtin_amdgcn_fractf(yy),
+                                    rz = __builtin_amdgcn_fractf(yz);
+                        bool sure = (fminf(fminf(rx, ry), rz) >= glo) & (fmaxf(fmaxf(rx, ry), rz) <= ghi);
+                        if (BOX)
+                            sure = sure & (fx >= 0.f) & (fx < fnx) & (fy >= 0.f) & (fy < fny) & (fz >= 0.f) &
+                                   (fz < fnz);
+                        const bool use = live & av[a];
+                        bad[a] = bad[a] | (use & !sure);
+                        const float fi = fmaf(fz, fsz, fmaf(fy, fsy, fx));
+                        off[t][a] = (uint32_t)((use & sure) ? fi : fsent);
+                    }
+                }
+            }
+#pragma unroll
+            for (int a = 0; a < kAng; a++)
+                if (a < A) {
+                    int d = 0;
+#pragma unroll
+                    for (int t = 0; t < kAtU; t++) d += (int)ldg(P.edt + off[t][a]);
+                    sum[a] += d;
+                }
+        }
+        // sum the groups of each angle through LDS; uncertain flags by ballot
+        uint32_t badbits[kAng];
+#pragma unroll
+        for (int a = 0; a < kAng; a++) {
+            badbits[a] = 0;
+            if (a < A) {
+                W.red[a * kWave + lane] = sum[a];
+                badbits[a] = fold_groups<NB>(__ballot(bad[a]));
+            }
+        }
+        wave_sync();
+        for (int L = lane; L < A * NB; L += kWave) {
+            const int a = L / NB, kk = L & (NB - 1);
+            const int k = kb + kk + NB * a;
+            if (k < n) {
+                int tot = 0;
+#pragma unroll
+                for (int gg = 0; gg < G; gg++) tot += W.red[a * kWave + kk + gg * NB];
+                uint32_t bb = badbits[0];
+#pragma unroll
+                for (int aa = 1; aa < kAng; aa++) bb = a == aa ? badbits[aa] : bb;
+                W.Slo[k] = tot;
+                W.Shi[k] = ((bb >> kk) & 1u) ? kOpenHi : tot;
+            }
+        }
+        wave_sync();
+    }
+}
+
 // Evaluate the candidate angles base + k*stride (k < n) of the current sweep;
 // returns the winning position (lowest S among feasible candidates, earliest
 // on ties) or -1 when none is feasible.
@@ -237,56 +330,10 @@ __device__ int eval_candidates(const PocketDev& P, const BatchDev& B, const Swee
     constexpr int G = kWave / NB;
     acc.poses += n;
 
-    // ---- score pass: lanes = (angle within block, atom group); four atoms
-    // per step so that four distance-grid gathers are in flight at once
-    const int nx = P.dim[0], ny = P.dim[1], nz = P.dim[2];
-    const float lim = 0.5f - sw.gcell;
-    for (int kb = 0; kb < n; kb += NB) {
-        const int k = kb + (lane & (NB - 1));
-        const int g = lane / NB;
-        int slo = 0, shi = 0;
-        if (k < n) {
-            const int deg = base + k * stride;
-            const float c = trig[deg], s = trig[360 + deg];
-            int j = g;
-            for (; j + 3 * G < sw.m; j += 4 * G) {
-                CellRef r[4];
-#pragma unroll
-                for (int t = 0; t < 4; t++) {
-                    const int jj = j + t * G;
-                    const float4 p0 = W.MV[3 * jj], u = W.MV[3 * jj + 1], v = W.MV[3 * jj + 2];
-                    r[t] = cell_ref(fmaf(s, v.x, fmaf(c, u.x, p0.x)), fmaf(s, v.y, fmaf(c, u.y, p0.y)),
-                                    fmaf(s, v.z, fmaf(c, u.z, p0.z)), lim, nx, ny, nz);
-                }
-                int d[4];
-#pragma unroll
-                for (int t = 0; t < 4; t++) d[t] = ldg(P.edt + r[t].idx);
-#pragma unroll
-                for (int t = 0; t < 4; t++) cell_acc(r[t], d[t], slo, shi, acc.oob);
-            }
-            for (; j < sw.m; j += G) {
-                const float4 p0 = W.MV[3 * j], u = W.MV[3 * j + 1], v = W.MV[3 * j + 2];
-                const CellRef r = cell_ref(fmaf(s, v.x, fmaf(c, u.x, p0.x)), fmaf(s, v.y, fmaf(c, u.y, p0.y)),
-                                           fmaf(s, v.z, fmaf(c, u.z, p0.z)), lim, nx, ny, nz);
-                cell_acc(r, ldg(P.edt + r.idx), slo, shi, acc.oob);
-            }
-        }
-        // sum the groups of each angle through LDS
-        W.red[lane] = slo;
-        W.red[kWave + lane] = shi;
-        wave_sync();
-        if (lane < NB && k < n) {
-            int a = 0, b = 0;
-#pragma unroll
-            for (int gg = 0; gg < G; gg++) {
-                a += W.red[lane + gg * NB];
-                b = min(b + W.red[kWave + lane + gg * NB], kOpenHi);
-            }
-            W.Slo[k] = a;
-            W.Shi[k] = b >= kOpenHi ? kOpenHi : b;
-        }
-        wave_sync();
-    }
+    if (sw.inside)
+        score_pass<NB, false>(P, sw, W, trig, base, stride, n);
+    else
+        score_pass<NB, true>(P, sw, W, trig, base, stride, n);
 
     // ---- bump pass: lanes = straddling pairs (the survivors of the prune),
     // loop over the angles of a word of 64 candidates
@@ -421,7 +468,9 @@ __device__ __forceinline__ void sweep_setup(const PocketDev& P, const BatchDev& 
         r2max = fmaxf(r2max, (float)uu);
     }
     float amax = 0.f, umax = 0.f;
+    bool outside = false;
     const double ih = P.inv_h;
+    const double bx = (double)P.dim[0] - 0.01, by = (double)P.dim[1] - 0.01, bz = (double)P.dim[2] - 0.01;
     for (int j = lane; j < sw.m; j += kWave) {
         int i = ldg(sw.mvl + j);
         double ux = Xx[i] - px, uy = Xy[i] - py, uz = Xz[i] - pz;
@@ -434,11 +483,19 @@ __device__ __forceinline__ void sweep_setup(const PocketDev& P, const BatchDev& 
         W.MV[3 * j] = make_float4((float)ax0, (float)ay0, (float)az0, 0.f);
         W.MV[3 * j + 1] = make_float4((float)Ux, (float)Uy, (float)Uz, 0.f);
         W.MV[3 * j + 2] = make_float4((float)Vx, (float)Vy, (float)Vz, 0.f);
+        // the circle's extent along axis a is P0_a +- sqrt(U_a^2 + V_a^2): keep it
+        // 0.01 cell inside the box on both sides
+        const double ex2 = Ux * Ux + Vx * Vx, ey2 = Uy * Uy + Vy * Vy, ez2 = Uz * Uz + Vz * Vz;
+        const double lx = ax0 - 0.01, ly = ay0 - 0.01, lz = az0 - 0.01;
+        const double hx = bx - ax0, hy = by - ay0, hz = bz - az0;
+        outside |= !(lx >= 0.0 && ly >= 0.0 && lz >= 0.0 && hx >= 0.0 && hy >= 0.0 && hz >= 0.0 && ex2 <= lx * lx &&
+                     ey2 <= ly * ly && ez2 <= lz * lz && ex2 <= hx * hx && ey2 <= hy * hy && ez2 <= hz * hz);
         amax = fmaxf(amax, (float)fmax(fabs(ax0), fmax(fabs(ay0), fabs(az0))));
         umax = fmaxf(umax, (float)fmax(fmax(fabs(Ux), fmax(fabs(Uy), fabs(Uz))),
                                        fmax(fabs(Vx), fmax(fabs(Vy), fabs(Vz)))));
     }
     r2max = wave_maxf(r2max);
+    sw.inside = __ballot(outside) == 0;
     amax = wave_maxf(amax);
     umax = wave_maxf(umax);
     // Rounding guards (u = 2^-24), each doubled for safety and with the maxima

@@ -46,7 +46,8 @@ struct alignas(16) LigMeta {
 
 // Device view of a pocket.
 struct PocketDev {
-    const uint16_t* edt;      // D on the box, x fastest
+    const uint16_t* edt;      // D on the box, x fastest, then one zero sentinel cell
+    int32_t n_cells;          // cells of the box (= index of the sentinel), < 2^24
     const int32_t* occ;       // occupied cells (global lattice), 3 per cell
     int32_t n_occ;
     int32_t lo[3];            // box origin (lattice index)
@@ -117,7 +118,7 @@ struct PoseDev {
 
 struct Tiling {
     int waves_per_block = 4;
-    int angle_block = 8;
+    int angle_block = 32;
     int pairs_per_lane = 4;
 };
 

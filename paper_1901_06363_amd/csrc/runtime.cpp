@@ -179,7 +179,8 @@ gd_status create_pocket(const gd_pocket_desc* desc, hipStream_t stream, gd_pocke
         occ.push_back(cells[3 * i + 2]);
     }
     const size_t total = (size_t)dim[0] * dim[1] * dim[2];
-    std::vector<double> g(total, 1e15), tmp(total);
+    if (total >= ((size_t)1 << 24)) return fail(GD_ERR_CAPACITY, "gd_create_pocket: grid box exceeds 2^24 cells");
+    std::vector<double> g(total, 1e15);
     for (size_t m = 0; m < occ.size() / 3; m++) {
         int ix = occ[3 * m] - lo[0], iy = occ[3 * m + 1] - lo[1], iz = occ[3 * m + 2] - lo[2];
         g[((size_t)iz * dim[1] + iy) * dim[0] + ix] = 0.0;
@@ -208,7 +209,7 @@ gd_status create_pocket(const gd_pocket_desc* desc, hipStream_t stream, gd_pocke
                 for (int iz = 0; iz < dim[2]; iz++) g[((size_t)iz * dim[1] + iy) * dim[0] + ix] = d[iz];
             }
     }
-    std::vector<uint16_t> edt(total);
+    std::vector<uint16_t> edt(total + 1, 0);  // + a zero sentinel cell read by masked lanes
     for (size_t i = 0; i < total; i++) {
         if (g[i] > 65535.0) return fail(GD_ERR_CAPACITY, "gd_create_pocket: distance grid value exceeds 65535");
         edt[i] = (uint16_t)g[i];
@@ -219,6 +220,7 @@ gd_status create_pocket(const gd_pocket_desc* desc, hipStream_t stream, gd_pocke
     if ((e = P->occ.upload(occ.data(), occ.size() * 4, stream)) != hipSuccess) return hip_fail(e, "gd_create_pocket");
     PocketDev& D = P->dev;
     D.edt = (const uint16_t*)P->edt.ptr;
+    D.n_cells = (int32_t)total;
     D.occ = (const int32_t*)P->occ.ptr;
     D.n_occ = (int32_t)(occ.size() / 3);
     for (int a = 0; a < 3; a++) {
@@ -897,7 +899,7 @@ gd_status gd_pocket_get_info(const gd_pocket* P, gd_pocket_info* info) {
 gd_status gd_pocket_read_grid(const gd_pocket* P, uint16_t* host_out) {
     clear_error();
     if (!P || !host_out) return fail(GD_ERR_ARG, "gd_pocket_read_grid: null argument");
-    hipError_t e = hipMemcpy(host_out, P->edt.ptr, P->edt.bytes, hipMemcpyDeviceToHost);
+    hipError_t e = hipMemcpy(host_out, P->edt.ptr, (size_t)P->dev.n_cells * sizeof(uint16_t), hipMemcpyDeviceToHost);
     return e == hipSuccess ? GD_OK : hip_fail(e, "gd_pocket_read_grid");
 }
 
