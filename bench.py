@@ -56,27 +56,22 @@ def refine_leg(gd, torch, np, n_lig):
     """The refinement workload: top-64 docked poses of n_lig ligands, 50 ascent
     steps on the blurred-density surrogate, exact rescoring and acceptance."""
     from synth import configs
+    from paper_1901_06363_amd.stream import poses_from_topk
     w = configs.REFINE
     e = w.extra
     ligs = w.ligands(0, n_lig)
     P = gd.Pocket(w.pocket_points(), 0.5, w.pad, blur_sigma=e["blur_sigma"], blur_h=e["blur_h"])
     B = gd.Batch(P, ligs, w.quaternions(), hp=w.hp, top_k=w.top_k)
     r = B.dock(gd.BATCHED)
-    k, lmax = w.top_k, r.xyz.shape[2]
-    nat = np.diff(ligs.atom_off).astype(np.int64)
-    pose_lig = np.repeat(np.arange(n_lig), k)
-    pa = nat[pose_lig]
-    first = np.concatenate([[0], np.cumsum(pa)[:-1]])
-    idx = np.repeat(np.arange(len(pose_lig)) * lmax - first, pa) + np.arange(pa.sum())
-    X = r.xyz.reshape(-1, 3).index_select(0, torch.from_numpy(idx).cuda())
+    k = w.top_k
+    pose_lig, px, py, pz = poses_from_topk(r, ligs)
+    pa = np.diff(ligs.atom_off)[pose_lig]
     kw = dict(steps=e["steps"], lr_t=e["lr_t"], lr_q=e["lr_q"], lr_tau=e["lr_tau"], max_dt=e["max_dt"],
               max_dtau=e["max_dtau"])
     # warm-up on a slice, then the timed call over every pose
     m = min(len(pose_lig), 4096)
     n_warm = int(pa[:m].sum())
-    gd.refine(P, ligs, pose_lig[:m], X[:n_warm, 0].contiguous(), X[:n_warm, 1].contiguous(),
-              X[:n_warm, 2].contiguous(), **kw)
-    px, py, pz = (X[:, a].contiguous() for a in range(3))
+    gd.refine(P, ligs, pose_lig[:m], px[:n_warm].clone(), py[:n_warm].clone(), pz[:n_warm].clone(), **kw)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     out = gd.refine(P, ligs, pose_lig, px, py, pz, time_kernel=True, **kw)

@@ -1,0 +1,96 @@
+"""Streaming screen of a large ligand library through the persistent kernel.
+
+A library too large for one batch is docked chunk by chunk.  While chunk i
+docks on the GPU, a host thread prepares chunk i+1 (validation, topology,
+straddling pairs, work queue, upload on a side stream), so host preparation
+overlaps device work.  The top-k poses of each chunk can then be refined on
+the density surrogate and re-scored exactly (``refine_poses=dict(...)``, the
+options of ``refine``).
+
+Ligand sources are callables ``source(first, count) -> LigandBatch`` so that a
+chunk is generated (or read) only when it is about to be prepared.
+"""
+from __future__ import annotations
+
+import threading
+
+import numpy as np
+
+from . import BATCHED, Batch, _torch, refine as _refine
+
+
+def poses_from_topk(res, ligands):
+    """CSR pose arrays (pose_lig, px, py, pz) of every top-k pose of a docking
+    result, gathered on the device from its (n, k, max_atoms, 3) coordinates."""
+    torch = _torch()
+    n, k, lmax = res.xyz.shape[0], res.xyz.shape[1], res.xyz.shape[2]
+    nat = np.diff(np.asarray(ligands.atom_off)).astype(np.int64)
+    pose_lig = np.repeat(np.arange(n), k)
+    pa = nat[pose_lig]
+    first = np.concatenate([[0], np.cumsum(pa)[:-1]])
+    idx = np.repeat(np.arange(len(pose_lig)) * lmax - first, pa) + np.arange(pa.sum())
+    X = res.xyz.reshape(-1, 3).index_select(0, torch.from_numpy(idx).to(res.xyz.device))
+    return pose_lig, X[:, 0].contiguous(), X[:, 1].contiguous(), X[:, 2].contiguous()
+
+
+class _Prepared:
+    def __init__(self):
+        self.batch = None
+        self.ligands = None
+        self.error = None
+
+
+def _prepare(slot, pocket, source, first, count, quats, knobs, stream):
+    try:
+        ligs = source(first, count)
+        slot.ligands = ligs
+        slot.batch = Batch(pocket, ligs, quats, stream=stream, **knobs)
+    except BaseException as e:  # re-raised in the consumer
+        slot.error = e
+
+
+def screen(pocket, source, n_ligands, quats, chunk=65536, mode=BATCHED, refine_poses=None, want_xyz=True, **knobs):
+    """Dock ligands [0, n_ligands) of ``source`` in chunks; yields one dict per
+    chunk: first, count, ligands, poses, result (host arrays of the top-k
+    poses), and with ``refine_poses`` the refined poses' surrogate, exact S,
+    clash, acceptance and coordinates.  ``knobs`` are the Batch knobs (hp, lp,
+    threshold, repetitions, refine (tile peeling), top_k, clash_dist,
+    clash_min_bonds); the pocket needs a density grid for ``refine_poses``.
+    """
+    torch = _torch()
+    if refine_poses is not None and not want_xyz:
+        raise ValueError("refinement needs the pose coordinates (want_xyz=True)")
+    side = torch.cuda.Stream()
+    main = torch.cuda.current_stream()
+    starts = list(range(0, n_ligands, chunk))
+
+    def launch(i):
+        slot = _Prepared()
+        first = starts[i]
+        th = threading.Thread(target=_prepare, args=(slot, pocket, source, first, min(chunk, n_ligands - first),
+                                                     quats, knobs, side))
+        th.start()
+        return slot, th
+
+    nxt = launch(0) if starts else None
+    for i, first in enumerate(starts):
+        slot, th = nxt
+        th.join()
+        if slot.error is not None:
+            raise slot.error
+        B = slot.batch
+        out = B.alloc_outputs(want_angles=True, want_xyz=want_xyz)
+        B.dock(mode, out)
+        # prepare the next chunk while this one docks
+        nxt = launch(i + 1) if i + 1 < len(starts) else None
+        item = dict(first=first, count=B.n_ligands, ligands=slot.ligands, poses=B.poses_expected)
+        if refine_poses is not None:
+            pose_lig, px, py, pz = poses_from_topk(out, slot.ligands)
+            r = _refine(pocket, slot.ligands, pose_lig, px, py, pz, **refine_poses)
+            item["refine"] = dict(pose_lig=pose_lig, F=r["F"].cpu().numpy(), S=r["S"].cpu().numpy(),
+                                  clash=r["clash"].cpu().numpy(), accepted=r["accepted"].cpu().numpy(),
+                                  xyz=torch.stack([px, py, pz], 1).cpu().numpy())
+        main.synchronize()
+        item["result"] = out.host()
+        yield item
+        del out, B, slot
