@@ -29,6 +29,37 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X published FP32 vector peak
+# sources of the docking kernel; the HBM traffic measured with rocprofv3 counters
+# is reported only while they are unchanged since the measurement
+KERNEL_SOURCES = ["dock.hip", "device_common.h", "gd_internal.h"]
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "dock_persistent_kernel.screen.traffic.md")
+
+
+def kernel_fingerprint():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1901_06363_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the docking kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by a plain copy kernel's
+    reading), or None when the kernel sources changed since it was taken."""
+    try:
+        vals = {}
+        with open(TRAFFIC_PROFILE) as fh:
+            for ln in fh:
+                if ":" in ln and ln.startswith("- "):
+                    k, v = ln[2:].split(":", 1)
+                    vals[k.strip()] = v.strip().strip("`")
+        if vals.get("kernel source fingerprint") != kernel_fingerprint():
+            return None
+        return dict(fetch=float(vals["HBM bytes read per launch"]), write=float(vals["HBM bytes written per launch"]))
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def log(*a):
@@ -101,14 +132,19 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-ligand", action="store_true")
     ap.add_argument("--no-refine", action="store_true")
+    ap.add_argument("--refine-only", action="store_true", help="run only the refinement leg (profiling)")
     ap.add_argument("--refine-ligands", type=int, default=4096)
     ap.add_argument("--tiling", type=str, default="")
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--n-ligands", type=int, default=0, help="override the ligand count (testing only)")
+    ap.add_argument("--fingerprint", action="store_true", help="print the docking kernel's source fingerprint")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (the reference kernel for HBM byte counters)")
     args = ap.parse_args()
 
+    if args.fingerprint:
+        print(kernel_fingerprint())
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (ligand batches shard trivially "
               "across GPUs, see DESIGN.md); got --gpus %d" % args.gpus, file=sys.stderr)
@@ -131,6 +167,9 @@ def main():
         torch.neg(a, out=b)
         torch.cuda.synchronize()
         log("copy calibration: read %d B, wrote %d B" % (n, n))
+        return
+    if args.refine_only:
+        print(json.dumps(refine_leg(gd, torch, np, args.refine_ligands)), flush=True)
         return
     w = configs.SCREEN
     n_lig = args.n_ligands or w.n_ligands
@@ -218,6 +257,7 @@ def main():
         log("cpu baseline:", cpu)
 
     achieved = B.algo_flops / (k_ms * 1e-3) / 1e12
+    tr = measured_traffic() if n_lig == w.n_ligands else None
     line = {
         "metric": "poses scored/s and ligands docked/s, batched vs per-ligand, same GPU, exact",
         "value": value,
@@ -255,7 +295,9 @@ def main():
             "peak": FP32_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": (tr["fetch"] + tr["write"]) if tr else None,
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "traffic_GBps": ((tr["fetch"] + tr["write"]) / (k_ms * 1e-3) / 1e9) if tr else None,
             "kernel": "dock_persistent_kernel",
             "kernel_ms": k_ms,
             "algo_flops_per_launch": B.algo_flops,
