@@ -62,7 +62,7 @@ __device__ __forceinline__ void rotate_about(double px, double py, double pz, co
 // --------------------------------------------------------------------------
 // per-wave LDS
 
-constexpr int kSurvCap = 256;  // straddling pairs that can still bump in one sweep
+constexpr int kSurvCap = 128;  // straddling pairs that can still bump in one sweep (LDS list)
 constexpr int kAng = 1;        // angle blocks scored together by one lane (score pass)
 constexpr int kAtU = 4;        // atoms per lane per step of the score pass
 
@@ -74,7 +74,7 @@ struct WaveLds {
     int* Slo;        // [nmax] lower bound of each candidate's S over the moving atoms
     int* Shi;        // [nmax] upper bound
     uint8_t* st;     // [nmax] bit0: certain bump, bit1: possible bump
-    uint16_t* surv;  // [kSurvCap] the pairs that survive the sweep's prune
+    float4* surv;    // [kSurvCap] (A, B, C, -) of the pairs that survive the sweep's prune
     int* red;        // [kAng * 64] transpose buffer of the score reduction
 };
 
@@ -82,8 +82,8 @@ __host__ __device__ inline int lds_pitch(int lmax) { return (lmax + 15) & ~15; }
 __host__ __device__ inline size_t wave_lds_bytes(int lmax, int nmax) {
     int lp = lds_pitch(lmax);
     int np = (nmax + 15) & ~15;
-    size_t b = sizeof(double) * 3 * lp + sizeof(double) * 8 + sizeof(float4) * 5 * lp + sizeof(int) * 2 * np + np +
-               sizeof(uint16_t) * kSurvCap + sizeof(int) * kAng * kWave;
+    size_t b = sizeof(double) * 3 * lp + sizeof(double) * 8 + sizeof(float4) * (5 * lp + kSurvCap) +
+               sizeof(int) * 2 * np + np + sizeof(int) * kAng * kWave;
     return (b + 15) & ~(size_t)15;
 }
 __host__ __device__ inline size_t replay_lds_bytes(int lmax) {
@@ -98,11 +98,11 @@ __device__ inline WaveLds carve(char* base, int lmax, int nmax) {
     W.SW = W.X + 3 * lp;
     W.AD = (float4*)(W.SW + 8);
     W.MV = W.AD + 2 * lp;
-    W.Slo = (int*)(W.MV + 3 * lp);
+    W.surv = W.MV + 3 * lp;
+    W.Slo = (int*)(W.surv + kSurvCap);
     W.Shi = W.Slo + np;
     W.red = W.Shi + np;
-    W.surv = (uint16_t*)(W.red + kAng * kWave);
-    W.st = (uint8_t*)(W.surv + kSurvCap);
+    W.st = (uint8_t*)(W.red + kAng * kWave);
     return W;
 }
 
@@ -179,7 +179,7 @@ __device__ __forceinline__ void bump_block(const Sweep& sw, const WaveLds& W, in
     for (int t = 0; t < K; t++) {
         const int q = q0 + t * kWave + lane;
         if (q < nq) {
-            uint16_t pr = sw.pruned ? W.surv[q] : ldg(sw.pairs + q);
+            uint16_t pr = ldg(sw.pairs + q);
             int li = pr & 0xff, ri = pr >> 8;
             int m = sw.side == 0 ? li : ri, f = sw.side == 0 ? ri : li;
             const float4 um = W.AD[2 * m], wm = W.AD[2 * m + 1], uf = W.AD[2 * f], wf = W.AD[2 * f + 1];
@@ -335,24 +335,49 @@ __device__ int eval_candidates(const PocketDev& P, const BatchDev& B, const Swee
     else
         score_pass<NB, true>(P, sw, W, trig, base, stride, n);
 
-    // ---- bump pass: lanes = straddling pairs (the survivors of the prune),
-    // loop over the angles of a word of 64 candidates
-    for (int w0 = 0; w0 < n; w0 += kWave) {
-        const int nw = min(kWave, n - w0);
-        float cl = 0.f, sl = 0.f;
-        if (lane < nw) {
-            int deg = base + (w0 + lane) * stride;
-            cl = trig[deg];
-            sl = trig[360 + deg];
+    // ---- bump pass.  After a successful prune: lanes = candidate angles (64
+    // per word), each takes the minimum of d^2 = A + B cos + C sin over the
+    // survivors' coefficients (broadcast from LDS); a certain bump is
+    // min < cd^2 - guard, a possible one min < cd^2 + guard.  Otherwise (more
+    // survivors than the LDS list holds): lanes = straddling pairs, looping
+    // over the angles of the word.
+    if (sw.pruned) {
+        for (int w0 = 0; w0 < n; w0 += kWave) {
+            const int k = w0 + lane;
+            const int deg = base + (k < n ? k : 0) * stride;
+            const float c = trig[deg], s = trig[360 + deg];
+            float d0 = 3.0e38f, d1 = 3.0e38f;
+            int q = 0;
+            for (; q + 1 < sw.nsurv; q += 2) {
+                const float4 e0 = W.surv[q], e1 = W.surv[q + 1];
+                d0 = fminf(d0, fmaf(e0.z, s, fmaf(e0.y, c, e0.x)));
+                d1 = fminf(d1, fmaf(e1.z, s, fmaf(e1.y, c, e1.x)));
+            }
+            if (q < sw.nsurv) {
+                const float4 e0 = W.surv[q];
+                d0 = fminf(d0, fmaf(e0.z, s, fmaf(e0.y, c, e0.x)));
+            }
+            const float d = fminf(d0, d1);
+            if (k < n) W.st[k] = (uint8_t)((d < sw.thr_lo ? 1 : 0) | (d < sw.thr_hi ? 2 : 0));
         }
-        uint64_t cert = 0, maybe = 0;
-        const int nq = sw.pruned ? sw.nsurv : sw.npairs;
-        int q0 = 0;
-        if (PPL > 1)
-            for (; nq - q0 > kWave * (PPL - 1); q0 += kWave * PPL)
-                bump_block<PPL>(sw, W, q0, nq, nw, cl, sl, cert, maybe);
-        for (; q0 < nq; q0 += kWave) bump_block<1>(sw, W, q0, nq, nw, cl, sl, cert, maybe);
-        if (lane < nw) W.st[w0 + lane] = (uint8_t)(((cert >> lane) & 1) | (((maybe >> lane) & 1) << 1));
+    } else {
+        for (int w0 = 0; w0 < n; w0 += kWave) {
+            const int nw = min(kWave, n - w0);
+            float cl = 0.f, sl = 0.f;
+            if (lane < nw) {
+                int deg = base + (w0 + lane) * stride;
+                cl = trig[deg];
+                sl = trig[360 + deg];
+            }
+            uint64_t cert = 0, maybe = 0;
+            const int nq = sw.npairs;
+            int q0 = 0;
+            if (PPL > 1)
+                for (; nq - q0 > kWave * (PPL - 1); q0 += kWave * PPL)
+                    bump_block<PPL>(sw, W, q0, nq, nw, cl, sl, cert, maybe);
+            for (; q0 < nq; q0 += kWave) bump_block<1>(sw, W, q0, nq, nw, cl, sl, cert, maybe);
+            if (lane < nw) W.st[w0 + lane] = (uint8_t)(((cert >> lane) & 1) | (((maybe >> lane) & 1) << 1));
+        }
     }
     wave_sync();
 
@@ -526,22 +551,25 @@ __device__ __forceinline__ void sweep_setup(const PocketDev& P, const BatchDev& 
         for (int t = 0; t < 4; t++) {
             const int q = q0 + t * kWave + lane;
             bool keep = false;
+            float A = 0.f, Bv = 0.f, Cv = 0.f;
             if (q < sw.npairs) {
+                // the same FP32 expressions as the bump test, so the stored
+                // coefficients equal what it would compute
                 const uint16_t pr = prs[t];
                 int li = pr & 0xff, ri2 = pr >> 8;
                 int m = side == 0 ? li : ri2, f = side == 0 ? ri2 : li;
                 const float4 um = W.AD[2 * m], wm = W.AD[2 * m + 1], uf = W.AD[2 * f], wf = W.AD[2 * f + 1];
                 float kk = um.w * uf.w;
-                float A = wm.w + wf.w - 2.f * kk;
-                float Bv = -2.f * (um.x * uf.x + um.y * uf.y + um.z * uf.z - kk);
-                float Cv = -2.f * (uf.x * wm.x + uf.y * wm.y + uf.z * wm.z);
+                A = wm.w + wf.w - 2.f * kk;
+                Bv = -2.f * (um.x * uf.x + um.y * uf.y + um.z * uf.z - kk);
+                Cv = -2.f * (uf.x * wm.x + uf.y * wm.y + uf.z * wm.z);
                 float Am = A - T;
                 keep = !(Am > 0.f && Am * Am > 1.0001f * (Bv * Bv + Cv * Cv));
             }
             const uint64_t mk = __ballot(keep);
             const int pos =
                 nsurv + __builtin_amdgcn_mbcnt_hi((uint32_t)(mk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0));
-            if (keep && pos < kSurvCap) W.surv[pos] = prs[t];
+            if (keep && pos < kSurvCap) W.surv[pos] = make_float4(A, Bv, Cv, 0.f);
             nsurv += __popcll(mk);
         }
     }
