@@ -222,7 +222,7 @@ gd_status gd_dock_batch(const gd_pocket* pocket, const gd_ligands* ligands, cons
 
 /*
  * Kernel tiling of the docking kernel.  waves_per_block: 1,2,4,8; angle_block:
- * candidate poses scored side by side per wavefront pass (4, 8, 16, 32);
+ * candidate poses scored side by side per wavefront pass (8, 16, 32);
  * pairs_per_lane: straddling pairs each lane holds while sweeping the
  * angles (1, 2, 4, 8).  Results do not depend on the tiling.
  */

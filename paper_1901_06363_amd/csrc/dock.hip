@@ -62,28 +62,46 @@ __device__ __forceinline__ void rotate_about(double px, double py, double pz, co
 // --------------------------------------------------------------------------
 // per-wave LDS
 
+// LDS (address space 3) views of the per-wave working set: 32-bit addresses
+// and LDS-only memory instructions.
+typedef __attribute__((address_space(3))) double lds_double;
+typedef __attribute__((address_space(3))) float lds_float;
+typedef float f4 __attribute__((ext_vector_type(4)));  // plain 16-byte vector (copyable from LDS)
+typedef __attribute__((address_space(3))) f4 lds_float4;
+
+__device__ __forceinline__ f4 mk4(float a, float b, float c, float d) {
+    f4 v;
+    v.x = a;
+    v.y = b;
+    v.z = c;
+    v.w = d;
+    return v;
+}
+typedef __attribute__((address_space(3))) int lds_int;
+typedef __attribute__((address_space(3))) uint8_t lds_u8;
+
 constexpr int kSurvCap = 128;  // straddling pairs that can still bump in one sweep (LDS list)
-constexpr int kAng = 1;        // angle blocks scored together by one lane (score pass)
 constexpr int kAtU = 4;        // atoms per lane per step of the score pass
+constexpr int kMvPad = 32;     // sentinel rows after the moving list (covers a step at >= 8 angles per block)
 
 struct WaveLds {
-    double* X;       // [3][lp] FP64 master coordinates (x, y, z planes)
-    double* SW;      // [8] FP64 axis k (3) and pivot p (3) of the sweep in progress
-    float4* AD;      // [lp][2] per-atom sweep data: (u, k.u), (k x u, |u|^2), u = X - p (A)
-    float4* MV;      // [lp][3] moving atoms: P0, U, V in cell units (w unused)
-    int* Slo;        // [nmax] lower bound of each candidate's S over the moving atoms
-    int* Shi;        // [nmax] upper bound
-    uint8_t* st;     // [nmax] bit0: certain bump, bit1: possible bump
-    float4* surv;    // [kSurvCap] (A, B, C, -) of the pairs that survive the sweep's prune
-    int* red;        // [kAng * 64] transpose buffer of the score reduction
+    lds_double* X;   // [3][lp] FP64 master coordinates (x, y, z planes)
+    lds_double* SW;  // [8] FP64 axis k (3) and pivot p (3) of the sweep in progress
+    lds_float4* AD;  // [lp][2] per-atom sweep data: (u, k.u), (k x u, |u|^2), u = X - p (A)
+    lds_float4* MV;  // [lp + kMvPad][3] moving atoms: P0, U, V in cell units (w unused), then sentinel rows
+    lds_int* Slo;    // [nmax] lower bound of each candidate's S over the moving atoms
+    lds_int* Shi;    // [nmax] upper bound
+    lds_u8* st;      // [nmax] bit0: certain bump, bit1: possible bump
+    lds_float4* surv;  // [kSurvCap] (A, B, C, -) of the pairs that survive the sweep's prune
+    lds_int* red;    // [64] transpose buffer of the score reduction
 };
 
 __host__ __device__ inline int lds_pitch(int lmax) { return (lmax + 15) & ~15; }
 __host__ __device__ inline size_t wave_lds_bytes(int lmax, int nmax) {
     int lp = lds_pitch(lmax);
     int np = (nmax + 15) & ~15;
-    size_t b = sizeof(double) * 3 * lp + sizeof(double) * 8 + sizeof(float4) * (5 * lp + kSurvCap) +
-               sizeof(int) * 2 * np + np + sizeof(int) * kAng * kWave;
+    size_t b = sizeof(double) * 3 * lp + sizeof(double) * 8 + sizeof(f4) * (5 * lp + 3 * kMvPad + kSurvCap) +
+               sizeof(int) * 2 * np + np + sizeof(int) * kWave;
     return (b + 15) & ~(size_t)15;
 }
 __host__ __device__ inline size_t replay_lds_bytes(int lmax) {
@@ -94,15 +112,15 @@ __device__ inline WaveLds carve(char* base, int lmax, int nmax) {
     int lp = lds_pitch(lmax);
     int np = (nmax + 15) & ~15;
     WaveLds W;
-    W.X = (double*)base;
+    W.X = (lds_double*)base;
     W.SW = W.X + 3 * lp;
-    W.AD = (float4*)(W.SW + 8);
+    W.AD = (lds_float4*)(W.SW + 8);
     W.MV = W.AD + 2 * lp;
-    W.surv = W.MV + 3 * lp;
-    W.Slo = (int*)(W.surv + kSurvCap);
+    W.surv = W.MV + 3 * (lp + kMvPad);
+    W.Slo = (lds_int*)(W.surv + kSurvCap);
     W.Shi = W.Slo + np;
     W.red = W.Shi + np;
-    W.st = (uint8_t*)(W.red + kAng * kWave);
+    W.st = (lds_u8*)(W.red + kWave);
     return W;
 }
 
@@ -131,7 +149,7 @@ struct Sweep {
 // argument is a value or a pointer so that nothing of the caller's state has
 // to live in scratch memory.  Returns S in the low 32 bits, feasibility in
 // bit 32 and this lane's count of out-of-box lookups from bit 40.
-__device__ __noinline__ uint64_t eval_fp64(const PocketDev* Pp, const double* X, const double* SWp, int lp,
+__device__ __noinline__ uint64_t eval_fp64(const PocketDev* Pp, const lds_double* X, const lds_double* SWp, int lp,
                                            const uint8_t* mvl, int m, const uint16_t* pairs, int npairs, int side,
                                            double cd2, int deg) {
     const PocketDev& P = *Pp;
@@ -139,9 +157,9 @@ __device__ __noinline__ uint64_t eval_fp64(const PocketDev* Pp, const double* X,
     const double kx = uniform_d(SWp[0]), ky = uniform_d(SWp[1]), kz = uniform_d(SWp[2]);
     const double px = uniform_d(SWp[3]), py = uniform_d(SWp[4]), pz = uniform_d(SWp[5]);
     const Mat3 R = axis_angle(kx, ky, kz, deg);
-    const double* Xx = X;
-    const double* Xy = X + lp;
-    const double* Xz = X + 2 * lp;
+    const lds_double* Xx = X;
+    const lds_double* Xy = X + lp;
+    const lds_double* Xz = X + 2 * lp;
     int S = 0, oob = 0;
     for (int j = lane; j < m; j += kWave) {
         int i = ldg(mvl + j);
@@ -182,7 +200,7 @@ __device__ __forceinline__ void bump_block(const Sweep& sw, const WaveLds& W, in
             uint16_t pr = ldg(sw.pairs + q);
             int li = pr & 0xff, ri = pr >> 8;
             int m = sw.side == 0 ? li : ri, f = sw.side == 0 ? ri : li;
-            const float4 um = W.AD[2 * m], wm = W.AD[2 * m + 1], uf = W.AD[2 * f], wf = W.AD[2 * f + 1];
+            const f4 um = W.AD[2 * m], wm = W.AD[2 * m + 1], uf = W.AD[2 * f], wf = W.AD[2 * f + 1];
             float kk = um.w * uf.w;
             float uv = um.x * uf.x + um.y * uf.y + um.z * uf.z;
             float vw = uf.x * wm.x + uf.y * wm.y + uf.z * wm.z;
@@ -207,14 +225,15 @@ __device__ __forceinline__ void bump_block(const Sweep& sw, const WaveLds& W, in
 }
 
 // Score pass over the candidate angles base + k*stride (k < n).  Lanes are
-// (k0 < NB, atom group g < 64/NB); a super-block covers up to kAng blocks of
-// NB angles, and a lane scores the angles k0 + NB*a (a < kAng) of its atoms,
-// so each atom's coefficients are read from LDS once for up to kAng angles
-// and up to kAtU*kAng distance-grid gathers are in flight.  Atoms past the end of
-// the moving list, and atoms whose cell is not certain, read the zero sentinel
-// cell.  The cell test is branch-free; with BOX the grid bounds are tested
-// per atom, otherwise the sweep set-up has proven that every moving atom stays
-// inside the box.  Writes W.Slo / W.Shi per candidate.
+// (k0 < NB, atom group g < 64/NB): a lane scores angle kb + k0 over the atoms
+// g, g + G, ... of the moving list, kAtU atoms per step so that kAtU
+// distance-grid gathers are in flight.  The moving list is followed by
+// kMvPad rows whose position is the zero sentinel cell (certain, D = 0), so
+// the steps need no end-of-list masking; an atom whose cell is not certain
+// reads the sentinel too and marks its candidate uncertain (a ballot mask in
+// scalar registers).  With BOX the grid bounds are tested per atom, otherwise
+// the sweep set-up has proven that every moving atom stays inside the box.
+// Writes W.Slo / W.Shi per candidate.
 template <int NB>
 __device__ __forceinline__ uint32_t fold_groups(uint64_t m) {
     // OR together the bits of lanes k0 + NB*g over g: result bit k0
@@ -224,96 +243,65 @@ __device__ __forceinline__ uint32_t fold_groups(uint64_t m) {
 }
 
 template <int NB, bool BOX>
-__device__ __forceinline__ void score_pass(const PocketDev& P, const Sweep& sw, const WaveLds& W, const float* trig,
+__device__ __forceinline__ void score_pass(const PocketDev& P, const Sweep& sw, const WaveLds& W, const lds_float* trig,
                                            int base, int stride, int n) {
+    static_assert(kWave / NB * kAtU <= kMvPad + 1, "sentinel rows must cover a step");
     const int lane = lane_id();
     constexpr int G = kWave / NB;
     const int k0 = lane & (NB - 1), g = lane / NB;
     const float fnx = (float)P.dim[0], fny = (float)P.dim[1], fnz = (float)P.dim[2];
-    const float fsy = fnx, fsz = fnx * fny;  // exact: the box holds fewer than 2^24 cells
-    const float fsent = (float)P.n_cells;
+    // byte offsets 2 * (z nx ny + y nx + x) in FP32: every partial result is an
+    // even integer below 2^25, hence exact
+    const float fsy2 = 2.f * fnx, fsz2 = 2.f * fnx * fny;
+    const float fsent2 = 2.f * (float)P.n_cells;
     const float glo = sw.gcell, ghi = 1.f - sw.gcell;
     const int m = sw.m;
-    for (int kb = 0; kb < n; kb += NB * kAng) {
-        const int A = min(kAng, (n - kb + NB - 1) / NB);
-        float c[kAng], s[kAng];
-        bool av[kAng];
-#pragma unroll
-        for (int a = 0; a < kAng; a++) {
-            const int k = kb + k0 + NB * a;
-            av[a] = (a < A) & (k < n);
-            const int deg = base + (av[a] ? k : 0) * stride;
-            c[a] = trig[deg];
-            s[a] = trig[360 + deg];
-        }
-        int sum[kAng];
-        bool bad[kAng];
-#pragma unroll
-        for (int a = 0; a < kAng; a++) {
-            sum[a] = 0;
-            bad[a] = false;
-        }
-        for (int j = g; j < m; j += kAtU * G) {
-            uint32_t off[kAtU][kAng];
+    const __attribute__((address_space(1))) char* edt = (const __attribute__((address_space(1))) char*)P.edt;
+    for (int kb = 0; kb < n; kb += NB) {
+        const int k = kb + k0;
+        const int deg = base + (k < n ? k : 0) * stride;
+        const float c = trig[deg], s = trig[360 + deg];
+        int sum = 0;
+        uint64_t badm = 0;
+        const lds_float4* row = W.MV + 3 * g;
+        for (int j = g; j < m; j += kAtU * G, row += 3 * kAtU * G) {
+            uint32_t off[kAtU];
 #pragma unroll
             for (int t = 0; t < kAtU; t++) {
-                const int jj = j + t * G;
-                const bool live = jj < m;
-                const int ja = live ? jj : j;
-                const float4 p0 = W.MV[3 * ja], u = W.MV[3 * ja + 1], v = W.MV[3 * ja + 2];
-#pragma unroll
-                for (int a = 0; a < kAng; a++) {
-                    off[t][a] = (uint32_t)fsent;
-                    if (a < A) {
-                        const float yx = fmaf(s[a], v.x, fmaf(c[a], u.x, p0.x));
-                        const float yy = fmaf(s[a], v.y, fmaf(c[a], u.y, p0.y));
-                        const float yz = fmaf(s[a], v.z, fmaf(c[a], u.z, p0.z));
-                        const float fx = floorf(yx), fy = floorf(yy), fz = floorf(yz);
-                        const float rx = __builtin_amdgcn_fractf(yx), ry = __builtin_amdgcn_fractf(yy),
-                                    rz = __builtin_amdgcn_fractf(yz);
-                        bool sure = (fminf(fminf(rx, ry), rz) >= glo) & (fmaxf(fmaxf(rx, ry), rz) <= ghi);
-                        if (BOX)
-                            sure = sure & (fx >= 0.f) & (fx < fnx) & (fy >= 0.f) & (fy < fny) & (fz >= 0.f) &
-                                   (fz < fnz);
-                        const bool use = live & av[a];
-                        bad[a] = bad[a] | (use & !sure);
-                        const float fi = fmaf(fz, fsz, fmaf(fy, fsy, fx));
-                        off[t][a] = (uint32_t)((use & sure) ? fi : fsent);
-                    }
+                const f4 p0 = row[3 * t * G], u = row[3 * t * G + 1], v = row[3 * t * G + 2];
+                const float yx = fmaf(s, v.x, fmaf(c, u.x, p0.x));
+                const float yy = fmaf(s, v.y, fmaf(c, u.y, p0.y));
+                const float yz = fmaf(s, v.z, fmaf(c, u.z, p0.z));
+                const float fx = floorf(yx), fy = floorf(yy), fz = floorf(yz);
+                const float rx = __builtin_amdgcn_fractf(yx), ry = __builtin_amdgcn_fractf(yy),
+                            rz = __builtin_amdgcn_fractf(yz);
+                bool sure = (fminf(fminf(rx, ry), rz) >= glo) & (fmaxf(fmaxf(rx, ry), rz) <= ghi);
+                bool live = true;
+                if (BOX) {
+                    live = j + t * G < m;
+                    sure = sure & (fx >= 0.f) & (fx < fnx) & (fy >= 0.f) & (fy < fny) & (fz >= 0.f) & (fz < fnz);
                 }
+                badm |= __ballot(live & !sure);
+                const float fi2 = fmaf(fz, fsz2, fmaf(fy, fsy2, fx + fx));
+                off[t] = (uint32_t)((live & sure) ? fi2 : fsent2);
             }
+            int d = 0;
 #pragma unroll
-            for (int a = 0; a < kAng; a++)
-                if (a < A) {
-                    int d = 0;
-#pragma unroll
-                    for (int t = 0; t < kAtU; t++) d += (int)ldg(P.edt + off[t][a]);
-                    sum[a] += d;
-                }
+            for (int t = 0; t < kAtU; t++) d += (int)*(const __attribute__((address_space(1))) uint16_t*)(edt + off[t]);
+            sum += d;
         }
-        // sum the groups of each angle through LDS; uncertain flags by ballot
-        uint32_t badbits[kAng];
-#pragma unroll
-        for (int a = 0; a < kAng; a++) {
-            badbits[a] = 0;
-            if (a < A) {
-                W.red[a * kWave + lane] = sum[a];
-                badbits[a] = fold_groups<NB>(__ballot(bad[a]));
-            }
-        }
+        // sum the groups of each angle through LDS; uncertain flags folded from the ballots
+        W.red[lane] = sum;
+        const uint32_t badbits = fold_groups<NB>(badm);
         wave_sync();
-        for (int L = lane; L < A * NB; L += kWave) {
-            const int a = L / NB, kk = L & (NB - 1);
-            const int k = kb + kk + NB * a;
-            if (k < n) {
+        if (lane < NB) {
+            const int kk = kb + lane;
+            if (kk < n) {
                 int tot = 0;
 #pragma unroll
-                for (int gg = 0; gg < G; gg++) tot += W.red[a * kWave + kk + gg * NB];
-                uint32_t bb = badbits[0];
-#pragma unroll
-                for (int aa = 1; aa < kAng; aa++) bb = a == aa ? badbits[aa] : bb;
-                W.Slo[k] = tot;
-                W.Shi[k] = ((bb >> kk) & 1u) ? kOpenHi : tot;
+                for (int gg = 0; gg < G; gg++) tot += W.red[lane + gg * NB];
+                W.Slo[kk] = tot;
+                W.Shi[kk] = ((badbits >> lane) & 1u) ? kOpenHi : tot;
             }
         }
         wave_sync();
@@ -325,7 +313,7 @@ __device__ __forceinline__ void score_pass(const PocketDev& P, const Sweep& sw, 
 // on ties) or -1 when none is feasible.
 template <int NB, int PPL>
 __device__ int eval_candidates(const PocketDev& P, const BatchDev& B, const Sweep& sw, const WaveLds& W,
-                               const float* trig, int base, int stride, int n, Acc& acc) {
+                               const lds_float* trig, int base, int stride, int n, Acc& acc) {
     const int lane = lane_id();
     constexpr int G = kWave / NB;
     acc.poses += n;
@@ -349,12 +337,12 @@ __device__ int eval_candidates(const PocketDev& P, const BatchDev& B, const Swee
             float d0 = 3.0e38f, d1 = 3.0e38f;
             int q = 0;
             for (; q + 1 < sw.nsurv; q += 2) {
-                const float4 e0 = W.surv[q], e1 = W.surv[q + 1];
+                const f4 e0 = W.surv[q], e1 = W.surv[q + 1];
                 d0 = fminf(d0, fmaf(e0.z, s, fmaf(e0.y, c, e0.x)));
                 d1 = fminf(d1, fmaf(e1.z, s, fmaf(e1.y, c, e1.x)));
             }
             if (q < sw.nsurv) {
-                const float4 e0 = W.surv[q];
+                const f4 e0 = W.surv[q];
                 d0 = fminf(d0, fmaf(e0.z, s, fmaf(e0.y, c, e0.x)));
             }
             const float d = fminf(d0, d1);
@@ -426,9 +414,9 @@ __device__ int eval_candidates(const PocketDev& P, const BatchDev& B, const Swee
 // stored in W.SW), from the current master coordinates.
 __device__ __forceinline__ void sweep_axis(const WaveLds& W, int lp, int a, int c, int piv) {
     if (lane_id() == 0) {
-        const double* Xx = W.X;
-        const double* Xy = W.X + lp;
-        const double* Xz = W.X + 2 * lp;
+        const lds_double* Xx = W.X;
+        const lds_double* Xy = W.X + lp;
+        const lds_double* Xz = W.X + 2 * lp;
         double ax = Xx[c] - Xx[a], ay = Xy[c] - Xy[a], az = Xz[c] - Xz[a];
         double nrm = sqrt(ax * ax + ay * ay + az * az);
         W.SW[0] = ax / nrm;
@@ -469,9 +457,9 @@ __device__ __forceinline__ void sweep_setup(const PocketDev& P, const BatchDev& 
                                          const SideInfo& ri, int side, const WaveLds& W, Sweep& sw) {
     const int lane = lane_id();
     const int lp = lds_pitch(B.lmax);
-    const double* Xx = W.X;
-    const double* Xy = W.X + lp;
-    const double* Xz = W.X + 2 * lp;
+    const lds_double* Xx = W.X;
+    const lds_double* Xy = W.X + lp;
+    const lds_double* Xz = W.X + 2 * lp;
     sw.lp = lp;
     sw.side = side;
     sw.mvl = B.mv + ri.mv_off;
@@ -487,8 +475,8 @@ __device__ __forceinline__ void sweep_setup(const PocketDev& P, const BatchDev& 
         double ux = Xx[i] - px, uy = Xy[i] - py, uz = Xz[i] - pz;
         double ku = kx * ux + ky * uy + kz * uz;
         double uu = ux * ux + uy * uy + uz * uz;
-        W.AD[2 * i] = make_float4((float)ux, (float)uy, (float)uz, (float)ku);
-        W.AD[2 * i + 1] = make_float4((float)(ky * uz - kz * uy), (float)(kz * ux - kx * uz),
+        W.AD[2 * i] = mk4((float)ux, (float)uy, (float)uz, (float)ku);
+        W.AD[2 * i + 1] = mk4((float)(ky * uz - kz * uy), (float)(kz * ux - kx * uz),
                                       (float)(kx * uy - ky * ux), (float)uu);
         r2max = fmaxf(r2max, (float)uu);
     }
@@ -505,9 +493,9 @@ __device__ __forceinline__ void sweep_setup(const PocketDev& P, const BatchDev& 
         double az0 = (pz + ku * kz) * ih - (double)P.lo[2];
         double Ux = (ux - ku * kx) * ih, Uy = (uy - ku * ky) * ih, Uz = (uz - ku * kz) * ih;
         double Vx = (ky * uz - kz * uy) * ih, Vy = (kz * ux - kx * uz) * ih, Vz = (kx * uy - ky * ux) * ih;
-        W.MV[3 * j] = make_float4((float)ax0, (float)ay0, (float)az0, 0.f);
-        W.MV[3 * j + 1] = make_float4((float)Ux, (float)Uy, (float)Uz, 0.f);
-        W.MV[3 * j + 2] = make_float4((float)Vx, (float)Vy, (float)Vz, 0.f);
+        W.MV[3 * j] = mk4((float)ax0, (float)ay0, (float)az0, 0.f);
+        W.MV[3 * j + 1] = mk4((float)Ux, (float)Uy, (float)Uz, 0.f);
+        W.MV[3 * j + 2] = mk4((float)Vx, (float)Vy, (float)Vz, 0.f);
         // the circle's extent along axis a is P0_a +- sqrt(U_a^2 + V_a^2): keep it
         // 0.01 cell inside the box on both sides
         const double ex2 = Ux * Ux + Vx * Vx, ey2 = Uy * Uy + Vy * Vy, ez2 = Uz * Uz + Vz * Vz;
@@ -523,6 +511,14 @@ __device__ __forceinline__ void sweep_setup(const PocketDev& P, const BatchDev& 
     sw.inside = __ballot(outside) == 0;
     amax = wave_maxf(amax);
     umax = wave_maxf(umax);
+    // sentinel rows after the list: U = V = 0 at the centre of cell (0, 0, nz),
+    // whose linear index is the zero sentinel cell
+    if (lane < kMvPad) {
+        const f4 z4 = mk4(0.f, 0.f, 0.f, 0.f);
+        W.MV[3 * (sw.m + lane)] = mk4(0.5f, 0.5f, (float)P.dim[2] + 0.5f, 0.f);
+        W.MV[3 * (sw.m + lane) + 1] = z4;
+        W.MV[3 * (sw.m + lane) + 2] = z4;
+    }
     // Rounding guards (u = 2^-24), each doubled for safety and with the maxima
     // rounded up by 1 %:
     //  cell: Y = fma(s, V, fma(c, U, P0)) from P0, U, V rounded once from FP64
@@ -558,7 +554,7 @@ __device__ __forceinline__ void sweep_setup(const PocketDev& P, const BatchDev& 
                 const uint16_t pr = prs[t];
                 int li = pr & 0xff, ri2 = pr >> 8;
                 int m = side == 0 ? li : ri2, f = side == 0 ? ri2 : li;
-                const float4 um = W.AD[2 * m], wm = W.AD[2 * m + 1], uf = W.AD[2 * f], wf = W.AD[2 * f + 1];
+                const f4 um = W.AD[2 * m], wm = W.AD[2 * m + 1], uf = W.AD[2 * f], wf = W.AD[2 * f + 1];
                 float kk = um.w * uf.w;
                 A = wm.w + wf.w - 2.f * kk;
                 Bv = -2.f * (um.x * uf.x + um.y * uf.y + um.z * uf.z - kk);
@@ -569,7 +565,7 @@ __device__ __forceinline__ void sweep_setup(const PocketDev& P, const BatchDev& 
             const uint64_t mk = __ballot(keep);
             const int pos =
                 nsurv + __builtin_amdgcn_mbcnt_hi((uint32_t)(mk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0));
-            if (keep && pos < kSurvCap) W.surv[pos] = make_float4(A, Bv, Cv, 0.f);
+            if (keep && pos < kSurvCap) W.surv[pos] = mk4(A, Bv, Cv, 0.f);
             nsurv += __popcll(mk);
         }
     }
@@ -585,9 +581,9 @@ __device__ __forceinline__ void commit(const uint8_t* mvl, int m, const WaveLds&
     const double kx = uniform_d(W.SW[0]), ky = uniform_d(W.SW[1]), kz = uniform_d(W.SW[2]);
     const double px = uniform_d(W.SW[3]), py = uniform_d(W.SW[4]), pz = uniform_d(W.SW[5]);
     const Mat3 R = axis_angle(kx, ky, kz, deg);
-    double* Xx = W.X;
-    double* Xy = W.X + lp;
-    double* Xz = W.X + 2 * lp;
+    lds_double* Xx = W.X;
+    lds_double* Xy = W.X + lp;
+    lds_double* Xz = W.X + 2 * lp;
     for (int j = lane; j < m; j += kWave) {
         int i = mvl[j];
         double ox, oy, oz;
@@ -620,9 +616,9 @@ __device__ __forceinline__ void endpoint(const PocketDev& P, const BatchDev& B, 
                                       int& S, bool& clash, Acc& acc) {
     const int lane = lane_id();
     const int lp = lds_pitch(B.lmax);
-    const double* Xx = W.X;
-    const double* Xy = W.X + lp;
-    const double* Xz = W.X + 2 * lp;
+    const lds_double* Xx = W.X;
+    const lds_double* Xy = W.X + lp;
+    const lds_double* Xz = W.X + 2 * lp;
     int s = 0;
     for (int i = lane; i < L.l; i += kWave) s += D_exact(P, Xx[i], Xy[i], Xz[i], acc.oob);
     S = wave_sum(s);
@@ -640,7 +636,7 @@ __device__ __forceinline__ void endpoint(const PocketDev& P, const BatchDev& B, 
 // The greedy sweep of one orientation (Alg. 2).
 template <int NB, int PPL>
 __device__ void dock_orientation(const PocketDev& P, const BatchDev& B, int lig, int o, const WaveLds& W,
-                                 const float* trig, Acc& acc) {
+                                 const lds_float* trig, Acc& acc) {
     const LigMeta L = B.lig[lig];
     place(P, B, L, o, W);
     const int nrec = B.reps * L.nr * 2;
@@ -706,7 +702,7 @@ __global__ void __launch_bounds__(512) dock_ligand_kernel(const PocketDev* __res
     const WaveLds W = carve(smem + wave * wave_lds_bytes(B.lmax, nmax), B.lmax, nmax);
     const int o = uniform(blockIdx.x * (blockDim.x / kWave) + wave);
     Acc acc;
-    if (o < B.n_orient) dock_orientation<NB, PPL>(P, B, lig, o, W, trig, acc);
+    if (o < B.n_orient) dock_orientation<NB, PPL>(P, B, lig, o, W, (const lds_float*)trig, acc);
     flush(counters, acc);
 }
 
@@ -735,7 +731,7 @@ __global__ void __launch_bounds__(512) dock_persistent_kernel(const PocketDev* _
         if (item >= B.n_items) break;
         const int lig = uniform(B.items[2 * item]), o0 = uniform(B.items[2 * item + 1]);
         const int o1 = min(o0 + B.orient_per_item, B.n_orient);
-        for (int o = o0; o < o1; o++) dock_orientation<NB, PPL>(P, B, lig, o, W, trig, acc);
+        for (int o = o0; o < o1; o++) dock_orientation<NB, PPL>(P, B, lig, o, W, (const lds_float*)trig, acc);
     }
     flush(counters, acc);
 }
@@ -810,7 +806,7 @@ __global__ void __launch_bounds__(256) replay_kernel(PocketDev P, BatchDev B, co
     const int lig = idx / B.top_k;
     WaveLds W{};
     const int lp = lds_pitch(B.lmax);
-    W.X = (double*)(smem + wave * replay_lds_bytes(B.lmax));
+    W.X = (lds_double*)(smem + wave * replay_lds_bytes(B.lmax));
     W.SW = W.X + 3 * lp;
     const LigMeta L = B.lig[lig];
     const int o = recs[idx].orient;
@@ -893,7 +889,6 @@ static hipError_t launch_dock_nb(const DockLaunch& L, const Tiling& t, bool pers
 
 hipError_t launch_dock(const DockLaunch& L, const Tiling& t, bool persistent, int lig, int grid, hipStream_t s) {
     switch (t.angle_block) {
-        case 4: return launch_dock_nb<4>(L, t, persistent, lig, grid, s);
         case 8: return launch_dock_nb<8>(L, t, persistent, lig, grid, s);
         case 16: return launch_dock_nb<16>(L, t, persistent, lig, grid, s);
         case 32: return launch_dock_nb<32>(L, t, persistent, lig, grid, s);

@@ -25,6 +25,12 @@
 
 namespace gd {
 
+// The tilings the docking kernel is instantiated for.
+bool tiling_supported(int waves_per_block, int angle_block, int pairs_per_lane) {
+    auto in = [](int v, std::initializer_list<int> set) { return std::find(set.begin(), set.end(), v) != set.end(); };
+    return in(waves_per_block, {1, 2, 4, 8}) && in(angle_block, {8, 16, 32}) && in(pairs_per_lane, {1, 2, 4, 8});
+}
+
 // --------------------------------------------------------------------------
 // errors
 
@@ -746,7 +752,7 @@ gd_status prepare_batch(const gd_pocket* pocket, const gd_ligands* L, const gd_k
     if ((e = B->devcopy.upload(&B->dev, sizeof(BatchDev), stream)) != hipSuccess) return hip_fail(e, "gd_prepare_batch");
     if (const char* env = getenv("GD_TILING")) {
         int w, nb, ppl;
-        if (sscanf(env, "%d,%d,%d", &w, &nb, &ppl) == 3) {
+        if (sscanf(env, "%d,%d,%d", &w, &nb, &ppl) == 3 && tiling_supported(w, nb, ppl)) {
             B->tiling.waves_per_block = w;
             B->tiling.angle_block = nb;
             B->tiling.pairs_per_lane = ppl;
@@ -961,9 +967,7 @@ gd_status gd_batch_read_timing(gd_batch* B, float* ms_out, int32_t max_n, int32_
 gd_status gd_batch_set_tiling(gd_batch* B, const gd_tiling* t) {
     clear_error();
     if (!B || !t) return fail(GD_ERR_ARG, "gd_batch_set_tiling: null argument");
-    auto in = [](int v, std::initializer_list<int> s) { return std::find(s.begin(), s.end(), v) != s.end(); };
-    if (!in(t->waves_per_block, {1, 2, 4, 8}) || !in(t->angle_block, {4, 8, 16, 32}) ||
-        !in(t->pairs_per_lane, {1, 2, 4, 8}))
+    if (!tiling_supported(t->waves_per_block, t->angle_block, t->pairs_per_lane))
         return fail(GD_ERR_ARG, "gd_batch_set_tiling: unsupported tiling");
     B->tiling.waves_per_block = t->waves_per_block;
     B->tiling.angle_block = t->angle_block;

@@ -40,6 +40,7 @@ gd_status hip_fail(hipError_t e, const char* where);
 void clear_error();
 const char* last_error();
 int tile_size(int hp);
+bool tiling_supported(int waves_per_block, int angle_block, int pairs_per_lane);
 
 // Host topology of a ligand set for scoring: atom counts and far pairs.
 struct TopoHost {
