@@ -93,7 +93,6 @@ struct WaveLds {
     lds_int* Shi;    // [nmax] upper bound
     lds_u8* st;      // [nmax] bit0: certain bump, bit1: possible bump
     lds_float4* surv;  // [kSurvCap] (A, B, C, -) of the pairs that survive the sweep's prune
-    lds_int* red;    // [64] transpose buffer of the score reduction
 };
 
 __host__ __device__ inline int lds_pitch(int lmax) { return (lmax + 15) & ~15; }
@@ -101,7 +100,7 @@ __host__ __device__ inline size_t wave_lds_bytes(int lmax, int nmax) {
     int lp = lds_pitch(lmax);
     int np = (nmax + 15) & ~15;
     size_t b = sizeof(double) * 3 * lp + sizeof(double) * 8 + sizeof(f4) * (5 * lp + 3 * kMvPad + kSurvCap) +
-               sizeof(int) * 2 * np + np + sizeof(int) * kWave;
+               sizeof(int) * 2 * np + np;
     return (b + 15) & ~(size_t)15;
 }
 __host__ __device__ inline size_t replay_lds_bytes(int lmax) {
@@ -119,8 +118,7 @@ __device__ inline WaveLds carve(char* base, int lmax, int nmax) {
     W.surv = W.MV + 3 * (lp + kMvPad);
     W.Slo = (lds_int*)(W.surv + kSurvCap);
     W.Shi = W.Slo + np;
-    W.red = W.Shi + np;
-    W.st = (lds_u8*)(W.red + kWave);
+    W.st = (lds_u8*)(W.Shi + np);
     return W;
 }
 
@@ -186,39 +184,43 @@ __device__ __noinline__ uint64_t eval_fp64(const PocketDev* Pp, const lds_double
 // candidate is re-evaluated in FP64 if it can still win its sweep.
 constexpr int kOpenHi = 0x20000000;
 
-// K pairs per lane starting at q0: FP32 A, B, C from the per-atom data, then
-// for each of the nw angles of the word a certain / possible bump bit.
+// FP32 coefficients of d^2(theta) = A + 2 B cos(theta) + 2 C sin(theta) for a
+// straddling pair (li on the left, ri on the right) in the frame of the
+// current sweep, from the per-atom data u = X - p, k.u, k x u, |u|^2:
+//   A = |u_l|^2 + |u_r|^2 - 2 (k.u_l)(k.u_r),   B = (k.u_l)(k.u_r) - u_l.u_r,
+//   C = -(k x u_l).u_r when the left side turns; turning the right side
+//   instead flips the sign of C (csign = -1 left, +1 right).
+__device__ __forceinline__ f4 pair_coeffs(const WaveLds& W, uint32_t pr, float csign) {
+    const int li = pr & 0xff, ri = pr >> 8;
+    const f4 ul = W.AD[2 * li], wl = W.AD[2 * li + 1], ur = W.AD[2 * ri], wr = W.AD[2 * ri + 1];
+    const float kk = ul.w * ur.w;
+    const float A = fmaf(-2.f, kk, wl.w + wr.w);
+    const float uv = fmaf(ul.z, ur.z, fmaf(ul.y, ur.y, ul.x * ur.x));
+    const float vw = fmaf(ur.z, wl.z, fmaf(ur.y, wl.y, ur.x * wl.x));
+    return mk4(A, kk - uv, csign * vw, 0.f);
+}
+
+// K pairs per lane starting at q0 (lanes = straddling pairs), then for each
+// of the nw angles of the word (c2 = 2 cos, s2 = 2 sin per lane) a certain /
+// possible bump bit.  Used when more pairs survive the prune than the LDS list
+// holds.
 template <int K>
-__device__ __forceinline__ void bump_block(const Sweep& sw, const WaveLds& W, int q0, int nq, int nw, float cl,
-                                           float sl, uint64_t& cert, uint64_t& maybe) {
+__device__ __forceinline__ void bump_block(const Sweep& sw, const WaveLds& W, int q0, int nq, int nw, float c2,
+                                           float s2, uint64_t& cert, uint64_t& maybe) {
     const int lane = lane_id();
-    float A[K], Bc[K], Cs[K];
+    const float csign = sw.side == 0 ? -1.f : 1.f;
+    f4 e[K];
 #pragma unroll
     for (int t = 0; t < K; t++) {
         const int q = q0 + t * kWave + lane;
-        if (q < nq) {
-            uint16_t pr = ldg(sw.pairs + q);
-            int li = pr & 0xff, ri = pr >> 8;
-            int m = sw.side == 0 ? li : ri, f = sw.side == 0 ? ri : li;
-            const f4 um = W.AD[2 * m], wm = W.AD[2 * m + 1], uf = W.AD[2 * f], wf = W.AD[2 * f + 1];
-            float kk = um.w * uf.w;
-            float uv = um.x * uf.x + um.y * uf.y + um.z * uf.z;
-            float vw = uf.x * wm.x + uf.y * wm.y + uf.z * wm.z;
-            A[t] = wm.w + wf.w - 2.f * kk;
-            Bc[t] = -2.f * (uv - kk);
-            Cs[t] = -2.f * vw;
-        } else {
-            A[t] = 3.0e38f;
-            Bc[t] = 0.f;
-            Cs[t] = 0.f;
-        }
+        e[t] = q < nq ? pair_coeffs(W, ldg(sw.pairs + q), csign) : mk4(3.0e38f, 0.f, 0.f, 0.f);
     }
     for (int k = 0; k < nw; k++) {
-        const float c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cl), k));
-        const float s = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sl), k));
-        float d = fmaf(Cs[0], s, fmaf(Bc[0], c, A[0]));
+        const float c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(c2), k));
+        const float s = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(s2), k));
+        float d = fmaf(e[0].z, s, fmaf(e[0].y, c, e[0].x));
 #pragma unroll
-        for (int t = 1; t < K; t++) d = fminf(d, fmaf(Cs[t], s, fmaf(Bc[t], c, A[t])));
+        for (int t = 1; t < K; t++) d = fminf(d, fmaf(e[t].z, s, fmaf(e[t].y, c, e[t].x)));
         if (__ballot(d < sw.thr_lo)) cert |= 1ull << k;
         if (__ballot(d < sw.thr_hi)) maybe |= 1ull << k;
     }
@@ -240,6 +242,22 @@ __device__ __forceinline__ uint32_t fold_groups(uint64_t m) {
 #pragma unroll
     for (int sh = 32; sh >= NB; sh >>= 1) m |= m >> sh;
     return (uint32_t)m & (uint32_t)((1ull << NB) - 1);
+}
+
+// Sum over the lanes k0 + NB*g (g < 64/NB) in every lane: swaps of rows of
+// eight lanes (DPP rotate by 8 within a row of 16), then of rows of 16 and 32
+// lanes (the gfx950 permlane swaps: the two outputs together hold a lane's
+// value and its partner's, whichever output holds which).
+template <int NB>
+__device__ __forceinline__ int group_sum(int v) {
+    static_assert(NB >= 8 && NB <= 32, "angle blocks of 8, 16 or 32");
+    if (NB == 8) v += __builtin_amdgcn_update_dpp(0, v, 0x128, 0xf, 0xf, false);  // row_ror:8
+    if (NB <= 16) {
+        const auto p = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        v = (int)p[0] + (int)p[1];
+    }
+    const auto q = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return (int)q[0] + (int)q[1];
 }
 
 template <int NB, bool BOX>
@@ -290,22 +308,15 @@ __device__ __forceinline__ void score_pass(const PocketDev& P, const Sweep& sw, 
             for (int t = 0; t < kAtU; t++) d += (int)*(const __attribute__((address_space(1))) uint16_t*)(edt + off[t]);
             sum += d;
         }
-        // sum the groups of each angle through LDS; uncertain flags folded from the ballots
-        W.red[lane] = sum;
+        // sum the groups of each angle across lanes; uncertain flags folded from the ballots
+        const int tot = group_sum<NB>(sum);
         const uint32_t badbits = fold_groups<NB>(badm);
-        wave_sync();
-        if (lane < NB) {
-            const int kk = kb + lane;
-            if (kk < n) {
-                int tot = 0;
-#pragma unroll
-                for (int gg = 0; gg < G; gg++) tot += W.red[lane + gg * NB];
-                W.Slo[kk] = tot;
-                W.Shi[kk] = ((badbits >> lane) & 1u) ? kOpenHi : tot;
-            }
+        if (lane < NB && kb + lane < n) {
+            W.Slo[kb + lane] = tot;
+            W.Shi[kb + lane] = ((badbits >> lane) & 1u) ? kOpenHi : tot;
         }
-        wave_sync();
     }
+    wave_sync();
 }
 
 // Evaluate the candidate angles base + k*stride (k < n) of the current sweep;
@@ -324,7 +335,7 @@ __device__ int eval_candidates(const PocketDev& P, const BatchDev& B, const Swee
         score_pass<NB, true>(P, sw, W, trig, base, stride, n);
 
     // ---- bump pass.  After a successful prune: lanes = candidate angles (64
-    // per word), each takes the minimum of d^2 = A + B cos + C sin over the
+    // per word), each takes the minimum of d^2 = A + 2B cos + 2C sin over the
     // survivors' coefficients (broadcast from LDS); a certain bump is
     // min < cd^2 - guard, a possible one min < cd^2 + guard.  Otherwise (more
     // survivors than the LDS list holds): lanes = straddling pairs, looping
@@ -333,7 +344,7 @@ __device__ int eval_candidates(const PocketDev& P, const BatchDev& B, const Swee
         for (int w0 = 0; w0 < n; w0 += kWave) {
             const int k = w0 + lane;
             const int deg = base + (k < n ? k : 0) * stride;
-            const float c = trig[deg], s = trig[360 + deg];
+            const float c = 2.f * trig[deg], s = 2.f * trig[360 + deg];
             float d0 = 3.0e38f, d1 = 3.0e38f;
             int q = 0;
             for (; q + 1 < sw.nsurv; q += 2) {
@@ -354,8 +365,8 @@ __device__ int eval_candidates(const PocketDev& P, const BatchDev& B, const Swee
             float cl = 0.f, sl = 0.f;
             if (lane < nw) {
                 int deg = base + (w0 + lane) * stride;
-                cl = trig[deg];
-                sl = trig[360 + deg];
+                cl = 2.f * trig[deg];
+                sl = 2.f * trig[360 + deg];
             }
             uint64_t cert = 0, maybe = 0;
             const int nq = sw.npairs;
@@ -523,18 +534,20 @@ __device__ __forceinline__ void sweep_setup(const PocketDev& P, const BatchDev& 
     // rounded up by 1 %:
     //  cell: Y = fma(s, V, fma(c, U, P0)) from P0, U, V rounded once from FP64
     //        deviates by <= u (3|P0| + 4|U| + 3|V|) cell units;
-    //  bump: A, B, C formed in FP32 from per-atom data rounded from FP64
-    //        (|u| <= R) carry <= 18, 20 and 10 u R^2; their evaluation adds
-    //        <= u (3|A| + 4|B| + 3|C|) <= 26 u R^2: 74 u R^2 in all.
+    //  bump: A, 2B, 2C formed in FP32 from per-atom data rounded from FP64
+    //        (|u| <= R) carry <= 18, 20 and 10 u R^2; their evaluation with
+    //        the rounded cos/sin adds <= u (3|A| + 4|2B| + 3|2C|) <= 26 u R^2:
+    //        74 u R^2 in all.
     const double u32 = 1.0 / 16777216.0;
     sw.gcell = (float)(2.0 * u32 * (3.0 * 1.01 * amax + 7.0 * 1.01 * umax) + 1e-6);
     const double gc = 2.0 * u32 * 74.0 * 1.01 * (double)r2max + 1e-6;
     sw.thr_lo = (float)(B.cd2 - gc);
     sw.thr_hi = (float)(B.cd2 + gc);
     wave_sync();
-    // Prune: a pair whose smallest distance over a full turn, A - sqrt(B^2 +
-    // C^2), clears the bump distance by more than twice the guard never bumps.
+    // Prune: a pair whose smallest d^2 over a full turn, A - 2 sqrt(B^2 + C^2),
+    // clears the bump distance by more than twice the guard never bumps.
     const float T = (float)(B.cd2 + 2.0 * gc);
+    const float csign = side == 0 ? -1.f : 1.f;
     int nsurv = 0;
     for (int q0 = 0; q0 < sw.npairs; q0 += 4 * kWave) {
         uint16_t prs[4];
@@ -547,25 +560,16 @@ __device__ __forceinline__ void sweep_setup(const PocketDev& P, const BatchDev& 
         for (int t = 0; t < 4; t++) {
             const int q = q0 + t * kWave + lane;
             bool keep = false;
-            float A = 0.f, Bv = 0.f, Cv = 0.f;
+            f4 e = mk4(0.f, 0.f, 0.f, 0.f);
             if (q < sw.npairs) {
-                // the same FP32 expressions as the bump test, so the stored
-                // coefficients equal what it would compute
-                const uint16_t pr = prs[t];
-                int li = pr & 0xff, ri2 = pr >> 8;
-                int m = side == 0 ? li : ri2, f = side == 0 ? ri2 : li;
-                const f4 um = W.AD[2 * m], wm = W.AD[2 * m + 1], uf = W.AD[2 * f], wf = W.AD[2 * f + 1];
-                float kk = um.w * uf.w;
-                A = wm.w + wf.w - 2.f * kk;
-                Bv = -2.f * (um.x * uf.x + um.y * uf.y + um.z * uf.z - kk);
-                Cv = -2.f * (uf.x * wm.x + uf.y * wm.y + uf.z * wm.z);
-                float Am = A - T;
-                keep = !(Am > 0.f && Am * Am > 1.0001f * (Bv * Bv + Cv * Cv));
+                e = pair_coeffs(W, prs[t], csign);
+                const float Am = e.x - T;
+                keep = !((Am > 0.f) & (Am * Am > 4.0004f * fmaf(e.z, e.z, e.y * e.y)));
             }
             const uint64_t mk = __ballot(keep);
             const int pos =
                 nsurv + __builtin_amdgcn_mbcnt_hi((uint32_t)(mk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0));
-            if (keep && pos < kSurvCap) W.surv[pos] = mk4(A, Bv, Cv, 0.f);
+            if (keep && pos < kSurvCap) W.surv[pos] = e;
             nsurv += __popcll(mk);
         }
     }
