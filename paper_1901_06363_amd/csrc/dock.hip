@@ -380,26 +380,26 @@ __device__ int eval_candidates(const PocketDev& P, const BatchDev& B, const Swee
     }
     wave_sync();
 
-    // ---- decision: best certain candidate, then resolve uncertain contenders
-    uint64_t best = ~0ull;
+    // ---- decision: key = S << 9 | position (S of at most 128 moving atoms of
+    // D <= 65535 is below 2^23; a schedule has at most 360 positions): the
+    // lowest certain key, then the uncertain contenders whose lower bound could
+    // still win, re-evaluated in FP64 in position order
+    static_assert(kMaxAtoms * 65535 < (1 << 23), "moving-atom S must fit 23 bits");
+    uint32_t best = 0xffffffffu;
     for (int k0 = 0; k0 < n; k0 += kWave) {
         const int k = k0 + lane;
         if (k < n) {
-            int lo = W.Slo[k], hi = W.Shi[k];
-            if (!(W.st[k] & 2) && lo == hi) {
-                uint64_t key = ((uint64_t)(uint32_t)lo << 16) | (uint64_t)k;
-                best = key < best ? key : best;
-            }
+            const int lo = W.Slo[k], hi = W.Shi[k];
+            if (!(W.st[k] & 2) && lo == hi) best = min(best, ((uint32_t)lo << 9) | (uint32_t)k);
         }
     }
-    best = wave_min_u64(best);
+    best = wave_min_u32(best);
     for (int k0 = 0; k0 < n; k0 += kWave) {
         const int k = k0 + lane;
         bool need = false;
         if (k < n) {
-            int st = W.st[k], lo = W.Slo[k], hi = W.Shi[k];
-            uint64_t key = ((uint64_t)(uint32_t)lo << 16) | (uint64_t)k;
-            need = !(st & 1) && ((st & 2) || lo != hi) && key < best;
+            const int st = W.st[k], lo = W.Slo[k], hi = W.Shi[k];
+            need = !(st & 1) && ((st & 2) || lo != hi) && (((uint32_t)lo << 9) | (uint32_t)k) < best;
         }
         uint64_t mask = __ballot(need);
         while (mask) {
@@ -410,15 +410,11 @@ __device__ int eval_candidates(const PocketDev& P, const BatchDev& B, const Swee
                                          base + kk * stride);
             acc.fallback++;
             acc.oob += (int)(r >> 40);
-            if ((r >> 32) & 1) {
-                const int S = (int)(uint32_t)r;
-                uint64_t key = ((uint64_t)(uint32_t)S << 16) | (uint64_t)kk;
-                best = key < best ? key : best;
-            }
+            if ((r >> 32) & 1) best = min(best, ((uint32_t)r << 9) | (uint32_t)kk);
         }
     }
     wave_sync();
-    return best == ~0ull ? -1 : (int)(best & 0xffff);
+    return best == 0xffffffffu ? -1 : (int)(best & 511u);
 }
 
 // Axis k = (X_c - X_a)/|X_c - X_a| and pivot of one fragment sweep (FP64,
