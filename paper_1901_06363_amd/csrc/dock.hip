@@ -81,8 +81,7 @@ typedef __attribute__((address_space(3))) int lds_int;
 typedef __attribute__((address_space(3))) uint8_t lds_u8;
 
 constexpr int kSurvCap = 128;  // straddling pairs that can still bump in one sweep (LDS list)
-constexpr int kAtU = 4;        // atoms per lane per step of the score pass
-constexpr int kMvPad = 32;     // sentinel rows after the moving list (covers a step at >= 8 angles per block)
+constexpr int kMvPad = 32;     // sentinel rows after the moving list (cover one step of the score pass)
 
 struct WaveLds {
     lds_double* X;   // [3][lp] FP64 master coordinates (x, y, z planes)
@@ -227,14 +226,18 @@ __device__ __forceinline__ void bump_block(const Sweep& sw, const WaveLds& W, in
 }
 
 // Score pass over the candidate angles base + k*stride (k < n).  Lanes are
-// (k0 < NB, atom group g < 64/NB): a lane scores angle kb + k0 over the atoms
-// g, g + G, ... of the moving list, kAtU atoms per step so that kAtU
-// distance-grid gathers are in flight.  The moving list is followed by
-// kMvPad rows whose position is the zero sentinel cell (certain, D = 0), so
-// the steps need no end-of-list masking; an atom whose cell is not certain
-// reads the sentinel too and marks its candidate uncertain (a ballot mask in
-// scalar registers).  With BOX the grid bounds are tested per atom, otherwise
-// the sweep set-up has proven that every moving atom stays inside the box.
+// (k0 < NB, atom group g < G = 64/NB); a block covers up to KANG*NB angles
+// and a lane scores the angles kb + k0 + NB*a (a < KANG) over the atoms g,
+// g + G, ... of the moving list, KATU atoms per step, so each atom's
+// coefficients are read from LDS once for up to KANG angles and KATU*KANG
+// distance-grid gathers are in flight.  (NB, KANG, KATU) = (8, 4, 1),
+// (16, 2, 2) or (32, 1, 4): up to 32 angles per block and 8 atoms per step
+// over the groups.  The moving list is followed by kMvPad rows
+// whose position is the zero sentinel cell (certain, D = 0), so the steps
+// need no end-of-list masking; an atom whose cell is not certain reads the
+// sentinel too and marks its candidate uncertain (a ballot mask in scalar
+// registers).  With BOX the grid bounds are tested per atom, otherwise the
+// sweep set-up has proven that every moving atom stays inside the box.
 // Writes W.Slo / W.Shi per candidate.
 template <int NB>
 __device__ __forceinline__ uint32_t fold_groups(uint64_t m) {
@@ -263,9 +266,11 @@ __device__ __forceinline__ int group_sum(int v) {
 template <int NB, bool BOX>
 __device__ __forceinline__ void score_pass(const PocketDev& P, const Sweep& sw, const WaveLds& W, const lds_float* trig,
                                            int base, int stride, int n) {
-    static_assert(kWave / NB * kAtU <= kMvPad + 1, "sentinel rows must cover a step");
-    const int lane = lane_id();
     constexpr int G = kWave / NB;
+    constexpr int KANG = NB == 8 ? 4 : NB == 16 ? 2 : 1;
+    constexpr int KATU = NB == 8 ? 1 : NB == 16 ? 2 : 4;
+    static_assert(G * KATU <= kMvPad + 1, "sentinel rows must cover a step");
+    const int lane = lane_id();
     const int k0 = lane & (NB - 1), g = lane / NB;
     const float fnx = (float)P.dim[0], fny = (float)P.dim[1], fnz = (float)P.dim[2];
     // byte offsets 2 * (z nx ny + y nx + x) in FP32: every partial result is an
@@ -275,46 +280,72 @@ __device__ __forceinline__ void score_pass(const PocketDev& P, const Sweep& sw, 
     const float glo = sw.gcell, ghi = 1.f - sw.gcell;
     const int m = sw.m;
     const __attribute__((address_space(1))) char* edt = (const __attribute__((address_space(1))) char*)P.edt;
-    for (int kb = 0; kb < n; kb += NB) {
-        const int k = kb + k0;
-        const int deg = base + (k < n ? k : 0) * stride;
-        const float c = trig[deg], s = trig[360 + deg];
-        int sum = 0;
-        uint64_t badm = 0;
+    for (int kb = 0; kb < n; kb += NB * KANG) {
+        const int A = min(KANG, (n - kb + NB - 1) / NB);
+        float c[KANG], s[KANG];
+#pragma unroll
+        for (int a = 0; a < KANG; a++) {
+            const int k = kb + k0 + NB * a;
+            const int deg = base + ((a < A) & (k < n) ? k : 0) * stride;
+            c[a] = trig[deg];
+            s[a] = trig[360 + deg];
+        }
+        int sum[KANG];
+        uint64_t badm[KANG];
+#pragma unroll
+        for (int a = 0; a < KANG; a++) {
+            sum[a] = 0;
+            badm[a] = 0;
+        }
         const lds_float4* row = W.MV + 3 * g;
-        for (int j = g; j < m; j += kAtU * G, row += 3 * kAtU * G) {
-            uint32_t off[kAtU];
+        for (int j = g; j < m; j += KATU * G, row += 3 * KATU * G) {
+            uint32_t off[KATU][KANG];
 #pragma unroll
-            for (int t = 0; t < kAtU; t++) {
+            for (int t = 0; t < KATU; t++) {
                 const f4 p0 = row[3 * t * G], u = row[3 * t * G + 1], v = row[3 * t * G + 2];
-                const float yx = fmaf(s, v.x, fmaf(c, u.x, p0.x));
-                const float yy = fmaf(s, v.y, fmaf(c, u.y, p0.y));
-                const float yz = fmaf(s, v.z, fmaf(c, u.z, p0.z));
-                const float fx = floorf(yx), fy = floorf(yy), fz = floorf(yz);
-                const float rx = __builtin_amdgcn_fractf(yx), ry = __builtin_amdgcn_fractf(yy),
-                            rz = __builtin_amdgcn_fractf(yz);
-                bool sure = (fminf(fminf(rx, ry), rz) >= glo) & (fmaxf(fmaxf(rx, ry), rz) <= ghi);
-                bool live = true;
-                if (BOX) {
-                    live = j + t * G < m;
-                    sure = sure & (fx >= 0.f) & (fx < fnx) & (fy >= 0.f) & (fy < fny) & (fz >= 0.f) & (fz < fnz);
-                }
-                badm |= __ballot(live & !sure);
-                const float fi2 = fmaf(fz, fsz2, fmaf(fy, fsy2, fx + fx));
-                off[t] = (uint32_t)((live & sure) ? fi2 : fsent2);
-            }
-            int d = 0;
+                const bool live = BOX ? (j + t * G < m) : true;
 #pragma unroll
-            for (int t = 0; t < kAtU; t++) d += (int)*(const __attribute__((address_space(1))) uint16_t*)(edt + off[t]);
-            sum += d;
+                for (int a = 0; a < KANG; a++) {
+                    off[t][a] = 0;
+                    if (a < A) {
+                        const float yx = fmaf(s[a], v.x, fmaf(c[a], u.x, p0.x));
+                        const float yy = fmaf(s[a], v.y, fmaf(c[a], u.y, p0.y));
+                        const float yz = fmaf(s[a], v.z, fmaf(c[a], u.z, p0.z));
+                        const float fx = floorf(yx), fy = floorf(yy), fz = floorf(yz);
+                        const float rx = __builtin_amdgcn_fractf(yx), ry = __builtin_amdgcn_fractf(yy),
+                                    rz = __builtin_amdgcn_fractf(yz);
+                        bool sure = (fminf(fminf(rx, ry), rz) >= glo) & (fmaxf(fmaxf(rx, ry), rz) <= ghi);
+                        if (BOX)
+                            sure = sure & (fx >= 0.f) & (fx < fnx) & (fy >= 0.f) & (fy < fny) & (fz >= 0.f) &
+                                   (fz < fnz);
+                        badm[a] |= __ballot(live & !sure);
+                        const float fi2 = fmaf(fz, fsz2, fmaf(fy, fsy2, fx + fx));
+                        off[t][a] = (uint32_t)((live & sure) ? fi2 : fsent2);
+                    }
+                }
+            }
+#pragma unroll
+            for (int a = 0; a < KANG; a++)
+                if (a < A) {
+                    int d = 0;
+#pragma unroll
+                    for (int t = 0; t < KATU; t++)
+                        d += (int)*(const __attribute__((address_space(1))) uint16_t*)(edt + off[t][a]);
+                    sum[a] += d;
+                }
         }
         // sum the groups of each angle across lanes; uncertain flags folded from the ballots
-        const int tot = group_sum<NB>(sum);
-        const uint32_t badbits = fold_groups<NB>(badm);
-        if (lane < NB && kb + lane < n) {
-            W.Slo[kb + lane] = tot;
-            W.Shi[kb + lane] = ((badbits >> lane) & 1u) ? kOpenHi : tot;
-        }
+#pragma unroll
+        for (int a = 0; a < KANG; a++)
+            if (a < A) {
+                const int tot = group_sum<NB>(sum[a]);
+                const uint32_t badbits = fold_groups<NB>(badm[a]);
+                const int k = kb + NB * a + lane;
+                if (lane < NB && k < n) {
+                    W.Slo[k] = tot;
+                    W.Shi[k] = ((badbits >> lane) & 1u) ? kOpenHi : tot;
+                }
+            }
     }
     wave_sync();
 }
