@@ -23,10 +23,34 @@ namespace gd {
 
 constexpr int kSlots = kMaxAtoms / kWave;  // atoms per lane
 
+// Sum over the wavefront, the total in every lane, without LDS: a butterfly
+// of DPP lane permutations (lane ^ 1, lane ^ 2, the two quads of a half row,
+// the two halves of a row) and then the gfx950 permlane swaps of rows of 16
+// and halves of the wave (the two outputs of a swap hold a lane's value and
+// its partner's).
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+
 __device__ __forceinline__ float wsum(float v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
+    v += dpp_f<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_f<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_f<0x141>(v);  // row_half_mirror
+    v += dpp_f<0x128>(v);  // row_ror:8
+    const auto p = __builtin_amdgcn_permlane16_swap(__float_as_int(v), __float_as_int(v), false, false);
+    v = __int_as_float((int)p[0]) + __int_as_float((int)p[1]);
+    const auto q = __builtin_amdgcn_permlane32_swap(__float_as_int(v), __float_as_int(v), false, false);
+    return __int_as_float((int)q[0]) + __int_as_float((int)q[1]);
+}
+
+// Coordinate of a wave-uniform atom index held in the per-lane slots (atom i
+// lives in lane i % 64 of slot i / 64).
+__device__ __forceinline__ float atom_at(const float Y[kSlots][3], int i, int a) {
+    static_assert(kSlots == 2, "two atom slots per lane");
+    const float lo = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(Y[0][a]), i & 63));
+    const float hi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(Y[1][a]), i & 63));
+    return i < kWave ? lo : hi;
 }
 
 // Trilinear density and its gradient; corners outside the tabulated box are 0
@@ -58,8 +82,8 @@ __device__ __forceinline__ float rho_tri(const PocketDev& P, float x, float y, f
 }
 
 __device__ __forceinline__ void quat_mat(const float* q, float* R) {
-    float n = sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-    float w = q[0] / n, x = q[1] / n, y = q[2] / n, z = q[3] / n;
+    const float in = 1.f / sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    float w = q[0] * in, x = q[1] * in, y = q[2] * in, z = q[3] * in;
     R[0] = 1.f - 2.f * (y * y + z * z); R[1] = 2.f * (x * y - w * z);       R[2] = 2.f * (x * z + w * y);
     R[3] = 2.f * (x * y + w * z);       R[4] = 1.f - 2.f * (x * x + z * z); R[5] = 2.f * (y * z - w * x);
     R[6] = 2.f * (x * z - w * y);       R[7] = 2.f * (y * z + w * x);       R[8] = 1.f - 2.f * (x * x + y * y);
@@ -70,6 +94,7 @@ struct PoseState {
     int l, nr, tree0;
     float x0[kSlots][3];  // input pose (this lane's atoms)
     float c0[3];          // centroid of the input pose
+    uint64_t mv[kSlots];  // bit e: this lane's atom moves with rotamer e (root-first order)
 };
 
 __device__ void load_pose(const TreeDev& T, const PoseDev& X, int pose, PoseState& S) {
@@ -91,36 +116,43 @@ __device__ void load_pose(const TreeDev& T, const PoseDev& X, int pose, PoseStat
         s[2] += S.x0[k][2];
     }
     for (int a = 0; a < 3; a++) S.c0[a] = wsum(s[a]) / (float)S.l;
+#pragma unroll
+    for (int k = 0; k < kSlots; k++) {
+        const int i = lane + k * kWave;
+        uint64_t b = 0;
+        for (int e = 0; e < S.nr; e++) {
+            const uint32_t* mk = T.tmask + 4 * (size_t)(S.tree0 + e);
+            if (i < S.l && ((mk[i >> 5] >> (i & 31)) & 1u)) b |= 1ull << e;
+        }
+        S.mv[k] = b;
+    }
 }
 
 // Forward kinematics + rigid motion; Ys gets FK_tau(X0) for this lane's
-// atoms, Xf the final pose.  lds: 3 * 128 floats of this wave.
+// atoms, Xf the final pose.
 __device__ void pose_forward(const TreeDev& T, const PoseState& S, const float* t, const float* q, const float* tau,
-                             float* lds, float Ys[kSlots][3], float Xf[kSlots][3]) {
-    const int lane = lane_id();
+                             float* axes, float Ys[kSlots][3], float Xf[kSlots][3], float Rq[9]) {
 #pragma unroll
     for (int k = 0; k < kSlots; k++)
         for (int a = 0; a < 3; a++) Ys[k][a] = S.x0[k][a];
     for (int e = 0; e < S.nr; e++) {
         const int4 te = T.tree[S.tree0 + e];
-        const uint32_t* mk = T.tmask + 4 * (size_t)(S.tree0 + e);
-#pragma unroll
-        for (int k = 0; k < kSlots; k++) {
-            int i = lane + k * kWave;
-            if (i < S.l) {
-                lds[i] = Ys[k][0];
-                lds[kMaxAtoms + i] = Ys[k][1];
-                lds[2 * kMaxAtoms + i] = Ys[k][2];
-            }
-        }
-        wave_sync();
-        const float px = lds[te.x], py = lds[kMaxAtoms + te.x], pz = lds[2 * kMaxAtoms + te.x];
-        float kx = lds[te.y] - px, ky = lds[kMaxAtoms + te.y] - py, kz = lds[2 * kMaxAtoms + te.y] - pz;
-        wave_sync();
-        float inv = 1.f / sqrtf(kx * kx + ky * ky + kz * kz);
+        const int ia = __builtin_amdgcn_readfirstlane(te.x), ib = __builtin_amdgcn_readfirstlane(te.y);
+        const float px = atom_at(Ys, ia, 0), py = atom_at(Ys, ia, 1), pz = atom_at(Ys, ia, 2);
+        float kx = atom_at(Ys, ib, 0) - px, ky = atom_at(Ys, ib, 1) - py, kz = atom_at(Ys, ib, 2) - pz;
+        const float inv = rsqrtf(kx * kx + ky * ky + kz * kz);
         kx *= inv;
         ky *= inv;
         kz *= inv;
+        if (axes && lane_id() == 0) {
+            float* ax = axes + 6 * te.z;
+            ax[0] = px;
+            ax[1] = py;
+            ax[2] = pz;
+            ax[3] = kx;
+            ax[4] = ky;
+            ax[5] = kz;
+        }
         float s, c;
         sincosf(tau[te.z], &s, &c);
         float tt = 1.f - c;
@@ -129,9 +161,7 @@ __device__ void pose_forward(const TreeDev& T, const PoseState& S, const float* 
                       tt * kx * kz - s * ky, tt * ky * kz + s * kx, tt * kz * kz + c};
 #pragma unroll
         for (int k = 0; k < kSlots; k++) {
-            int i = lane + k * kWave;
-            bool mv = i < S.l && ((mk[i >> 5] >> (i & 31)) & 1u);
-            if (mv) {
+            if ((S.mv[k] >> e) & 1) {
                 float d0 = Ys[k][0] - px, d1 = Ys[k][1] - py, d2 = Ys[k][2] - pz;
                 Ys[k][0] = px + (R[0] * d0 + R[1] * d1 + R[2] * d2);
                 Ys[k][1] = py + (R[3] * d0 + R[4] * d1 + R[5] * d2);
@@ -139,7 +169,6 @@ __device__ void pose_forward(const TreeDev& T, const PoseState& S, const float* 
             }
         }
     }
-    float Rq[9];
     quat_mat(q, Rq);
 #pragma unroll
     for (int k = 0; k < kSlots; k++) {
@@ -150,16 +179,17 @@ __device__ void pose_forward(const TreeDev& T, const PoseState& S, const float* 
     }
 }
 
-// F and (optionally) dF/d(t, q, tau) at the given parameters.  tau and gtau
-// are this wave's LDS arrays indexed by rotamer (list order); only
-// lane-uniform values are returned.
+// F and (optionally) dF/d(t, q, tau) at the given parameters.  tau, gtau and
+// axes (6 floats per rotamer: pivot and unit axis in the torsion frame) are
+// this wave's LDS arrays indexed by rotamer (list order); only lane-uniform
+// values are returned.
 template <bool GRAD>
 __device__ float surrogate_eval(const PocketDev& P, const TreeDev& T, const PoseState& S, const float* t,
-                                const float* q, const float* tau, float* lds, float* gt, float* gq, float* gtau,
+                                const float* q, const float* tau, float* axes, float* gt, float* gq, float* gtau,
                                 float Xout[kSlots][3]) {
     const int lane = lane_id();
-    float Ys[kSlots][3], Xf[kSlots][3], g[kSlots][3];
-    pose_forward(T, S, t, q, tau, lds, Ys, Xf);
+    float Ys[kSlots][3], Xf[kSlots][3], g[kSlots][3], Rq[9];
+    pose_forward(T, S, t, q, tau, GRAD ? axes : nullptr, Ys, Xf, Rq);
     float F = 0.f;
 #pragma unroll
     for (int k = 0; k < kSlots; k++) {
@@ -176,72 +206,65 @@ __device__ float surrogate_eval(const PocketDev& P, const TreeDev& T, const Pose
     if (!GRAD) return F;
     // translation
     for (int a = 0; a < 3; a++) gt[a] = wsum(g[0][a] + g[1][a]);
-    // quaternion
-    float G[9];
-    for (int r = 0; r < 3; r++)
-        for (int c = 0; c < 3; c++) {
-            float v = 0.f;
+    // x x g per atom, for the quaternion and the torsions
+    float xg[kSlots][3];
 #pragma unroll
-            for (int k = 0; k < kSlots; k++) v += g[k][r] * (Ys[k][c] - S.c0[c]);
-            G[3 * r + c] = wsum(v);
-        }
-    {
-        float n = sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-        float w = q[0] / n, x = q[1] / n, y = q[2] / n, z = q[3] / n;
-        float Dw[9] = {0, -2 * z, 2 * y, 2 * z, 0, -2 * x, -2 * y, 2 * x, 0};
-        float Dx[9] = {0, 2 * y, 2 * z, 2 * y, -4 * x, -2 * w, 2 * z, 2 * w, -4 * x};
-        float Dy[9] = {-4 * y, 2 * x, 2 * w, 2 * x, 0, 2 * z, -2 * w, 2 * z, -4 * y};
-        float Dz[9] = {-4 * z, -2 * w, 2 * x, 2 * w, -4 * z, 2 * y, 2 * x, 2 * y, 0};
-        float gh[4] = {0, 0, 0, 0};
-        for (int e = 0; e < 9; e++) {
-            gh[0] += G[e] * Dw[e];
-            gh[1] += G[e] * Dx[e];
-            gh[2] += G[e] * Dy[e];
-            gh[3] += G[e] * Dz[e];
-        }
-        float qh[4] = {w, x, y, z};
-        float dot = qh[0] * gh[0] + qh[1] * gh[1] + qh[2] * gh[2] + qh[3] * gh[3];
-        for (int k = 0; k < 4; k++) gq[k] = (gh[k] - qh[k] * dot) / n;
-    }
-    // torsions, in the final frame
     for (int k = 0; k < kSlots; k++) {
-        int i = lane + k * kWave;
-        if (i < S.l) {
-            lds[i] = Xf[k][0];
-            lds[kMaxAtoms + i] = Xf[k][1];
-            lds[2 * kMaxAtoms + i] = Xf[k][2];
-        }
+        xg[k][0] = Xf[k][1] * g[k][2] - Xf[k][2] * g[k][1];
+        xg[k][1] = Xf[k][2] * g[k][0] - Xf[k][0] * g[k][2];
+        xg[k][2] = Xf[k][0] * g[k][1] - Xf[k][1] * g[k][0];
     }
+    // quaternion: a tangent change dq of the unit quaternion (w, v) turns the
+    // pose by omega = 2 (w dv - dw v + v x dv) about c0 + t, so dF = omega . tau
+    // with the torque tau = sum (X - c0 - t) x g; divided by |q| for the
+    // unnormalised parameter
+    {
+        float sx[3];
+        for (int a = 0; a < 3; a++) sx[a] = wsum(xg[0][a] + xg[1][a]);
+        const float ox = S.c0[0] + t[0], oy = S.c0[1] + t[1], oz = S.c0[2] + t[2];
+        const float tx = sx[0] - (oy * gt[2] - oz * gt[1]);
+        const float ty = sx[1] - (oz * gt[0] - ox * gt[2]);
+        const float tz = sx[2] - (ox * gt[1] - oy * gt[0]);
+        const float in = 1.f / sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+        const float w = q[0] * in, x = q[1] * in, y = q[2] * in, z = q[3] * in;
+        gq[0] = -2.f * (tx * x + ty * y + tz * z) * in;
+        gq[1] = 2.f * (w * tx + (ty * z - tz * y)) * in;
+        gq[2] = 2.f * (w * ty + (tz * x - tx * z)) * in;
+        gq[3] = 2.f * (w * tz + (tx * y - ty * x)) * in;
+    }
+    // torsions, in the final frame: per rotamer the moving atoms' sums of
+    // x x g and g about the pivot and axis of the forward pass, carried into
+    // the final frame
     wave_sync();
     for (int e = 0; e < S.nr; e++) {
         const int4 te = T.tree[S.tree0 + e];
-        const uint32_t* mk = T.tmask + 4 * (size_t)(S.tree0 + e);
         float sxg[3] = {0, 0, 0}, sg[3] = {0, 0, 0};
 #pragma unroll
         for (int k = 0; k < kSlots; k++) {
-            int i = lane + k * kWave;
-            bool mv = i < S.l && ((mk[i >> 5] >> (i & 31)) & 1u);
-            if (mv) {
-                sxg[0] += Xf[k][1] * g[k][2] - Xf[k][2] * g[k][1];
-                sxg[1] += Xf[k][2] * g[k][0] - Xf[k][0] * g[k][2];
-                sxg[2] += Xf[k][0] * g[k][1] - Xf[k][1] * g[k][0];
-                sg[0] += g[k][0];
-                sg[1] += g[k][1];
-                sg[2] += g[k][2];
+            if ((S.mv[k] >> e) & 1) {
+                for (int a = 0; a < 3; a++) {
+                    sxg[a] += xg[k][a];
+                    sg[a] += g[k][a];
+                }
             }
         }
         for (int a = 0; a < 3; a++) {
             sxg[a] = wsum(sxg[a]);
             sg[a] = wsum(sg[a]);
         }
-        float ax = lds[te.x], ay = lds[kMaxAtoms + te.x], az = lds[2 * kMaxAtoms + te.x];
-        float kx = lds[te.y] - ax, ky = lds[kMaxAtoms + te.y] - ay, kz = lds[2 * kMaxAtoms + te.y] - az;
-        float inv = 1.f / sqrtf(kx * kx + ky * ky + kz * kz);
+        const float* axe = axes + 6 * te.z;
+        const float d0 = axe[0] - S.c0[0], d1 = axe[1] - S.c0[1], d2 = axe[2] - S.c0[2];
+        const float ax = (Rq[0] * d0 + Rq[1] * d1 + Rq[2] * d2) + S.c0[0] + t[0];
+        const float ay = (Rq[3] * d0 + Rq[4] * d1 + Rq[5] * d2) + S.c0[1] + t[1];
+        const float az = (Rq[6] * d0 + Rq[7] * d1 + Rq[8] * d2) + S.c0[2] + t[2];
+        const float kx = Rq[0] * axe[3] + Rq[1] * axe[4] + Rq[2] * axe[5];
+        const float ky = Rq[3] * axe[3] + Rq[4] * axe[4] + Rq[5] * axe[5];
+        const float kz = Rq[6] * axe[3] + Rq[7] * axe[4] + Rq[8] * axe[5];
         // sum (x_i - A) x g_i = sum x_i x g_i - A x sum g_i
         float tx = sxg[0] - (ay * sg[2] - az * sg[1]);
         float ty = sxg[1] - (az * sg[0] - ax * sg[2]);
         float tz = sxg[2] - (ax * sg[1] - ay * sg[0]);
-        if (lane == 0) gtau[te.z] = (kx * tx + ky * ty + kz * tz) * inv;
+        if (lane == 0) gtau[te.z] = kx * tx + ky * ty + kz * tz;
     }
     wave_sync();
     return F;
@@ -253,13 +276,11 @@ __global__ void __launch_bounds__(256) surrogate_kernel(PocketDev P, TreeDev T, 
                                                         const float* t, const float* q, const float* tau,
                                                         int tau_stride, const float* dF, float* F_out, float* dt_out,
                                                         float* dq_out, float* dtau_out) {
-    __shared__ float lds_all[4][3 * kMaxAtoms];
-    __shared__ float tau_all[4][kMaxRot], gtau_all[4][kMaxRot];
+    __shared__ float tau_all[4][kMaxRot], gtau_all[4][kMaxRot], axes_all[4][6 * kMaxRot];
     const int wave = threadIdx.x / kWave;
     const int pose = blockIdx.x * 4 + wave;
     if (pose >= n_poses) return;
     const int lane = lane_id();
-    float* lds = lds_all[wave];
     float* tau_l = tau_all[wave];
     float* gtau = gtau_all[wave];
     PoseState S;
@@ -272,12 +293,12 @@ __global__ void __launch_bounds__(256) surrogate_kernel(PocketDev P, TreeDev T, 
     }
     wave_sync();
     if (!dF) {
-        float F = surrogate_eval<false>(P, T, S, tp, qp, tau_l, lds, nullptr, nullptr, nullptr, nullptr);
+        float F = surrogate_eval<false>(P, T, S, tp, qp, tau_l, nullptr, nullptr, nullptr, nullptr, nullptr);
         if (lane == 0) F_out[pose] = F;
         return;
     }
     float gt[3], gq[4];
-    float F = surrogate_eval<true>(P, T, S, tp, qp, tau_l, lds, gt, gq, gtau, nullptr);
+    float F = surrogate_eval<true>(P, T, S, tp, qp, tau_l, axes_all[wave], gt, gq, gtau, nullptr);
     const float up = dF[pose];
     if (lane == 0) {
         if (F_out) F_out[pose] = F;
@@ -292,13 +313,11 @@ __global__ void __launch_bounds__(256) surrogate_kernel(PocketDev P, TreeDev T, 
 // registers; the final pose is written to (rx, ry, rz).
 __global__ void __launch_bounds__(256) refine_kernel(PocketDev P, TreeDev T, PoseDev X, int n_poses, RefineParams rp,
                                                      float* rx, float* ry, float* rz, float* F_out) {
-    __shared__ float lds_all[4][3 * kMaxAtoms];
-    __shared__ float tau_all[4][kMaxRot], gtau_all[4][kMaxRot];
+    __shared__ float tau_all[4][kMaxRot], gtau_all[4][kMaxRot], axes_all[4][6 * kMaxRot];
     const int wave = threadIdx.x / kWave;
     const int pose = blockIdx.x * 4 + wave;
     if (pose >= n_poses) return;
     const int lane = lane_id();
-    float* lds = lds_all[wave];
     float* tau = tau_all[wave];
     float* gtau = gtau_all[wave];
     PoseState S;
@@ -308,7 +327,7 @@ __global__ void __launch_bounds__(256) refine_kernel(PocketDev P, TreeDev T, Pos
     for (int r = lane; r < kMaxRot; r += kWave) tau[r] = gtau[r] = 0.f;
     wave_sync();
     for (int s = 0; s < rp.steps; s++) {
-        surrogate_eval<true>(P, T, S, t, q, tau, lds, gt, gq, gtau, nullptr);
+        surrogate_eval<true>(P, T, S, t, q, tau, axes_all[wave], gt, gq, gtau, nullptr);
         float dt[3] = {rp.lr_t * gt[0], rp.lr_t * gt[1], rp.lr_t * gt[2]};
         float n = sqrtf(dt[0] * dt[0] + dt[1] * dt[1] + dt[2] * dt[2]);
         float sc = n > rp.max_dt ? rp.max_dt / n : 1.f;
@@ -318,14 +337,14 @@ __global__ void __launch_bounds__(256) refine_kernel(PocketDev P, TreeDev T, Pos
             q[a] += rp.lr_q * gq[a];
             qn += q[a] * q[a];
         }
-        qn = sqrtf(qn);
-        for (int a = 0; a < 4; a++) q[a] /= qn;
+        qn = 1.f / sqrtf(qn);
+        for (int a = 0; a < 4; a++) q[a] *= qn;
         for (int r = lane; r < S.nr; r += kWave)
             tau[r] += fminf(fmaxf(rp.lr_tau * gtau[r], -rp.max_dtau), rp.max_dtau);
         wave_sync();
     }
     float Xf[kSlots][3];
-    float F = surrogate_eval<false>(P, T, S, t, q, tau, lds, nullptr, nullptr, nullptr, Xf);
+    float F = surrogate_eval<false>(P, T, S, t, q, tau, nullptr, nullptr, nullptr, nullptr, Xf);
     const int off = X.pose_off[pose];
     for (int k = 0; k < kSlots; k++) {
         int i = lane_id() + k * kWave;
