@@ -121,6 +121,33 @@ def refine_leg(gd, torch, np, n_lig):
                 gather_GBps=gather_bytes / (kms * 1e-3) / 1e9)
 
 
+def large_leg(gd, torch, n_chunks):
+    """The large library streamed through the persistent kernel in chunks of
+    65,536 ligands (host preparation of the next chunk overlaps docking), with
+    the top-8 poses of every chunk refined and re-scored."""
+    from synth import configs
+    from paper_1901_06363_amd.stream import screen
+    w = configs.LARGE
+    r = configs.REFINE.extra
+    P = gd.Pocket(w.pocket_points(), 0.5, w.pad, blur_sigma=r["blur_sigma"], blur_h=r["blur_h"])
+    ropt = dict(steps=r["steps"], lr_t=r["lr_t"], lr_q=r["lr_q"], lr_tau=r["lr_tau"], max_dt=r["max_dt"],
+                max_dtau=r["max_dtau"])
+    n = n_chunks * w.chunk
+    poses = atoms = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for item in screen(P, w.ligands, n, w.quaternions(), chunk=w.chunk, refine_poses=ropt, hp=w.hp, top_k=w.top_k):
+        poses += item["poses"]
+        atoms += int(item["ligands"].atom_off[-1])
+        log("large: chunk at %d done (%.1f s)" % (item["first"], time.perf_counter() - t0))
+    dt = time.perf_counter() - t0
+    return dict(workload="large: %d ligands (15-120 atoms, 0-16 rotatable bonds, 5%% with a ring) x 10,000-point "
+                         "pocket, 1024 orientations, 10-degree steps, chunks of %d, top-8 refined" % (n, w.chunk),
+                ligands=n, poses=poses, seconds=dt, poses_per_s=poses / dt, ligands_per_s=n / dt,
+                atoms_per_s=atoms / dt, note="wall clock over the whole stream: generation, preparation, docking, "
+                                             "top-k, refinement and host copies")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -134,6 +161,7 @@ def main():
     ap.add_argument("--no-refine", action="store_true")
     ap.add_argument("--refine-only", action="store_true", help="run only the refinement leg (profiling)")
     ap.add_argument("--refine-ligands", type=int, default=4096)
+    ap.add_argument("--large-chunks", type=int, default=0, help="also stream this many chunks of the large library")
     ap.add_argument("--tiling", type=str, default="")
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--n-ligands", type=int, default=0, help="override the ligand count (testing only)")
@@ -250,6 +278,11 @@ def main():
         ref = refine_leg(gd, torch, np, args.refine_ligands)
         log("refinement:", ref)
 
+    large = None
+    if args.large_chunks > 0:
+        large = large_leg(gd, torch, args.large_chunks)
+        log("large:", large)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, ligs, q, min(args.cpu_sample, n_lig))
@@ -289,6 +322,7 @@ def main():
         "end_to_end_poses_per_s_incl_prep": B.poses_expected / (prep_s + dt / args.steps),
         "per_ligand": per_lig,
         "refine": ref,
+        "large": large,
         "roofline": {
             "bound": "alu",
             "achieved": achieved,
