@@ -449,17 +449,22 @@ __device__ int eval_candidates(const PocketDev& P, const BatchDev& B, const Swee
 }
 
 // Axis k = (X_c - X_a)/|X_c - X_a| and pivot of one fragment sweep (FP64,
-// stored in W.SW), from the current master coordinates.
-__device__ __forceinline__ void sweep_axis(const WaveLds& W, int lp, int a, int c, int piv) {
+// stored in W.SW), from the current master coordinates.  The right side of a
+// rotamer follows its left side: the left commit leaves X_a exactly in place
+// (p + R 0 = p) and does not move X_c, so the axis in W.SW is already the
+// bit-exact result and only the pivot changes (keep_axis).
+__device__ __forceinline__ void sweep_axis(const WaveLds& W, int lp, int a, int c, int piv, bool keep_axis) {
     if (lane_id() == 0) {
         const lds_double* Xx = W.X;
         const lds_double* Xy = W.X + lp;
         const lds_double* Xz = W.X + 2 * lp;
-        double ax = Xx[c] - Xx[a], ay = Xy[c] - Xy[a], az = Xz[c] - Xz[a];
-        double nrm = sqrt(ax * ax + ay * ay + az * az);
-        W.SW[0] = ax / nrm;
-        W.SW[1] = ay / nrm;
-        W.SW[2] = az / nrm;
+        if (!keep_axis) {
+            double ax = Xx[c] - Xx[a], ay = Xy[c] - Xy[a], az = Xz[c] - Xz[a];
+            double nrm = sqrt(ax * ax + ay * ay + az * az);
+            W.SW[0] = ax / nrm;
+            W.SW[1] = ay / nrm;
+            W.SW[2] = az / nrm;
+        }
         W.SW[3] = Xx[piv];
         W.SW[4] = Xy[piv];
         W.SW[5] = Xz[piv];
@@ -504,7 +509,7 @@ __device__ __forceinline__ void sweep_setup(const PocketDev& P, const BatchDev& 
     sw.m = ri.n_mv;
     sw.pairs = B.pairs + ri.pair_off;
     sw.npairs = ri.n_pairs;
-    sweep_axis(W, lp, ri.a, ri.c, ri.piv);
+    sweep_axis(W, lp, ri.a, ri.c, ri.piv, side == 1);
     const double kx = uniform_d(W.SW[0]), ky = uniform_d(W.SW[1]), kz = uniform_d(W.SW[2]);
     const double px = uniform_d(W.SW[3]), py = uniform_d(W.SW[4]), pz = uniform_d(W.SW[5]);
 
@@ -849,7 +854,7 @@ __global__ void __launch_bounds__(256) replay_kernel(PocketDev P, BatchDev B, co
             const RotInfo* rp = B.rot + L.rot_off + r;
             for (int side = 0; side < 2; side++) {
                 const SideInfo ri = side_info(rp, side);
-                sweep_axis(W, lp, ri.a, ri.c, ri.piv);
+                sweep_axis(W, lp, ri.a, ri.c, ri.piv, side == 1);
                 commit(B.mv + ri.mv_off, ri.n_mv, W, lp, ang[(rep * L.nr + r) * 2 + side]);
             }
         }
