@@ -79,17 +79,19 @@ __device__ __forceinline__ f4 mk4(float a, float b, float c, float d) {
 }
 typedef __attribute__((address_space(3))) int lds_int;
 typedef __attribute__((address_space(3))) uint8_t lds_u8;
+typedef __attribute__((address_space(3))) uint16_t lds_u16;
 
 constexpr int kSurvCap = 128;  // straddling pairs that can still bump in one sweep (LDS list)
 constexpr int kMvPad = 32;     // sentinel rows after the moving list (cover one step of the score pass)
 
 struct WaveLds {
     lds_double* X;   // [3][lp] FP64 master coordinates (x, y, z planes)
-    lds_double* SW;  // [8] FP64 axis k (3) and pivot p (3) of the sweep in progress
+    lds_double* SW;  // [8] FP64 axis k (3), pivot p (3) and |X_c - X_a| of the sweep in progress
     lds_float4* AD;  // [lp][2] per-atom sweep data: (u, k.u), (k x u, |u|^2), u = X - p (A)
     lds_float4* MV;  // [lp + kMvPad][3] moving atoms: P0, U, V in cell units (w unused), then sentinel rows
     lds_int* Slo;    // [nmax] lower bound of each candidate's S over the moving atoms
     lds_int* Shi;    // [nmax] upper bound
+    lds_u16* surv_pr;  // [kSurvCap] the surviving pairs (left | right << 8)
     lds_u8* st;      // [nmax] bit0: certain bump, bit1: possible bump
     lds_float4* surv;  // [kSurvCap] (A, B, C, -) of the pairs that survive the sweep's prune
 };
@@ -99,7 +101,7 @@ __host__ __device__ inline size_t wave_lds_bytes(int lmax, int nmax) {
     int lp = lds_pitch(lmax);
     int np = (nmax + 15) & ~15;
     size_t b = sizeof(double) * 3 * lp + sizeof(double) * 8 + sizeof(f4) * (5 * lp + 3 * kMvPad + kSurvCap) +
-               sizeof(int) * 2 * np + np;
+               sizeof(int) * 2 * np + np + sizeof(uint16_t) * kSurvCap;
     return (b + 15) & ~(size_t)15;
 }
 __host__ __device__ inline size_t replay_lds_bytes(int lmax) {
@@ -118,6 +120,7 @@ __device__ inline WaveLds carve(char* base, int lmax, int nmax) {
     W.Slo = (lds_int*)(W.surv + kSurvCap);
     W.Shi = W.Slo + np;
     W.st = (lds_u8*)(W.Shi + np);
+    W.surv_pr = (lds_u16*)(W.st + np);
     return W;
 }
 
@@ -464,6 +467,7 @@ __device__ __forceinline__ void sweep_axis(const WaveLds& W, int lp, int a, int 
             W.SW[0] = ax / nrm;
             W.SW[1] = ay / nrm;
             W.SW[2] = az / nrm;
+            W.SW[6] = nrm;
         }
         W.SW[3] = Xx[piv];
         W.SW[4] = Xy[piv];
@@ -497,7 +501,8 @@ __device__ __forceinline__ SideInfo side_info(const RotInfo* rp, int side) {
 }
 
 __device__ __forceinline__ void sweep_setup(const PocketDev& P, const BatchDev& B, const LigMeta& L,
-                                         const SideInfo& ri, int side, const WaveLds& W, Sweep& sw) {
+                                         const SideInfo& ri, int side, int left_nsurv, const WaveLds& W,
+                                         Sweep& sw) {
     const int lane = lane_id();
     const int lp = lds_pitch(B.lmax);
     const lds_double* Xx = W.X;
@@ -578,31 +583,54 @@ __device__ __forceinline__ void sweep_setup(const PocketDev& P, const BatchDev& 
     wave_sync();
     // Prune: a pair whose smallest d^2 over a full turn, A - 2 sqrt(B^2 + C^2),
     // clears the bump distance by more than twice the guard never bumps.
-    const float T = (float)(B.cd2 + 2.0 * gc);
+    //
+    // That smallest d^2 depends only on the two atoms' radial and axial
+    // coordinates about the rotamer's axis, which neither the left commit nor
+    // the change of pivot along the axis alters, so the right sweep reuses the
+    // left sweep's survivors (left_nsurv >= 0) and only recomputes their
+    // coefficients.  For that the left prune clears twice the larger of its own
+    // guard and a bound on the right one (R_right <= R_left + |X_c - X_a|):
+    // the computed A - 2 sqrt(B^2 + C^2) errs by less than a third of a guard,
+    // and an evaluation by half a guard, so an excluded pair stays above
+    // cd^2 + guard at every angle of either sweep.
     const float csign = side == 0 ? -1.f : 1.f;
     int nsurv = 0;
-    for (int q0 = 0; q0 < sw.npairs; q0 += 4 * kWave) {
-        uint16_t prs[4];
-#pragma unroll
-        for (int t = 0; t < 4; t++) {
-            const int q = q0 + t * kWave + lane;
-            prs[t] = q < sw.npairs ? ldg(sw.pairs + q) : (uint16_t)0;
+    if (left_nsurv >= 0) {
+        nsurv = left_nsurv;
+        for (int q = lane; q < nsurv; q += kWave) W.surv[q] = pair_coeffs(W, W.surv_pr[q], csign);
+    } else {
+        double gp = gc;
+        if (side == 0) {
+            const double Rr = sqrt(1.01 * (double)r2max) + uniform_d(W.SW[6]);
+            gp = fmax(gp, 2.0 * u32 * 74.0 * 1.01 * Rr * Rr + 1e-6);
         }
+        const float T = (float)(B.cd2 + 2.0 * gp);
+        for (int q0 = 0; q0 < sw.npairs; q0 += 4 * kWave) {
+            uint16_t prs[4];
 #pragma unroll
-        for (int t = 0; t < 4; t++) {
-            const int q = q0 + t * kWave + lane;
-            bool keep = false;
-            f4 e = mk4(0.f, 0.f, 0.f, 0.f);
-            if (q < sw.npairs) {
-                e = pair_coeffs(W, prs[t], csign);
-                const float Am = e.x - T;
-                keep = !((Am > 0.f) & (Am * Am > 4.0004f * fmaf(e.z, e.z, e.y * e.y)));
+            for (int t = 0; t < 4; t++) {
+                const int q = q0 + t * kWave + lane;
+                prs[t] = q < sw.npairs ? ldg(sw.pairs + q) : (uint16_t)0;
             }
-            const uint64_t mk = __ballot(keep);
-            const int pos =
-                nsurv + __builtin_amdgcn_mbcnt_hi((uint32_t)(mk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0));
-            if (keep && pos < kSurvCap) W.surv[pos] = e;
-            nsurv += __popcll(mk);
+#pragma unroll
+            for (int t = 0; t < 4; t++) {
+                const int q = q0 + t * kWave + lane;
+                bool keep = false;
+                f4 e = mk4(0.f, 0.f, 0.f, 0.f);
+                if (q < sw.npairs) {
+                    e = pair_coeffs(W, prs[t], csign);
+                    const float Am = e.x - T;
+                    keep = !((Am > 0.f) & (Am * Am > 4.0004f * fmaf(e.z, e.z, e.y * e.y)));
+                }
+                const uint64_t mk = __ballot(keep);
+                const int pos = nsurv + __builtin_amdgcn_mbcnt_hi((uint32_t)(mk >> 32),
+                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0));
+                if (keep && pos < kSurvCap) {
+                    W.surv[pos] = e;
+                    W.surv_pr[pos] = prs[t];
+                }
+                nsurv += __popcll(mk);
+            }
         }
     }
     sw.nsurv = nsurv;
@@ -680,10 +708,12 @@ __device__ void dock_orientation(const PocketDev& P, const BatchDev& B, int lig,
     for (int rep = 0; rep < B.reps; rep++) {
         for (int r = 0; r < L.nr; r++) {
             const RotInfo* rp = B.rot + L.rot_off + r;
+            int left_nsurv = -1;
             for (int side = 0; side < 2; side++) {
                 const SideInfo ri = side_info(rp, side);
                 Sweep sw;
-                sweep_setup(P, B, L, ri, side, W, sw);
+                sweep_setup(P, B, L, ri, side, left_nsurv, W, sw);
+                left_nsurv = sw.pruned ? sw.nsurv : -1;
                 int deg;
                 if (ri.mode == kFlat) {
                     const int st = ri.step;
