@@ -752,7 +752,9 @@ __device__ void flush(unsigned long long* counters, Acc& acc) {
 
 // Per-ligand form: one launch per ligand, one wave per orientation.
 template <int NB, int PPL>
-__global__ void __launch_bounds__(512) dock_ligand_kernel(const PocketDev* __restrict__ Pp,
+// At least 3 waves per SIMD (<= 168 VGPRs): the kernel sits near that bound, and
+// dropping to 2 waves costs far more than a few spills.
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) dock_ligand_kernel(const PocketDev* __restrict__ Pp,
                                                           const BatchDev* __restrict__ Bp,
                                                           unsigned long long* counters, int lig, int nmax) {
     const PocketDev& P = *Pp;
@@ -775,7 +777,7 @@ __global__ void __launch_bounds__(512) dock_ligand_kernel(const PocketDev* __res
 // Batched form: a persistent grid; every wave pops (ligand, orientation
 // block) items from the device queue until it is empty.
 template <int NB, int PPL>
-__global__ void __launch_bounds__(512) dock_persistent_kernel(const PocketDev* __restrict__ Pp,
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) dock_persistent_kernel(const PocketDev* __restrict__ Pp,
                                                               const BatchDev* __restrict__ Bp,
                                                               unsigned long long* counters, int nmax) {
     const PocketDev& P = *Pp;
