@@ -84,6 +84,19 @@ __device__ __forceinline__ T ldg(const T* p) {
     return *(const __attribute__((address_space(1))) T*)p;
 }
 
+// The same for a plain record, word by word (records have no copy from the
+// global address space).
+template <class T>
+__device__ __forceinline__ T ldg_record(const T* p) {
+    static_assert(sizeof(T) % 4 == 0, "whole words");
+    T v;
+    uint32_t* d = reinterpret_cast<uint32_t*>(&v);
+    const uint32_t* s = reinterpret_cast<const uint32_t*>(p);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); i++) d[i] = ldg(s + i);
+    return v;
+}
+
 // --------------------------------------------------------------------------
 // exact distance field lookups
 

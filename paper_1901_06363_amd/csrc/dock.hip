@@ -663,7 +663,7 @@ __device__ __forceinline__ void commit(const uint8_t* mvl, int m, const WaveLds&
 __device__ void place(const PocketDev& P, const BatchDev& B, const LigMeta& L, int o, const WaveLds& W) {
     const int lane = lane_id();
     const int lp = lds_pitch(B.lmax);
-    const double* R = B.qmat + 9 * (size_t)o;
+    const __attribute__((address_space(1))) double* R = (const __attribute__((address_space(1))) double*)(B.qmat + 9 * (size_t)o);
     for (int i = lane; i < L.l; i += kWave) {
         double d0 = (double)ldg(B.x + L.atom_off + i) - L.cL[0];
         double d1 = (double)ldg(B.y + L.atom_off + i) - L.cL[1];
@@ -686,14 +686,20 @@ __device__ __forceinline__ void endpoint(const PocketDev& P, const BatchDev& B, 
     int s = 0;
     for (int i = lane; i < L.l; i += kWave) s += D_exact(P, Xx[i], Xy[i], Xz[i], acc.oob);
     S = wave_sum(s);
-    bool c = false;
+    // whole-ligand bump flag: any far pair closer than the bump distance (the
+    // scan stops at the first word of pairs that holds one)
     const uint16_t* fp = B.efar + L.far_off;
-    for (int q = lane; q < L.n_far; q += kWave) {
-        uint16_t pr = fp[q];
-        int i = pr & 0xff, j = pr >> 8;
-        c |= dist2(Xx[i], Xy[i], Xz[i], Xx[j], Xy[j], Xz[j]) < B.cd2;
+    clash = false;
+    for (int q0 = 0; q0 < L.n_far && !clash; q0 += kWave) {
+        const int q = q0 + lane;
+        bool c = false;
+        if (q < L.n_far) {
+            const uint16_t pr = ldg(fp + q);
+            const int i = pr & 0xff, j = pr >> 8;
+            c = dist2(Xx[i], Xy[i], Xz[i], Xx[j], Xy[j], Xz[j]) < B.cd2;
+        }
+        clash = __ballot(c) != 0;
     }
-    clash = __ballot(c) != 0;
     acc.poses += 1;
 }
 
@@ -701,7 +707,7 @@ __device__ __forceinline__ void endpoint(const PocketDev& P, const BatchDev& B, 
 template <int NB, int PPL>
 __device__ void dock_orientation(const PocketDev& P, const BatchDev& B, int lig, int o, const WaveLds& W,
                                  const lds_float* trig, Acc& acc) {
-    const LigMeta L = B.lig[lig];
+    const LigMeta L = ldg_record(B.lig + lig);
     place(P, B, L, o, W);
     const int nrec = B.reps * L.nr * 2;
     uint16_t* ang = B.ang + L.ang_off + (size_t)o * nrec;
@@ -797,7 +803,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) d
         if (lane_id() == 0) item = atomicAdd(B.head, 1);
         item = uniform(__shfl(item, 0));
         if (item >= B.n_items) break;
-        const int lig = uniform(B.items[2 * item]), o0 = uniform(B.items[2 * item + 1]);
+        const int lig = uniform(ldg(B.items + 2 * item)), o0 = uniform(ldg(B.items + 2 * item + 1));
         const int o1 = min(o0 + B.orient_per_item, B.n_orient);
         for (int o = o0; o < o1; o++) dock_orientation<NB, PPL>(P, B, lig, o, W, (const lds_float*)trig, acc);
     }
@@ -814,7 +820,7 @@ __global__ void reset_kernel(int* head, unsigned long long* counters) {
 __global__ void __launch_bounds__(256) topk_kernel(BatchDev B, gd_pose_rec* out, uint16_t* ang_out, int rmax,
                                                    double h) {
     const int lig = blockIdx.x;
-    const LigMeta L = B.lig[lig];
+    const LigMeta L = ldg_record(B.lig + lig);
     const uint64_t* keys = B.keys + L.key_off;
     __shared__ uint64_t red[256 / kWave];
     __shared__ uint64_t sel;
@@ -876,7 +882,7 @@ __global__ void __launch_bounds__(256) replay_kernel(PocketDev P, BatchDev B, co
     const int lp = lds_pitch(B.lmax);
     W.X = (lds_double*)(smem + wave * replay_lds_bytes(B.lmax));
     W.SW = W.X + 3 * lp;
-    const LigMeta L = B.lig[lig];
+    const LigMeta L = ldg_record(B.lig + lig);
     const int o = recs[idx].orient;
     place(P, B, L, o, W);
     const int nrec = B.reps * L.nr * 2;
