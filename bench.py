@@ -335,6 +335,8 @@ def main():
             "kernel": "dock_persistent_kernel",
             "kernel_ms": k_ms,
             "algo_flops_per_launch": B.algo_flops,
+            "algo_gather_bytes_per_launch": B.algo_bytes,
+            "gather_GBps": B.algo_bytes / (k_ms * 1e-3) / 1e9,
         },
         "cpu_baseline": cpu,
     }
