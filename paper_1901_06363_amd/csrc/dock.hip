@@ -87,8 +87,9 @@ constexpr int kMvPad = 32;     // sentinel rows after the moving list (cover one
 struct WaveLds {
     lds_double* X;   // [3][lp] FP64 master coordinates (x, y, z planes)
     lds_double* SW;  // [8] FP64 axis k (3), pivot p (3) and |X_c - X_a| of the sweep in progress
-    lds_float4* AD;  // [lp][2] per-atom sweep data: (u, k.u), (k x u, |u|^2), u = X - p (A)
-    lds_float4* MV;  // [lp + kMvPad][3] moving atoms: P0, U, V in cell units (w unused), then sentinel rows
+    lds_float4* AD;  // [lp][2] per-atom sweep data: (u, k.u), (k x u, |u|^2), u = X - p (A); set-up only
+    lds_float4* MV;  // [lp + kMvPad][3] moving atoms: P0, U, V in cell units (w unused), then sentinel
+                     // rows; written after the prune over the same memory as AD
     lds_int* Slo;    // [nmax] lower bound of each candidate's S over the moving atoms
     lds_int* Shi;    // [nmax] upper bound
     lds_u16* surv_pr;  // [kSurvCap] the surviving pairs (left | right << 8)
@@ -100,7 +101,7 @@ __host__ __device__ inline int lds_pitch(int lmax) { return (lmax + 15) & ~15; }
 __host__ __device__ inline size_t wave_lds_bytes(int lmax, int nmax) {
     int lp = lds_pitch(lmax);
     int np = (nmax + 15) & ~15;
-    size_t b = sizeof(double) * 3 * lp + sizeof(double) * 8 + sizeof(f4) * (5 * lp + 3 * kMvPad + kSurvCap) +
+    size_t b = sizeof(double) * 3 * lp + sizeof(double) * 8 + sizeof(f4) * (3 * (lp + kMvPad) + kSurvCap) +
                sizeof(int) * 2 * np + np + sizeof(uint16_t) * kSurvCap;
     return (b + 15) & ~(size_t)15;
 }
@@ -115,7 +116,7 @@ __device__ inline WaveLds carve(char* base, int lmax, int nmax) {
     W.X = (lds_double*)base;
     W.SW = W.X + 3 * lp;
     W.AD = (lds_float4*)(W.SW + 8);
-    W.MV = W.AD + 2 * lp;
+    W.MV = W.AD;
     W.surv = W.MV + 3 * (lp + kMvPad);
     W.Slo = (lds_int*)(W.surv + kSurvCap);
     W.Shi = W.Slo + np;
@@ -192,9 +193,7 @@ constexpr int kOpenHi = 0x20000000;
 //   A = |u_l|^2 + |u_r|^2 - 2 (k.u_l)(k.u_r),   B = (k.u_l)(k.u_r) - u_l.u_r,
 //   C = -(k x u_l).u_r when the left side turns; turning the right side
 //   instead flips the sign of C (csign = -1 left, +1 right).
-__device__ __forceinline__ f4 pair_coeffs(const WaveLds& W, uint32_t pr, float csign) {
-    const int li = pr & 0xff, ri = pr >> 8;
-    const f4 ul = W.AD[2 * li], wl = W.AD[2 * li + 1], ur = W.AD[2 * ri], wr = W.AD[2 * ri + 1];
+__device__ __forceinline__ f4 pair_coeffs_from(f4 ul, f4 wl, f4 ur, f4 wr, float csign) {
     const float kk = ul.w * ur.w;
     const float A = fmaf(-2.f, kk, wl.w + wr.w);
     const float uv = fmaf(ul.z, ur.z, fmaf(ul.y, ur.y, ul.x * ur.x));
@@ -202,20 +201,50 @@ __device__ __forceinline__ f4 pair_coeffs(const WaveLds& W, uint32_t pr, float c
     return mk4(A, kk - uv, csign * vw, 0.f);
 }
 
+__device__ __forceinline__ f4 pair_coeffs(const WaveLds& W, uint32_t pr, float csign) {
+    const int li = pr & 0xff, ri = pr >> 8;
+    return pair_coeffs_from(W.AD[2 * li], W.AD[2 * li + 1], W.AD[2 * ri], W.AD[2 * ri + 1], csign);
+}
+
+// Per-atom sweep data of atom i: (u, k.u) and (k x u, |u|^2) with u = X_i - p,
+// in FP64 and rounded once to FP32 (the values the set-up stores in W.AD).
+struct Frame {
+    double kx, ky, kz, px, py, pz;
+};
+
+__device__ __forceinline__ void atom_data(const WaveLds& W, int lp, const Frame& f, int i, f4& a0, f4& a1) {
+    const double ux = W.X[i] - f.px, uy = W.X[lp + i] - f.py, uz = W.X[2 * lp + i] - f.pz;
+    const double ku = f.kx * ux + f.ky * uy + f.kz * uz;
+    const double uu = ux * ux + uy * uy + uz * uz;
+    a0 = mk4((float)ux, (float)uy, (float)uz, (float)ku);
+    a1 = mk4((float)(f.ky * uz - f.kz * uy), (float)(f.kz * ux - f.kx * uz), (float)(f.kx * uy - f.ky * ux), (float)uu);
+}
+
 // K pairs per lane starting at q0 (lanes = straddling pairs), then for each
 // of the nw angles of the word (c2 = 2 cos, s2 = 2 sin per lane) a certain /
 // possible bump bit.  Used when more pairs survive the prune than the LDS list
-// holds.
+// holds (rare).
 template <int K>
 __device__ __forceinline__ void bump_block(const Sweep& sw, const WaveLds& W, int q0, int nq, int nw, float c2,
                                            float s2, uint64_t& cert, uint64_t& maybe) {
     const int lane = lane_id();
     const float csign = sw.side == 0 ? -1.f : 1.f;
+    // W.AD has been overwritten by the moving-atom rows: rebuild the per-atom
+    // data of both atoms from the FP64 masters (the same values)
+    const Frame fr{uniform_d(W.SW[0]), uniform_d(W.SW[1]), uniform_d(W.SW[2]),
+                   uniform_d(W.SW[3]), uniform_d(W.SW[4]), uniform_d(W.SW[5])};
     f4 e[K];
 #pragma unroll
     for (int t = 0; t < K; t++) {
         const int q = q0 + t * kWave + lane;
-        e[t] = q < nq ? pair_coeffs(W, ldg(sw.pairs + q), csign) : mk4(3.0e38f, 0.f, 0.f, 0.f);
+        e[t] = mk4(3.0e38f, 0.f, 0.f, 0.f);
+        if (q < nq) {
+            const uint32_t pr = ldg(sw.pairs + q);
+            f4 ul, wl, ur, wr;
+            atom_data(W, sw.lp, fr, pr & 0xff, ul, wl);
+            atom_data(W, sw.lp, fr, pr >> 8, ur, wr);
+            e[t] = pair_coeffs_from(ul, wl, ur, wr, csign);
+        }
     }
     for (int k = 0; k < nw; k++) {
         const float c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(c2), k));
@@ -518,55 +547,17 @@ __device__ __forceinline__ void sweep_setup(const PocketDev& P, const BatchDev& 
     const double kx = uniform_d(W.SW[0]), ky = uniform_d(W.SW[1]), kz = uniform_d(W.SW[2]);
     const double px = uniform_d(W.SW[3]), py = uniform_d(W.SW[4]), pz = uniform_d(W.SW[5]);
 
+    // per-atom data of every atom, for the pair coefficients
+    const Frame fr{kx, ky, kz, px, py, pz};
     float r2max = 0.f;
     for (int i = lane; i < L.l; i += kWave) {
-        double ux = Xx[i] - px, uy = Xy[i] - py, uz = Xz[i] - pz;
-        double ku = kx * ux + ky * uy + kz * uz;
-        double uu = ux * ux + uy * uy + uz * uz;
-        W.AD[2 * i] = mk4((float)ux, (float)uy, (float)uz, (float)ku);
-        W.AD[2 * i + 1] = mk4((float)(ky * uz - kz * uy), (float)(kz * ux - kx * uz),
-                                      (float)(kx * uy - ky * ux), (float)uu);
-        r2max = fmaxf(r2max, (float)uu);
-    }
-    float amax = 0.f, umax = 0.f;
-    bool outside = false;
-    const double ih = P.inv_h;
-    const double bx = (double)P.dim[0] - 0.01, by = (double)P.dim[1] - 0.01, bz = (double)P.dim[2] - 0.01;
-    for (int j = lane; j < sw.m; j += kWave) {
-        int i = ldg(sw.mvl + j);
-        double ux = Xx[i] - px, uy = Xy[i] - py, uz = Xz[i] - pz;
-        double ku = kx * ux + ky * uy + kz * uz;
-        double ax0 = (px + ku * kx) * ih - (double)P.lo[0];
-        double ay0 = (py + ku * ky) * ih - (double)P.lo[1];
-        double az0 = (pz + ku * kz) * ih - (double)P.lo[2];
-        double Ux = (ux - ku * kx) * ih, Uy = (uy - ku * ky) * ih, Uz = (uz - ku * kz) * ih;
-        double Vx = (ky * uz - kz * uy) * ih, Vy = (kz * ux - kx * uz) * ih, Vz = (kx * uy - ky * ux) * ih;
-        W.MV[3 * j] = mk4((float)ax0, (float)ay0, (float)az0, 0.f);
-        W.MV[3 * j + 1] = mk4((float)Ux, (float)Uy, (float)Uz, 0.f);
-        W.MV[3 * j + 2] = mk4((float)Vx, (float)Vy, (float)Vz, 0.f);
-        // the circle's extent along axis a is P0_a +- sqrt(U_a^2 + V_a^2): keep it
-        // 0.01 cell inside the box on both sides
-        const double ex2 = Ux * Ux + Vx * Vx, ey2 = Uy * Uy + Vy * Vy, ez2 = Uz * Uz + Vz * Vz;
-        const double lx = ax0 - 0.01, ly = ay0 - 0.01, lz = az0 - 0.01;
-        const double hx = bx - ax0, hy = by - ay0, hz = bz - az0;
-        outside |= !(lx >= 0.0 && ly >= 0.0 && lz >= 0.0 && hx >= 0.0 && hy >= 0.0 && hz >= 0.0 && ex2 <= lx * lx &&
-                     ey2 <= ly * ly && ez2 <= lz * lz && ex2 <= hx * hx && ey2 <= hy * hy && ez2 <= hz * hz);
-        amax = fmaxf(amax, (float)fmax(fabs(ax0), fmax(fabs(ay0), fabs(az0))));
-        umax = fmaxf(umax, (float)fmax(fmax(fabs(Ux), fmax(fabs(Uy), fabs(Uz))),
-                                       fmax(fabs(Vx), fmax(fabs(Vy), fabs(Vz)))));
+        f4 a0, a1;
+        atom_data(W, lp, fr, i, a0, a1);
+        W.AD[2 * i] = a0;
+        W.AD[2 * i + 1] = a1;
+        r2max = fmaxf(r2max, a1.w);
     }
     r2max = wave_maxf(r2max);
-    sw.inside = __ballot(outside) == 0;
-    amax = wave_maxf(amax);
-    umax = wave_maxf(umax);
-    // sentinel rows after the list: U = V = 0 at the centre of cell (0, 0, nz),
-    // whose linear index is the zero sentinel cell
-    if (lane < kMvPad) {
-        const f4 z4 = mk4(0.f, 0.f, 0.f, 0.f);
-        W.MV[3 * (sw.m + lane)] = mk4(0.5f, 0.5f, (float)P.dim[2] + 0.5f, 0.f);
-        W.MV[3 * (sw.m + lane) + 1] = z4;
-        W.MV[3 * (sw.m + lane) + 2] = z4;
-    }
     // Rounding guards (u = 2^-24), each doubled for safety and with the maxima
     // rounded up by 1 %:
     //  cell: Y = fma(s, V, fma(c, U, P0)) from P0, U, V rounded once from FP64
@@ -576,7 +567,6 @@ __device__ __forceinline__ void sweep_setup(const PocketDev& P, const BatchDev& 
     //        the rounded cos/sin adds <= u (3|A| + 4|2B| + 3|2C|) <= 26 u R^2:
     //        74 u R^2 in all.
     const double u32 = 1.0 / 16777216.0;
-    sw.gcell = (float)(2.0 * u32 * (3.0 * 1.01 * amax + 7.0 * 1.01 * umax) + 1e-6);
     const double gc = 2.0 * u32 * 74.0 * 1.01 * (double)r2max + 1e-6;
     sw.thr_lo = (float)(B.cd2 - gc);
     sw.thr_hi = (float)(B.cd2 + gc);
@@ -635,6 +625,49 @@ __device__ __forceinline__ void sweep_setup(const PocketDev& P, const BatchDev& 
     }
     sw.nsurv = nsurv;
     sw.pruned = nsurv <= kSurvCap;
+    // moving-atom rows for the score pass, over the memory of the per-atom data
+    // (no longer read: the prune is done)
+    wave_sync();
+    float amax = 0.f, umax = 0.f;
+    bool outside = false;
+    const double ih = P.inv_h;
+    const double bx = (double)P.dim[0] - 0.01, by = (double)P.dim[1] - 0.01, bz = (double)P.dim[2] - 0.01;
+    for (int j = lane; j < sw.m; j += kWave) {
+        int i = ldg(sw.mvl + j);
+        double ux = Xx[i] - px, uy = Xy[i] - py, uz = Xz[i] - pz;
+        double ku = kx * ux + ky * uy + kz * uz;
+        double ax0 = (px + ku * kx) * ih - (double)P.lo[0];
+        double ay0 = (py + ku * ky) * ih - (double)P.lo[1];
+        double az0 = (pz + ku * kz) * ih - (double)P.lo[2];
+        double Ux = (ux - ku * kx) * ih, Uy = (uy - ku * ky) * ih, Uz = (uz - ku * kz) * ih;
+        double Vx = (ky * uz - kz * uy) * ih, Vy = (kz * ux - kx * uz) * ih, Vz = (kx * uy - ky * ux) * ih;
+        W.MV[3 * j] = mk4((float)ax0, (float)ay0, (float)az0, 0.f);
+        W.MV[3 * j + 1] = mk4((float)Ux, (float)Uy, (float)Uz, 0.f);
+        W.MV[3 * j + 2] = mk4((float)Vx, (float)Vy, (float)Vz, 0.f);
+        // the circle's extent along axis a is P0_a +- sqrt(U_a^2 + V_a^2): keep it
+        // 0.01 cell inside the box on both sides
+        const double ex2 = Ux * Ux + Vx * Vx, ey2 = Uy * Uy + Vy * Vy, ez2 = Uz * Uz + Vz * Vz;
+        const double lx = ax0 - 0.01, ly = ay0 - 0.01, lz = az0 - 0.01;
+        const double hx = bx - ax0, hy = by - ay0, hz = bz - az0;
+        outside |= !(lx >= 0.0 && ly >= 0.0 && lz >= 0.0 && hx >= 0.0 && hy >= 0.0 && hz >= 0.0 && ex2 <= lx * lx &&
+                     ey2 <= ly * ly && ez2 <= lz * lz && ex2 <= hx * hx && ey2 <= hy * hy && ez2 <= hz * hz);
+        amax = fmaxf(amax, (float)fmax(fabs(ax0), fmax(fabs(ay0), fabs(az0))));
+        umax = fmaxf(umax, (float)fmax(fmax(fabs(Ux), fmax(fabs(Uy), fabs(Uz))),
+                                       fmax(fabs(Vx), fmax(fabs(Vy), fabs(Vz)))));
+    }
+    sw.inside = __ballot(outside) == 0;
+    amax = wave_maxf(amax);
+    umax = wave_maxf(umax);
+    // sentinel rows after the list: U = V = 0 at the centre of cell (0, 0, nz),
+    // whose linear index is the zero sentinel cell
+    if (lane < kMvPad) {
+        const f4 z4 = mk4(0.f, 0.f, 0.f, 0.f);
+        W.MV[3 * (sw.m + lane)] = mk4(0.5f, 0.5f, (float)P.dim[2] + 0.5f, 0.f);
+        W.MV[3 * (sw.m + lane) + 1] = z4;
+        W.MV[3 * (sw.m + lane) + 2] = z4;
+    }
+    sw.gcell = (float)(2.0 * u32 * (3.0 * 1.01 * amax + 7.0 * 1.01 * umax) + 1e-6);
+
     wave_sync();
 }
 
@@ -758,8 +791,10 @@ __device__ void flush(unsigned long long* counters, Acc& acc) {
 
 // Per-ligand form: one launch per ligand, one wave per orientation.
 template <int NB, int PPL>
-// At least 3 waves per SIMD (<= 168 VGPRs): the kernel sits near that bound, and
-// dropping to 2 waves costs far more than a few spills.
+// Register budget: the per-ligand form at >= 3 waves per SIMD (<= 168 VGPRs),
+// the persistent form at >= 4 (<= 128 VGPRs, a few spills outside the inner
+// loops); with 2-wave blocks the LDS slices then admit 4 waves per SIMD for
+// ligands of up to 80 atoms.
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) dock_ligand_kernel(const PocketDev* __restrict__ Pp,
                                                           const BatchDev* __restrict__ Bp,
                                                           unsigned long long* counters, int lig, int nmax) {
@@ -783,7 +818,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) d
 // Batched form: a persistent grid; every wave pops (ligand, orientation
 // block) items from the device queue until it is empty.
 template <int NB, int PPL>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) dock_persistent_kernel(const PocketDev* __restrict__ Pp,
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) dock_persistent_kernel(const PocketDev* __restrict__ Pp,
                                                               const BatchDev* __restrict__ Bp,
                                                               unsigned long long* counters, int nmax) {
     const PocketDev& P = *Pp;

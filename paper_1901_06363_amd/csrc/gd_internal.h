@@ -117,7 +117,7 @@ struct PoseDev {
 };
 
 struct Tiling {
-    int waves_per_block = 4;
+    int waves_per_block = 2;
     int angle_block = 32;
     int pairs_per_lane = 4;
 };
