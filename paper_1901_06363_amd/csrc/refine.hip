@@ -135,6 +135,11 @@ __device__ void pose_forward(const TreeDev& T, const PoseState& S, const float* 
 #pragma unroll
     for (int k = 0; k < kSlots; k++)
         for (int a = 0; a < 3; a++) Ys[k][a] = S.x0[k][a];
+    // Lane r holds sin/cos of torsion r (one torsion per lane at most); each
+    // edge reads its pair with a uniform readlane instead of evaluating it.
+    static_assert(kMaxRot <= kWave, "one torsion per lane");
+    float s_lane = 0.f, c_lane = 1.f;
+    if (lane_id() < S.nr) sincosf(tau[lane_id()], &s_lane, &c_lane);
     for (int e = 0; e < S.nr; e++) {
         const int4 te = T.tree[S.tree0 + e];
         const int ia = __builtin_amdgcn_readfirstlane(te.x), ib = __builtin_amdgcn_readfirstlane(te.y);
@@ -153,8 +158,9 @@ __device__ void pose_forward(const TreeDev& T, const PoseState& S, const float* 
             ax[4] = ky;
             ax[5] = kz;
         }
-        float s, c;
-        sincosf(tau[te.z], &s, &c);
+        const int rz = __builtin_amdgcn_readfirstlane(te.z);
+        const float s = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(s_lane), rz));
+        const float c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(c_lane), rz));
         float tt = 1.f - c;
         float R[9] = {tt * kx * kx + c,      tt * kx * ky - s * kz, tt * kx * kz + s * ky,
                       tt * kx * ky + s * kz, tt * ky * ky + c,      tt * ky * kz - s * kx,
