@@ -10,6 +10,8 @@ Parity status per function (what pins each one is listed in the tests):
   schedules / tiles  pinned: Eq. 2/3 and the paper's 18-degree example
   dock (Alg. 2)      pinned: pose-count closed form, kinematic invariants,
                      independent brute force over torsion combinations
+  continuous Eq. 1   pinned: exact rational brute force, one-point closed form,
+                     lattice and permutation invariances
   overlap values     parity unpinned against the paper's own numbers (the paper
                      prints no scores and its figures are missing)
 """
@@ -82,6 +84,8 @@ def _load():
         lib.orc_topk.restype = ctypes.c_int
         lib.orc_overlap.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_double]
         lib.orc_overlap.restype = ctypes.c_double
+        lib.orc_overlap_continuous.argtypes = [P, ctypes.c_int, P, P]
+        lib.orc_overlap_continuous.restype = ctypes.c_double
         lib.orc_score_poses.argtypes = [P, ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P, P, P, ctypes.c_double,
                                         ctypes.c_int, P, P]
         lib.orc_score_poses.restype = ctypes.c_int
@@ -148,6 +152,14 @@ class OraclePocket:
     def score_xyz(self, X) -> int:
         X = np.ascontiguousarray(X, dtype=np.float64).reshape(-1, 3)
         return int(_load().orc_score_xyz(self._ptr, len(X), _p(X)))
+
+    def overlap_continuous(self, X):
+        """Eq. 1 over the raw points: (sum over atoms of the smallest squared
+        distance, per-atom minima, overlap l / sum)."""
+        X = np.ascontiguousarray(X, dtype=np.float64).reshape(-1, 3)
+        m = np.zeros(len(X))
+        s = float(_load().orc_overlap_continuous(self._ptr, len(X), _p(X), _p(m)))
+        return s, m, (len(X) / s if s > 0 else float("inf"))
 
 
 def tile_size(hp: int) -> int:

@@ -508,6 +508,31 @@ int orc_topk(int n, const int64_t* S, const uint8_t* clash, int k, int* out) {
 double orc_overlap(int l, int64_t S, double h) { return (double)l / (h * h * (double)S); }
 
 /*
+ * Eq. 1 without the lattice: each atom's smallest squared distance to any
+ * pocket point (the points' FP32 input widened to FP64), summed over the
+ * atoms in index order.  The squared distance of one pair is dx^2 + dy^2 +
+ * dz^2 formed as fma(dz, dz, fma(dy, dy, dx * dx)): the plain definition with
+ * IEEE 754 fused multiply-add rounding.  X is l x 3 row-major FP64; min_d2
+ * (optional) receives the per-atom minima.  Returns the sum, from which the
+ * overlap is l / sum (+inf when the sum is 0).
+ */
+double orc_overlap_continuous(const orc_pocket* P, int l, const double* X, double* min_d2) {
+    double sum = 0.0;
+    for (int i = 0; i < l; i++) {
+        double best = INFINITY;
+        for (int j = 0; j < P->n_points; j++) {
+            const double dx = X[3 * i] - P->pts[3 * j];
+            const double dy = X[3 * i + 1] - P->pts[3 * j + 1];
+            const double dz = X[3 * i + 2] - P->pts[3 * j + 2];
+            best = fmin(best, fma(dz, dz, fma(dy, dy, dx * dx)));
+        }
+        if (min_d2) min_d2[i] = best;
+        sum += best;
+    }
+    return sum;
+}
+
+/*
  * Exact score of given poses (FP32 coordinates widened to FP64): S and the
  * whole-ligand clash flag, for one ligand topology.
  */

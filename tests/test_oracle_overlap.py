@@ -1,0 +1,115 @@
+"""Pins of the oracle's continuous Eq. 1 (no lattice) and of the Eq. 5 /
+Pareto host logic of the knob exploration.
+
+Eq. 1 (Section II-B): o = l / sum_i min_j d^2(L_i, P_j).  Independent
+references: exact rational arithmetic (fractions), closed forms, the lattice
+reading of Eq. 1 (itself pinned elsewhere) at cell centres, and invariances.
+"""
+import itertools
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import configs
+
+
+def _exact_sum(X, P):
+    """Exact rational sum over atoms of the smallest squared distance."""
+    tot = Fraction(0)
+    for a in X:
+        best = None
+        for p in P:
+            d = sum((Fraction(float(a[k])) - Fraction(float(p[k]))) ** 2 for k in range(3))
+            best = d if best is None or d < best else best
+        tot += best
+    return tot
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_continuous_matches_exact_rationals(seed):
+    # The FP64 sum must agree with the exact rational value within its
+    # rounding bound: each squared distance errs by <= 4u d^2 (three
+    # differences and two fused roundings), the minimum keeps that bound, and
+    # l sequential additions add <= l u of the total (u = 2^-53).
+    rng = np.random.default_rng(seed)
+    P = (rng.normal(size=(int(rng.integers(1, 40)), 3)) * 5).astype(np.float32)
+    X = rng.normal(size=(int(rng.integers(1, 12)), 3)) * 6
+    pk = oracle.OraclePocket(P, 0.5)
+    s, m, o = pk.overlap_continuous(X)
+    exact = _exact_sum(X, P)
+    u = 2.0 ** -53
+    assert abs(Fraction(s) - exact) <= (6 + len(X)) * u * exact
+    assert o == len(X) / s
+    for i, a in enumerate(X):
+        e = _exact_sum(a[None, :], P)
+        assert abs(Fraction(float(m[i])) - e) <= 6 * u * e
+
+
+def test_continuous_one_point_closed_form():
+    # One pocket point: the minimum is the distance to it; offsets (3, 4, 0),
+    # (1, 2, 2) and (0, 0, 0) give 25 + 9 + 0 = 34 exactly.
+    p = np.array([[1.5, -2.25, 0.75]], np.float32)
+    X = p.astype(np.float64) + np.array([[3, 4, 0], [1, 2, 2], [0, 0, 0]], np.float64)
+    s, m, o = oracle.OraclePocket(p, 0.5).overlap_continuous(X)
+    assert list(m) == [25.0, 9.0, 0.0]
+    assert s == 34.0 and o == 3 / 34.0
+    # every atom on a point: the sum is 0 and the overlap +inf
+    s0, _, o0 = oracle.OraclePocket(p, 0.5).overlap_continuous(p.astype(np.float64))
+    assert s0 == 0.0 and o0 == float("inf")
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_continuous_equals_lattice_score_at_cell_centres(seed):
+    # With every point and atom at a cell centre ((c + 1/2) h), the smallest
+    # squared distance is h^2 min |c - c'|^2 = h^2 D(c): continuous Eq. 1 and
+    # its lattice reading agree exactly (all values are exact binary fractions).
+    rng = np.random.default_rng(100 + seed)
+    h = 0.5
+    cells = rng.integers(-20, 20, size=(int(rng.integers(1, 30)), 3))
+    P = ((cells + 0.5) * h).astype(np.float32)
+    ac = rng.integers(-30, 30, size=(int(rng.integers(1, 20)), 3))
+    X = (ac + 0.5) * h
+    pk = oracle.OraclePocket(P, h)
+    s, m, _ = pk.overlap_continuous(X)
+    assert s == h * h * pk.score_xyz(X)
+    for i, c in enumerate(ac):
+        assert m[i] == h * h * pk.D(*c)
+
+
+def test_continuous_invariances():
+    # (a coarse lattice keeps the oracle's lattice memo small; the continuous
+    # score does not use it)
+    H = 8.0
+    rng = np.random.default_rng(7)
+    # integer coordinates: every difference and square is exact, so a joint
+    # integer translation, an axis permutation or a point reordering leaves
+    # each minimum and the sum bit-identical
+    P = rng.integers(-50, 50, size=(60, 3)).astype(np.float32)
+    X = rng.integers(-60, 60, size=(25, 3)).astype(np.float64)
+    s0, m0, _ = oracle.OraclePocket(P, H).overlap_continuous(X)
+    t = np.array([17, -9, 33])
+    s1, m1, _ = oracle.OraclePocket(P + t, H).overlap_continuous(X + t)
+    assert s1 == s0 and np.array_equal(m1, m0)
+    for perm in itertools.permutations(range(3)):
+        s2, m2, _ = oracle.OraclePocket(P[:, perm], H).overlap_continuous(X[:, perm])
+        assert s2 == s0 and np.array_equal(m2, m0)
+    s3, m3, _ = oracle.OraclePocket(P[rng.permutation(len(P))], H).overlap_continuous(X)
+    assert s3 == s0 and np.array_equal(m3, m0)
+    # adding a far point changes nothing; adding an atom's own position as a
+    # point makes that atom's minimum 0
+    s4, m4, _ = oracle.OraclePocket(np.vstack([P, [[500.0, 500.0, 500.0]]]), H).overlap_continuous(X)
+    assert s4 == s0
+    s5, m5, _ = oracle.OraclePocket(np.vstack([P, X[3:4].astype(np.float32)]), H).overlap_continuous(X)
+    assert m5[3] == 0.0 and np.all(m5 <= m0)
+
+
+def test_continuous_monotone_in_points():
+    # A superset of points can only lower every minimum (min over a larger set).
+    rng = np.random.default_rng(9)
+    P = (rng.normal(size=(200, 3)) * 4).astype(np.float32)
+    X = rng.normal(size=(30, 3)) * 5
+    _, m_half, _ = oracle.OraclePocket(P[:100], 8.0).overlap_continuous(X)
+    _, m_all, _ = oracle.OraclePocket(P, 8.0).overlap_continuous(X)
+    assert np.all(m_all <= m_half)
