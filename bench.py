@@ -29,33 +29,36 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X published FP32 vector peak
+FP64_PEAK_TFLOPS = 78.6          # MI355X published FP64 peak (vector and matrix)
 # sources of the docking kernel; the HBM traffic measured with rocprofv3 counters
 # is reported only while they are unchanged since the measurement
 KERNEL_SOURCES = ["dock.hip", "device_common.h", "gd_internal.h"]
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "dock_persistent_kernel.screen.traffic.md")
+OVERLAP_SOURCES = ["overlap.hip", "gd_internal.h"]
+OVERLAP_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "overlap_min_kernel.screen_top8.traffic.md")
 
 
-def kernel_fingerprint():
+def kernel_fingerprint(sources=None):
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources or KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_1901_06363_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the docking kernel from the committed counter
-    summary (FETCH_SIZE and WRITE_SIZE, each scaled by a plain copy kernel's
+def measured_traffic(profile=TRAFFIC_PROFILE, sources=None):
+    """HBM bytes per launch of a kernel from its committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by a plain copy kernel's
     reading), or None when the kernel sources changed since it was taken."""
     try:
         vals = {}
-        with open(TRAFFIC_PROFILE) as fh:
+        with open(profile) as fh:
             for ln in fh:
                 if ":" in ln and ln.startswith("- "):
                     k, v = ln[2:].split(":", 1)
                     vals[k.strip()] = v.strip().strip("`")
-        if vals.get("kernel source fingerprint") != kernel_fingerprint():
+        if vals.get("kernel source fingerprint") != kernel_fingerprint(sources):
             return None
         return dict(fetch=float(vals["HBM bytes read per launch"]), write=float(vals["HBM bytes written per launch"]))
     except (OSError, KeyError, ValueError):
@@ -121,6 +124,72 @@ def refine_leg(gd, torch, np, n_lig):
                 gather_GBps=gather_bytes / (kms * 1e-3) / 1e9)
 
 
+def continuous_leg(gd, torch, np, P, out, ligs, n_points, reps=10):
+    """Continuous Eq. 1 (no lattice) over the raw pocket points for every
+    top-k pose of the screen: per atom the smallest squared distance to any of
+    the points in FP64, per pose the in-order sum and l / sum."""
+    from paper_1901_06363_amd.stream import poses_from_topk
+    pose_lig, px, py, pz = poses_from_topk(out, ligs)
+    lay = gd.OverlapLayout(np.diff(np.asarray(ligs.atom_off))[pose_lig])
+    for _ in range(2):
+        gd.overlap_continuous(P, lay, px, py, pz)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        gd.overlap_continuous(P, lay, px, py, pz)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    pairs = lay.n_atoms * n_points
+    achieved = 8.0 * pairs / (ms * 1e-3) / 1e12  # 3 differences, 3 squares, 2 additions per pair
+    full = out.xyz.shape[0] == 10_000
+    tr = measured_traffic(OVERLAP_TRAFFIC_PROFILE, OVERLAP_SOURCES) if full else None
+    return dict(workload="continuous Eq. 1 rescoring of the screen's top-%d poses: %d poses, %d atoms x %d pocket "
+                         "points, FP64" % (out.xyz.shape[1], lay.n_poses, lay.n_atoms, n_points),
+                poses=lay.n_poses, atoms=lay.n_atoms, points=n_points, ms=ms, pairs_per_s=pairs / (ms * 1e-3),
+                poses_per_s=lay.n_poses / (ms * 1e-3),
+                roofline=dict(bound="alu", kernel="overlap_min_kernel (+ overlap_sum_kernel)", achieved=achieved,
+                              peak=FP64_PEAK_TFLOPS, unit="TFLOP/s", frac=achieved / FP64_PEAK_TFLOPS,
+                              algo_flops_per_launch=8.0 * pairs,
+                              traffic=(tr["fetch"] + tr["write"]) if tr else None,
+                              traffic_unit="HBM bytes per launch of overlap_min_kernel (rocprofv3 FETCH_SIZE + "
+                                           "WRITE_SIZE, copy-calibrated)"))
+
+
+def dse_leg(gd, torch, np, spaces, n_lig):
+    """Knob exploration (flat and/or full design space) on the exploration
+    workload: per configuration the docking and continuous re-scoring time,
+    atoms/s, the top-1 % mean continuous overlap, its Eq. 5 degradation
+    against the baseline and the Pareto front."""
+    from synth import configs
+    from paper_1901_06363_amd import dse
+    w = configs.DSE
+    n_lig = n_lig or w.n_ligands
+    ligs = w.ligands(0, n_lig)
+    P = gd.Pocket(w.pocket_points(), 0.5, w.pad)
+    q = w.quaternions()
+    res = {}
+    for sp in spaces:
+        t0 = time.perf_counter()
+
+        def prog(i, n, rec):
+            log("dse %s %d/%d: hp %d lp %d thr %.1f reps %d peel %d: %.1f ms, top mean %.5f (%.0f s)" % (
+                sp, i + 1, n, rec["hp"], rec["lp"], rec["threshold"], rec["repetitions"], rec["refine"],
+                rec["time_ms"], rec["top_mean"], time.perf_counter() - t0))
+        recs = dse.explore(P, ligs, q, space=sp, top_k=w.top_k, progress=prog)
+        base = [r for r in recs if dse.is_baseline(r)][0]
+        front = sorted((r for r in recs if r["pareto"]), key=lambda r: -r["atoms_per_s"])
+        res[sp] = dict(configs=recs, baseline_ms=base["time_ms"],
+                       front=[dict(hp=r["hp"], lp=r["lp"], threshold=r["threshold"], repetitions=r["repetitions"],
+                                   refine=r["refine"], speedup=base["time_ms"] / r["time_ms"],
+                                   degradation=r["degradation"]) for r in front],
+                       wall_s=time.perf_counter() - t0)
+    return dict(workload="dse: %d ligands (28-120 atoms, 2-16 rotatable bonds) x 4,000-point pocket, %d "
+                         "orientations, top-1 pose re-scored with continuous Eq. 1; degradation over the top 1 %% "
+                         "ligands (Eq. 5)" % (n_lig, len(q)), spaces=res)
+
+
 def large_leg(gd, torch, n_chunks):
     """The large library streamed through the persistent kernel in chunks of
     65,536 ligands (host preparation of the next chunk overlaps docking), with
@@ -162,6 +231,9 @@ def main():
     ap.add_argument("--refine-only", action="store_true", help="run only the refinement leg (profiling)")
     ap.add_argument("--refine-ligands", type=int, default=4096)
     ap.add_argument("--large-chunks", type=int, default=0, help="also stream this many chunks of the large library")
+    ap.add_argument("--dse", type=str, default="", help="run only the knob exploration: flat, full or both")
+    ap.add_argument("--dse-ligands", type=int, default=0)
+    ap.add_argument("--no-continuous", action="store_true")
     ap.add_argument("--tiling", type=str, default="")
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--n-ligands", type=int, default=0, help="override the ligand count (testing only)")
@@ -171,7 +243,7 @@ def main():
     args = ap.parse_args()
 
     if args.fingerprint:
-        print(kernel_fingerprint())
+        print(kernel_fingerprint(), kernel_fingerprint(OVERLAP_SOURCES))
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (ligand batches shard trivially "
@@ -198,6 +270,10 @@ def main():
         return
     if args.refine_only:
         print(json.dumps(refine_leg(gd, torch, np, args.refine_ligands)), flush=True)
+        return
+    if args.dse:
+        spaces = ["flat", "full"] if args.dse == "both" else [args.dse]
+        print(json.dumps(dse_leg(gd, torch, np, spaces, args.dse_ligands)), flush=True)
         return
     w = configs.SCREEN
     n_lig = args.n_ligands or w.n_ligands
@@ -273,6 +349,11 @@ def main():
         log("per-ligand launches:", per_lig)
         del rp, hp_
 
+    cont = None
+    if not args.no_continuous:
+        cont = continuous_leg(gd, torch, np, P, out, ligs, len(pts))
+        log("continuous rescoring:", cont)
+
     ref = None
     if not args.no_refine and args.refine_ligands > 0:
         ref = refine_leg(gd, torch, np, args.refine_ligands)
@@ -321,6 +402,7 @@ def main():
         "prep_s": prep_s,
         "end_to_end_poses_per_s_incl_prep": B.poses_expected / (prep_s + dt / args.steps),
         "per_ligand": per_lig,
+        "continuous": cont,
         "refine": ref,
         "large": large,
         "roofline": {

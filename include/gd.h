@@ -255,6 +255,36 @@ gd_status gd_score_poses(const gd_pocket* pocket, const gd_ligands* topo, int32_
                          int32_t clash_min_bonds, void* stream, int32_t* S_out, uint8_t* clash_out);
 
 /* ------------------------------------------------------------------------ */
+/* Continuous overlap (Eq. 1 without the lattice)                            */
+
+/*
+ * Eq. 1 (Section III-A) on the pocket's raw points: for every atom the
+ * smallest squared distance to any of the points given to gd_create_pocket,
+ * then for every pose the sum over its atoms in index order and the overlap
+ * o = l / sum.  FP64 throughout: coordinates are the FP32 inputs widened, one
+ * pair's squared distance is fma(dz, dz, fma(dy, dy, dx * dx)).  Brute force
+ * over all points, O(l p) per pose, like the paper's overlap measure.
+ *   pose_off     device int32[n_poses + 1]: pose p owns atom rows
+ *                pose_off[p] .. pose_off[p + 1] - 1; must start at 0, not
+ *                decrease and end at n_atoms (not checked: a device array;
+ *                offsets outside [0, n_atoms] are clamped, never read past)
+ *   px, py, pz   device float[n_atoms], the poses' atoms in that order
+ *   min_d2_out   device double[n_atoms]: per-atom minima (A^2); also the
+ *                input of the per-pose sums, so it is required
+ *   sum_out      device double[n_poses]: sum of the pose's minima
+ *   overlap_out  device double[n_poses] or NULL: l / sum (+inf when the sum
+ *                is 0, NaN for an empty pose)
+ * Caller-owned buffers; nothing is allocated.  Asynchronous on `stream`.
+ * Errors: GD_ERR_ARG (null pocket, negative sizes, null arrays when there is
+ * work), GD_ERR_CAPACITY (n_atoms > 2^31 - 1, beyond int32 offsets),
+ * GD_ERR_HIP (launch failure).
+ * n_poses = 0 is a no-op.
+ */
+gd_status gd_overlap_continuous(const gd_pocket* pocket, int32_t n_poses, const int32_t* pose_off, int64_t n_atoms,
+                                const float* px, const float* py, const float* pz, void* stream,
+                                double* min_d2_out, double* sum_out, double* overlap_out);
+
+/* ------------------------------------------------------------------------ */
 /* Differentiable refinement on the blurred density                          */
 
 /*

@@ -159,7 +159,9 @@ class OraclePocket:
         X = np.ascontiguousarray(X, dtype=np.float64).reshape(-1, 3)
         m = np.zeros(len(X))
         s = float(_load().orc_overlap_continuous(self._ptr, len(X), _p(X), _p(m)))
-        return s, m, (len(X) / s if s > 0 else float("inf"))
+        with np.errstate(divide="ignore", invalid="ignore"):
+            o = float(np.float64(len(X)) / np.float64(s))  # IEEE: +inf for 0 sum, NaN for no atoms
+        return s, m, o
 
 
 def tile_size(hp: int) -> int:

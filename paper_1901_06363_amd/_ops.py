@@ -42,6 +42,44 @@ def score_poses(pocket, ligands, pose_lig, px, py, pz, clash_dist=2.0, clash_min
     return S, clash
 
 
+class OverlapLayout:
+    """Device pose offsets of a fixed list of pose sizes, reusable across
+    calls of overlap_continuous (no host-to-device copy per call)."""
+
+    def __init__(self, counts):
+        torch = _torch()
+        cnt = np.ascontiguousarray(counts, dtype=np.int64)
+        if np.any(cnt < 0):
+            raise ValueError("negative atom count")
+        off = np.zeros(len(cnt) + 1, np.int64)
+        np.cumsum(cnt, out=off[1:])
+        if off[-1] >= 2 ** 31:
+            raise ValueError("more than 2^31 - 1 atoms in one call")
+        self.n_poses, self.n_atoms = len(cnt), int(off[-1])
+        self.pose_off = torch.from_numpy(off.astype(np.int32)).to("cuda")
+
+
+def overlap_continuous(pocket, counts, px, py, pz, stream=None):
+    """Eq. 1 on the pocket's raw points for poses given as device float32
+    rows (px, py, pz) grouped by pose, ``counts[p]`` atoms for pose p (or an
+    OverlapLayout of them).  Returns device float64 tensors (min_d2 per atom,
+    sum per pose, overlap per pose)."""
+    torch = _torch()
+    lay = counts if isinstance(counts, OverlapLayout) else OverlapLayout(counts)
+    n, n_atoms, pose_off = lay.n_poses, lay.n_atoms, lay.pose_off
+    if n_atoms > 0 and (px.numel() < n_atoms or py.numel() < n_atoms or pz.numel() < n_atoms):
+        raise ValueError("coordinate arrays shorter than the atom count")
+    for t in (px, py, pz):
+        if n_atoms > 0 and (t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous()):
+            raise TypeError("coordinates must be contiguous float32 CUDA tensors")
+    min_d2 = torch.empty(max(n_atoms, 1), dtype=torch.float64, device="cuda")
+    s = torch.empty(max(n, 1), dtype=torch.float64, device="cuda")
+    o = torch.empty(max(n, 1), dtype=torch.float64, device="cuda")
+    _abi.check(_abi.load().gd_overlap_continuous(pocket.handle, n, _dp(pose_off), n_atoms, _dp(px), _dp(py), _dp(pz),
+                                                 _stream_ptr(stream), _dp(min_d2), _dp(s), _dp(o)))
+    return min_d2[:n_atoms], s[:n], o[:n]
+
+
 def _prm(t, q, tau, n):
     torch = _torch()
     t = t.contiguous().float()

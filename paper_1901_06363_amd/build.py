@@ -13,7 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgd.so")
-SOURCES = ["dock.hip", "score.hip", "refine.hip", "runtime.cpp", "api_extra.cpp", "refine_api.cpp"]
+SOURCES = ["dock.hip", "score.hip", "refine.hip", "overlap.hip", "runtime.cpp", "api_extra.cpp", "refine_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-ffp-contract=off", "-fno-fast-math",

@@ -183,6 +183,24 @@ gd_status gd_score_poses(const gd_pocket* pocket, const gd_ligands* topo, int32_
                        S_out, clash_out);
 }
 
+gd_status gd_overlap_continuous(const gd_pocket* pocket, int32_t n_poses, const int32_t* pose_off, int64_t n_atoms,
+                                const float* px, const float* py, const float* pz, void* stream, double* min_d2_out,
+                                double* sum_out, double* overlap_out) {
+    clear_error();
+    if (!pocket) return fail(GD_ERR_ARG, "gd_overlap_continuous: null pocket");
+    if (n_poses < 0 || n_atoms < 0) return fail(GD_ERR_ARG, "gd_overlap_continuous: negative size");
+    if (n_atoms > (int64_t)INT32_MAX)
+        return fail(GD_ERR_CAPACITY, "gd_overlap_continuous: more atoms than int32 offsets address");
+    if (n_poses == 0) return GD_OK;
+    if (!pose_off || !sum_out) return fail(GD_ERR_ARG, "gd_overlap_continuous: null pose offsets or sums");
+    if (n_atoms > 0 && (!px || !py || !pz || !min_d2_out))
+        return fail(GD_ERR_ARG, "gd_overlap_continuous: null coordinates or minima");
+    hipError_t e = launch_overlap((const double*)pocket->pts.ptr, pocket->pts_pad, pocket->pts_pad, pose_off, n_poses,
+                                  px, py, pz, n_atoms, min_d2_out, sum_out, overlap_out, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "gd_overlap_continuous");
+    return GD_OK;
+}
+
 gd_status gd_batch_autotune(const gd_pocket* pocket, gd_batch* batch, void* stream, int32_t reps,
                             const char* cache_path, gd_tiling* chosen) {
     clear_error();

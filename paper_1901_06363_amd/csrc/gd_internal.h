@@ -163,5 +163,11 @@ hipError_t launch_accept(const PoseDev& X, int n_poses, const int32_t* n_atoms, 
                          const uint8_t* c_in, hipStream_t s);
 hipError_t launch_replay(const PocketDev& P, const BatchDev& B, const gd_pose_rec* recs, float* xyz, int nmax,
                          hipStream_t s);
+// continuous Eq. 1: pocket points as three FP64 planes of `pitch`, padded to
+// n_pad (a multiple of kOvUnroll) with far points
+constexpr int kOvUnroll = 16;
+hipError_t launch_overlap(const double* pts, int n_pad, int pitch, const int32_t* pose_off, int n_poses,
+                          const float* px, const float* py, const float* pz, int64_t n_atoms, double* min_out,
+                          double* sum_out, double* o_out, hipStream_t s);
 
 }  // namespace gd

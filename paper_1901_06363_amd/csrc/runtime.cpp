@@ -224,6 +224,17 @@ gd_status create_pocket(const gd_pocket_desc* desc, hipStream_t stream, gd_pocke
     if ((e = upload_trig_tables()) != hipSuccess) return hip_fail(e, "gd_create_pocket");
     if ((e = P->edt.upload(edt.data(), edt.size() * 2, stream)) != hipSuccess) return hip_fail(e, "gd_create_pocket");
     if ((e = P->occ.upload(occ.data(), occ.size() * 4, stream)) != hipSuccess) return hip_fail(e, "gd_create_pocket");
+    {
+        // raw points for the continuous overlap: FP64 planes padded with far points
+        const int pad_n = (n + kOvUnroll - 1) / kOvUnroll * kOvUnroll;
+        std::vector<double> pl((size_t)3 * pad_n, 1e150);
+        for (int i = 0; i < n; i++)
+            for (int a = 0; a < 3; a++) pl[(size_t)a * pad_n + i] = (double)desc->xyz[3 * i + a];
+        if ((e = P->pts.upload(pl.data(), pl.size() * sizeof(double), stream)) != hipSuccess)
+            return hip_fail(e, "gd_create_pocket");
+        P->n_points = n;
+        P->pts_pad = pad_n;
+    }
     PocketDev& D = P->dev;
     D.edt = (const uint16_t*)P->edt.ptr;
     D.n_cells = (int32_t)total;

@@ -19,6 +19,11 @@ Each recipe fixes the generator streams, sizes and knobs of one workload:
              with a rigid 3-6 ring) x 1 pocket (10,000 points, 16/12/9 A);
              1024 orientations, 10-degree steps, chunks of 65,536, top-8
              refined.
+  dse        20,000 ligands (atoms U[28,120], rotatable bonds U[2,16]: the
+             paper's library spans 28-153 atoms and 2-53 rotamers, capped here
+             at the library's 128-atom limit and a moderate rotamer count) x
+             the screen pocket; 32 orientations, top-1 pose per ligand; the
+             knob configurations of the flat and full design spaces.
 
 Pocket centres sit off the lattice origin so that no symmetry of the grid is
 accidentally exploited.
@@ -94,7 +99,10 @@ REFINE = Workload("refine", lig_seed=4, n_ligands=4096, lmin=20, lmax=80, bmin=2
 LARGE = Workload("large", lig_seed=5, n_ligands=1_000_000, lmin=15, lmax=120, bmin=0, bmax=16, ring_frac=0.05,
                  pockets=[(1010, 10_000, (16.0, 12.0, 9.0))], n_orient=1024, hp=10, top_k=8, chunk=65_536, pad=20.0)
 
-ALL = {w.name: w for w in (SINGLE, SCREEN, GRID, REFINE, LARGE)}
+DSE = Workload("dse", lig_seed=6, n_ligands=20_000, lmin=28, lmax=120, bmin=2, bmax=16, ring_frac=0.0,
+               pockets=[(1001, 4000, (12.0, 9.0, 7.0))], n_orient=32, hp=1, repetitions=3, top_k=1, pad=20.0)
+
+ALL = {w.name: w for w in (SINGLE, SCREEN, GRID, REFINE, LARGE, DSE)}
 
 
 def tiny_ligand(seed: int, l: int, nrot: int):

@@ -1,7 +1,7 @@
 """Pins of the oracle's continuous Eq. 1 (no lattice) and of the Eq. 5 /
 Pareto host logic of the knob exploration.
 
-Eq. 1 (Section II-B): o = l / sum_i min_j d^2(L_i, P_j).  Independent
+Eq. 1 (Section III-A): o = l / sum_i min_j d^2(L_i, P_j).  Independent
 references: exact rational arithmetic (fractions), closed forms, the lattice
 reading of Eq. 1 (itself pinned elsewhere) at cell centres, and invariances.
 """
@@ -113,3 +113,60 @@ def test_continuous_monotone_in_points():
     _, m_half, _ = oracle.OraclePocket(P[:100], 8.0).overlap_continuous(X)
     _, m_all, _ = oracle.OraclePocket(P, 8.0).overlap_continuous(X)
     assert np.all(m_all <= m_half)
+
+
+# --------------------------------------------------------------------------
+# Knob exploration host logic (Sections IV-B, V-B): design spaces, Eq. 5,
+# top-1 % means and the Pareto front
+
+def test_design_space_sizes_and_baseline():
+    from paper_1901_06363_amd import dse
+    flat, full = dse.configurations("flat"), dse.configurations("full")
+    # full factorial sizes of the two spaces listed in Section V-B
+    assert len(flat) == 8 * 3 and len(full) == 4 * 2 * 4 * 3 * 2
+    assert len({tuple(sorted(c.items())) for c in full}) == len(full)
+    # the baseline (hp 1, threshold 0, 3 repetitions, no refinement) is a
+    # member of both spaces: once in flat, once per low-precision step in full
+    assert sum(dse.is_baseline(c) for c in flat) == 1
+    assert sum(dse.is_baseline(c) for c in full) == 2
+    assert all(c["lp"] == c["hp"] and c["threshold"] == 0.0 and not c["refine"] for c in flat)
+
+
+def test_eq5_degradation_closed_forms():
+    from paper_1901_06363_amd import dse
+    assert dse.degradation(5.0, 5.0) == 0.0
+    assert abs(dse.degradation(0.977, 1.0) - 2.3) < 1e-12   # the 2.3 % of Section V-B's first step
+    assert dse.degradation(1.1, 1.0) < 0                     # better than the baseline: negative
+    # top 1 %: ceil(0.01 n) best values (at least one)
+    s = np.arange(250, dtype=float)
+    assert dse.top_fraction_mean(s) == np.mean([249, 248, 247])
+    assert dse.top_fraction_mean([3.0, 1.0]) == 3.0
+    assert dse.top_fraction_mean(s, frac=0.1) == np.mean(np.arange(225, 250))
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_pareto_front_against_brute_force(seed):
+    from paper_1901_06363_amd import dse
+    rng = np.random.default_rng(seed)
+    n = 60
+    t = rng.integers(0, 12, n).astype(float)   # ties on both axes on purpose
+    d = rng.integers(0, 12, n).astype(float)
+    keep = dse.pareto_front(t, d)
+    # reference: sort by throughput descending, degradation ascending, and
+    # keep a point when its degradation is strictly below all earlier ones
+    # (points equal on both axes share their status)
+    order = sorted(range(n), key=lambda i: (-t[i], d[i]))
+    ref = np.zeros(n, bool)
+    best = float("inf")
+    for i in order:
+        if d[i] < best:
+            ref[i] = True
+            best = d[i]
+    for i in range(n):
+        for j in range(n):
+            if t[i] == t[j] and d[i] == d[j]:
+                ref[i] = ref[i] or ref[j]
+    assert np.array_equal(keep, ref)
+    # every excluded point is dominated by a kept one
+    for i in np.nonzero(~keep)[0]:
+        assert np.any(keep & (t >= t[i]) & (d <= d[i]))
