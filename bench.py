@@ -190,6 +190,90 @@ def dse_leg(gd, torch, np, spaces, n_lig):
                          "ligands (Eq. 5)" % (n_lig, len(q)), spaces=res)
 
 
+def tts_leg(gd, torch, np, dse_ligands=5000, records_path=None):
+    """Time-to-solution model (Eq. 4): a profiling campaign of every full-space
+    configuration on 4 pockets x 5 ligand mixes (5,000 ligands each), the
+    per-configuration regressions, their leave-one-pocket-out validation on
+    fresh databases of 1,000-10,000 ligands, and the budget-driven knob choice
+    of the two use-case scenarios with the degradations of a 5,000-ligand
+    exploration."""
+    import synth
+    from synth import configs
+    from paper_1901_06363_amd import dse, tts
+    w = configs.TTS
+    q = w.quaternions()
+    cfgs = dse.configurations("full")
+    pockets = []
+    for k in range(len(w.pockets)):
+        pts = w.pocket_points(k)
+        pockets.append((gd.Pocket(pts, 0.5, w.pad), len(pts)))
+    t0 = time.perf_counter()
+
+    def prog(tag):
+        def f(i, n, rec):
+            if i % 64 == 0 or i == n:
+                log("tts %s %d/%d (%.0f s)" % (tag, i, n, time.perf_counter() - t0))
+        return f
+    train_sets = configs.tts_training_sets()
+    recs = tts.campaign(pockets, train_sets, q, cfgs, warm=False, progress=prog("train"), top_k=1)
+    # floors: 1,000 ligands of the exploration's distribution (mix 2) on pockets 1 and 2
+    mix = 2
+    lo, hi, bl, bh = w.extra["mixes"][mix]
+    small = synth.ligands(w.lig_seed + 10 * mix, 0, 1000, lo, hi, bl, bh, 0.0)
+    fl = {pk: tts.floors(tts.campaign([pockets[pk]], [small], q, cfgs, warm=False, progress=prog("floor p%d" % pk),
+                                      top_k=1)) for pk in (1, 2)}
+    models = tts.fit_models(recs, fl[2])
+    r2 = np.array([m.r2_adj for m in models.values()])
+    errs = {v: {n: [] for n in w.extra["val_sizes"]} for v in ("eq4", "eq4_floor")}
+    vrecs = []
+    for f, (P, npts) in enumerate(pockets):
+        tr = [r for r in recs if r["pocket"] != f]
+        mf = {"eq4": tts.fit_models(tr), "eq4_floor": tts.fit_models(tr, fl[1 if f == 2 else 2])}
+        for n in w.extra["val_sizes"]:
+            L = configs.tts_validation_set(n, f)
+            a, r = tts.ligand_features(L)
+            for vr in tts.campaign([(P, npts)], [L], q, cfgs, warm=False, progress=prog("val p%d n%d" % (f, n)),
+                                   top_k=1):
+                vrecs.append(dict(vr, fold=f))
+                for v, m in mf.items():
+                    pred = m[tts.key(vr)].predict(npts, a, r, n)
+                    errs[v][n].append(100.0 * (pred - vr["ms"]) / vr["ms"])
+
+    def summ(e):
+        e = np.asarray(e)
+        return dict(runs=len(e), mean_abs_pct=float(np.mean(np.abs(e))), median_abs_pct=float(np.median(np.abs(e))),
+                    p95_abs_pct=float(np.percentile(np.abs(e), 95)), max_abs_pct=float(np.max(np.abs(e))),
+                    mean_signed_pct=float(np.mean(e)))
+    val = {v: {str(n): summ(e) for n, e in ev.items()} for v, ev in errs.items()}
+    if records_path:
+        with open(records_path, "w") as fh:
+            json.dump(dict(train=recs, val=vrecs, floors={str(k): {str(kk): vv for kk, vv in o.items()}
+                                                          for k, o in fl.items()}), fh)
+    # accuracy of every configuration (platform-independent): a 5,000-ligand exploration
+    d = configs.DSE
+    dl = d.ligands(0, dse_ligands)
+    drecs = dse.explore(gd.Pocket(d.pocket_points(), 0.5, d.pad), dl, d.quaternions(), space="full", top_k=1)
+    deg = {tts.key(r): r["degradation"] for r in drecs}
+    bkey = tts.key(dse.BASELINE | dict(lp=45))
+    p_d, (a_d, r_d) = len(d.pocket_points()), tts.ligand_features(dl)
+    tb = models[bkey].per_ligand(p_d, a_d, r_d)
+
+    def point(nu, budget_ms):
+        c = tts.choose(models, deg, p_d, a_d, r_d, nu, budget_ms)
+        k = c["key"]
+        return dict(ligands=nu, budget_h=budget_ms / 3.6e6, hp=k[0], lp=k[1], threshold=k[2], repetitions=k[3],
+                    refine=k[4], completion=c["completion"], degradation=c["degradation"],
+                    baseline_completion=min(1.0, budget_ms / (nu * tb)))
+    s1 = [point(nu, 3.6e6) for nu in (1e7, 2e7, 5e7, 1e8, 2e8, 5e8, 1e9, 2e9)]
+    s2 = [point(5e8, h * 3.6e6) for h in (0.25, 0.5, 1, 2, 4, 8, 24, 48)]
+    return dict(workload="tts: %d full-space configurations x 4 pockets (1,000-8,000 points) x 5 ligand mixes of 5,000 "
+                         "ligands, 32 orientations; leave-one-pocket-out validation on 1,000-10,000-ligand databases"
+                         % len(cfgs),
+                train_runs=len(recs), r2_adj_mean=float(np.mean(r2)), r2_adj_min=float(np.min(r2)),
+                validation_error=val, baseline_ms_per_ligand=tb,
+                scenario1_budget_1h=s1, scenario2_500M_ligands=s2, wall_s=time.perf_counter() - t0)
+
+
 def large_leg(gd, torch, n_chunks):
     """The large library streamed through the persistent kernel in chunks of
     65,536 ligands (host preparation of the next chunk overlaps docking), with
@@ -233,6 +317,9 @@ def main():
     ap.add_argument("--large-chunks", type=int, default=0, help="also stream this many chunks of the large library")
     ap.add_argument("--dse", type=str, default="", help="run only the knob exploration: flat, full or both")
     ap.add_argument("--dse-ligands", type=int, default=0)
+    ap.add_argument("--tts-records", type=str, default="", help="also write the campaign's raw records (JSON)")
+    ap.add_argument("--tts", action="store_true", help="run only the time-to-solution campaign, validation and "
+                                                          "budget scenarios")
     ap.add_argument("--no-continuous", action="store_true")
     ap.add_argument("--tiling", type=str, default="")
     ap.add_argument("--autotune", action="store_true")
@@ -270,6 +357,9 @@ def main():
         return
     if args.refine_only:
         print(json.dumps(refine_leg(gd, torch, np, args.refine_ligands)), flush=True)
+        return
+    if args.tts:
+        print(json.dumps(tts_leg(gd, torch, np, records_path=args.tts_records or None)), flush=True)
         return
     if args.dse:
         spaces = ["flat", "full"] if args.dse == "both" else [args.dse]

@@ -24,6 +24,12 @@ Each recipe fixes the generator streams, sizes and knobs of one workload:
              at the library's 128-atom limit and a moderate rotamer count) x
              the screen pocket; 32 orientations, top-1 pose per ligand; the
              knob configurations of the flat and full design spaces.
+  tts        time-to-solution campaign: the grid workload's 4 pockets x 5
+             ligand mixes of 5,000 ligands (atoms/rotatable bonds U[20,40]/
+             U[2,5], U[28,70]/U[2,8], U[28,120]/U[2,16], U[70,110]/U[2,5],
+             U[40,70]/U[9,14]) for training; validation databases of 1,000,
+             2,000, 5,000 and 10,000 ligands drawn from the dse distribution
+             with another seed; 32 orientations.
 
 Pocket centres sit off the lattice origin so that no symmetry of the grid is
 accidentally exploited.
@@ -102,7 +108,26 @@ LARGE = Workload("large", lig_seed=5, n_ligands=1_000_000, lmin=15, lmax=120, bm
 DSE = Workload("dse", lig_seed=6, n_ligands=20_000, lmin=28, lmax=120, bmin=2, bmax=16, ring_frac=0.0,
                pockets=[(1001, 4000, (12.0, 9.0, 7.0))], n_orient=32, hp=1, repetitions=3, top_k=1, pad=20.0)
 
-ALL = {w.name: w for w in (SINGLE, SCREEN, GRID, REFINE, LARGE, DSE)}
+TTS = Workload("tts", lig_seed=8, n_ligands=5000, lmin=28, lmax=120, bmin=2, bmax=16, ring_frac=0.0,
+               pockets=GRID.pockets, n_orient=32, hp=1, repetitions=3, top_k=1, pad=20.0,
+               extra=dict(mixes=((20, 40, 2, 5), (28, 70, 2, 8), (28, 120, 2, 16), (70, 110, 2, 5), (40, 70, 9, 14)),
+                          val_seed=9, val_sizes=(1000, 2000, 5000, 10000)))
+
+
+def tts_training_sets(w=None):
+    """The campaign's ligand mixes (one LigandBatch per mix)."""
+    w = w or TTS
+    return [ligands(w.lig_seed + 10 * i, 0, w.n_ligands, lo, hi, bl, bh, 0.0)
+            for i, (lo, hi, bl, bh) in enumerate(w.extra["mixes"])]
+
+
+def tts_validation_set(n, fold, w=None):
+    """A validation database of n ligands for one held-out pocket."""
+    w = w or TTS
+    return ligands(w.extra["val_seed"] + 100 * fold, 0, n, DSE.lmin, DSE.lmax, DSE.bmin, DSE.bmax, 0.0)
+
+
+ALL = {w.name: w for w in (SINGLE, SCREEN, GRID, REFINE, LARGE, DSE, TTS)}
 
 
 def tiny_ligand(seed: int, l: int, nrot: int):
