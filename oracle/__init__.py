@@ -10,6 +10,8 @@ Parity status per function (what pins each one is listed in the tests):
   schedules / tiles  pinned: Eq. 2/3 and the paper's 18-degree example
   dock (Alg. 2)      pinned: pose-count closed form, kinematic invariants,
                      independent brute force over torsion combinations
+  sweep profile      pinned: its argmin is the flat 1-degree sweep's choice;
+                     subsampling; the rotation by 0 is the pose itself
   continuous Eq. 1   pinned: exact rational brute force, one-point closed form,
                      lattice and permutation invariances
   overlap values     parity unpinned against the paper's own numbers (the paper
@@ -85,6 +87,9 @@ def _load():
         lib.orc_overlap.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_double]
         lib.orc_overlap.restype = ctypes.c_double
         lib.orc_overlap_continuous.argtypes = [P, ctypes.c_int, P, P]
+        lib.orc_sweep_profile.argtypes = [P, ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P, P, ctypes.c_int,
+                                          ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, P, P]
+        lib.orc_sweep_profile.restype = ctypes.c_int
         lib.orc_overlap_continuous.restype = ctypes.c_double
         lib.orc_score_poses.argtypes = [P, ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P, P, P, ctypes.c_double,
                                         ctypes.c_int, P, P]
@@ -181,6 +186,24 @@ def topology(lig: dict):
     left = np.zeros((max(len(rot) // 2, 1), l), np.uint8)
     rc = _load().orc_topology(l, len(bonds) // 2, _p(bonds), len(rot) // 2, _p(rot), _p(dist), _p(left))
     return rc, dist, left[:len(rot) // 2]
+
+
+def sweep_profile(pocket: OraclePocket, lig: dict, X, r: int, side: int, step: int = 1, clash_dist=2.0,
+                  clash_min_bonds=4):
+    """Overlap landscape of one rotamer side from pose X (l x 3 FP64):
+    (side size, S per angle, feasible per angle) for angles 0, step, ..."""
+    X = np.ascontiguousarray(X, np.float64).reshape(-1, 3)
+    bonds = np.ascontiguousarray(lig["bonds"], np.int32).reshape(-1)
+    rot = np.ascontiguousarray(lig["rot"], np.int32).reshape(-1)
+    n = 360 // step
+    S = np.zeros(n, np.int64)
+    f = np.zeros(n, np.uint8)
+    cd = float(np.float32(clash_dist))
+    rc = _load().orc_sweep_profile(pocket._ptr, len(X), len(bonds) // 2, _p(bonds), len(rot) // 2, _p(rot), _p(X),
+                                   int(r), int(side), int(step), cd, int(clash_min_bonds), _p(S), _p(f))
+    if rc < 0:
+        raise OracleError(-rc)
+    return rc, S, f.astype(bool)
 
 
 class DockResult:

@@ -395,23 +395,33 @@ static int best_of(sweep_ctx* C, const double* X, const unsigned char* moving, c
     return best;
 }
 
-static int sweep_side(sweep_ctx* C, double* X, int r, int side) {
-    const orc_topo* T = C->T;
+/* The moving set of one side of rotamer r (left = the side of its first
+ * atom), the pivot (that side's bond atom) and the unit axis a -> c from the
+ * pose X; returns the side's atom count. */
+static int side_frame(const orc_topo* T, const double* X, int r, int side, unsigned char* moving, double p[3],
+                      double k[3]) {
     int l = T->l;
     int a = T->rot[2 * r], c = T->rot[2 * r + 1];
-    unsigned char* moving = (unsigned char*)malloc(l);
     int size = 0;
     for (int i = 0; i < l; i++) {
         int in_left = T->left[(size_t)r * l + i];
         moving[i] = side == 0 ? in_left : !in_left;
         size += moving[i];
     }
-    double p[3], k[3];
     const double* piv = X + 3 * (side == 0 ? a : c);
     p[0] = piv[0]; p[1] = piv[1]; p[2] = piv[2];
     double ax = X[3 * c] - X[3 * a], ay = X[3 * c + 1] - X[3 * a + 1], az = X[3 * c + 2] - X[3 * a + 2];
     double nrm = sqrt(ax * ax + ay * ay + az * az);
     k[0] = ax / nrm; k[1] = ay / nrm; k[2] = az / nrm;
+    return size;
+}
+
+static int sweep_side(sweep_ctx* C, double* X, int r, int side) {
+    const orc_topo* T = C->T;
+    int l = T->l;
+    unsigned char* moving = (unsigned char*)malloc(l);
+    double p[3], k[3];
+    int size = side_frame(T, X, r, side, moving, p, k);
 
     int angles[360];
     int theta = 0;
@@ -502,6 +512,41 @@ int orc_topk(int n, const int64_t* S, const uint8_t* clash, int k, int* out) {
     memcpy(out, idx, sizeof(int) * k);
     free(idx);
     return ORC_OK;
+}
+
+/*
+ * Overlap landscape of one side of rotamer r (the peak analysis of Section
+ * III-B): from the pose X (l x 3, FP64) the side is turned about the bond by
+ * every multiple of `step` degrees in [0, 360), and each candidate is
+ * evaluated as a sweep evaluates it: whole-ligand S and feasibility of the
+ * straddling far pairs (strict).  S and feasible receive 360/step entries.
+ * Returns the side's atom count (its bond atom included), or an error code
+ * (negative).
+ */
+int orc_sweep_profile(orc_pocket* P, int l, int nb, const int* bonds, int nr, const int* rot, const double* X, int r,
+                      int side, int step, double clash_dist, int clash_min_bonds, int64_t* S, uint8_t* feasible) {
+    if (!P || !X || !S || !feasible || r < 0 || r >= nr || side < 0 || side > 1 || step < 1 || step > 360 ||
+        360 % step != 0)
+        return -ORC_ERR_ARG;
+    orc_topo T;
+    int rc = topo_build(&T, l, nb, bonds, nr, rot);
+    if (rc != ORC_OK) { topo_free(&T); return -rc; }
+    orc_knobs K;
+    memset(&K, 0, sizeof(K));
+    K.clash_min_bonds = clash_min_bonds;
+    sweep_ctx C;
+    C.P = P; C.T = &T; C.K = &K;
+    C.cd2 = clash_dist * clash_dist;
+    C.Y = (double*)malloc(sizeof(double) * 3 * l);
+    C.n_cand = 0;
+    unsigned char* moving = (unsigned char*)malloc(l);
+    double p[3], k[3];
+    int size = side_frame(&T, X, r, side, moving, p, k);
+    for (int t = 0; t < 360 / step; t++) feasible[t] = (uint8_t)eval_candidate(&C, X, moving, p, k, t * step, S + t);
+    free(moving);
+    free(C.Y);
+    topo_free(&T);
+    return size;
 }
 
 /* Overlap o = l / (h^2 S); S = 0 gives +inf. */

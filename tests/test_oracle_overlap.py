@@ -170,3 +170,56 @@ def test_pareto_front_against_brute_force(seed):
     # every excluded point is dominated by a kept one
     for i in np.nonzero(~keep)[0]:
         assert np.any(keep & (t >= t[i]) & (d <= d[i]))
+
+
+# --------------------------------------------------------------------------
+# Overlap landscape of a rotamer side (peak analysis, Section III-B)
+
+@pytest.mark.parametrize("seed", range(3))
+def test_profile_argmin_is_every_sweeps_choice(seed):
+    # Alg. 1 with a flat 1-degree step keeps the lowest S among the feasible
+    # angles (ties to the earliest, none feasible -> 0): the landscape taken
+    # at the pose before each sweep must reproduce every chosen angle
+    lig = configs.tiny_ligand(20 + seed, 14, 3)
+    pts = configs.SINGLE.pocket_points()
+    O = oracle.OraclePocket(pts, 0.5)
+    q = np.array([0.8, 0.2, -0.4, 0.4])
+    q = q / np.linalg.norm(q)
+    kn = oracle.knobs(hp=1, repetitions=1)
+    r = oracle.dock(O, lig, kn, q[None, :])
+    X = oracle.place(lig, q, O.centroid)
+    moves = []
+    nr = len(np.asarray(lig["rot"]).reshape(-1, 2))
+    for rr in range(nr):
+        for side in (0, 1):
+            done = [m for m in moves if m[2] != 0]
+            Xb = oracle.apply_torsions(lig, X, done) if done else X
+            size, S, f = oracle.sweep_profile(O, lig, Xb, rr, side, step=1)
+            assert 1 <= size < len(lig["x"])
+            if f.any():
+                best = int(np.flatnonzero(f)[np.argmin(S[f])])
+            else:
+                best = 0
+            assert best == r.angles[0, 0, rr, side], (rr, side)
+            moves.append((rr, side, best))
+    # the final pose is the placement with every chosen rotation applied (a
+    # sweep commits nothing for 0 degrees)
+    nz = [m for m in moves if m[2] != 0]
+    assert np.array_equal(oracle.apply_torsions(lig, X, nz) if nz else X, r.xyz[0])
+
+
+def test_profile_subsampling_and_clash_limits():
+    lig = configs.tiny_ligand(7, 16, 3)
+    O = oracle.OraclePocket(configs.SINGLE.pocket_points(), 0.5)
+    X = oracle.place(lig, np.array([1.0, 0, 0, 0]), O.centroid)
+    n1, S1, f1 = oracle.sweep_profile(O, lig, X, 1, 0, step=1)
+    n5, S5, f5 = oracle.sweep_profile(O, lig, X, 1, 0, step=5)
+    assert n1 == n5 and np.array_equal(S5, S1[::5]) and np.array_equal(f5, f1[::5])
+    # bump distance 0 never bumps (strict d^2 < 0); a 100 A distance bumps at
+    # every angle (the ligand has straddling pairs more than 3 bonds apart)
+    assert oracle.sweep_profile(O, lig, X, 1, 0, step=10, clash_dist=0.0)[2].all()
+    assert not oracle.sweep_profile(O, lig, X, 1, 0, step=10, clash_dist=100.0)[2].any()
+    with pytest.raises(oracle.OracleError):
+        oracle.sweep_profile(O, lig, X, 1, 0, step=7)
+    with pytest.raises(oracle.OracleError):
+        oracle.sweep_profile(O, lig, X, 9, 0, step=1)
