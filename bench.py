@@ -274,6 +274,41 @@ def tts_leg(gd, torch, np, dse_ligands=5000, records_path=None):
                 scenario1_budget_1h=s1, scenario2_500M_ligands=s2, wall_s=time.perf_counter() - t0)
 
 
+def peaks_leg(gd, torch, np, n_lig=2000, step=1):
+    """Peak analysis (Sec. III-B) on synthetic ligands: the exploration
+    workload's first n_lig ligands docked at the baseline knobs (hp 1, 3
+    repetitions), then the overlap landscape of every rotamer side at each
+    best pose in 1-degree steps, summarised by relative fragment size."""
+    from synth import configs
+    from paper_1901_06363_amd import dse, peaks
+    w = configs.DSE
+    ligs = w.ligands(0, n_lig)
+    P = gd.Pocket(w.pocket_points(), 0.5, w.pad)
+    b = dse.BASELINE
+    B = gd.Batch(P, ligs, w.quaternions(), hp=b["hp"], lp=b["lp"], threshold=b["threshold"],
+                 repetitions=b["repetitions"], refine=b["refine"], top_k=1)
+    res = B.dock(gd.BATCHED)
+    gd.sweep_profile(P, B, res, step=step)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    S, f, sz = gd.sweep_profile(P, B, res, step=step)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    h = res.host()
+    nat = np.diff(np.asarray(ligs.atom_off))
+    nrt = np.diff(np.asarray(ligs.rot_off))
+    evals = int(nrt.sum()) * 2 * (360 // step)
+    t0 = time.perf_counter()
+    recs = peaks.analyse(S.cpu().numpy(), f.cpu().numpy(), sz.cpu().numpy(), nat, nrt, h["S"], step=step)
+    summ = peaks.summarize(recs)
+    return dict(workload="peaks: %d ligands (28-120 atoms, 2-16 rotatable bonds) docked at the baseline knobs, "
+                         "landscapes of every rotamer side at the best pose in %d-degree steps" % (n_lig, step),
+                kernel="profile_kernel", kernel_ms=ms, evaluations=evals, evaluations_per_s=evals / (ms * 1e-3),
+                host_analysis_s=time.perf_counter() - t0, summary=summ)
+
+
 def large_leg(gd, torch, n_chunks):
     """The large library streamed through the persistent kernel in chunks of
     65,536 ligands (host preparation of the next chunk overlaps docking), with
@@ -317,6 +352,7 @@ def main():
     ap.add_argument("--large-chunks", type=int, default=0, help="also stream this many chunks of the large library")
     ap.add_argument("--dse", type=str, default="", help="run only the knob exploration: flat, full or both")
     ap.add_argument("--dse-ligands", type=int, default=0)
+    ap.add_argument("--peaks", action="store_true", help="run only the peak analysis of overlap landscapes")
     ap.add_argument("--tts-records", type=str, default="", help="also write the campaign's raw records (JSON)")
     ap.add_argument("--tts", action="store_true", help="run only the time-to-solution campaign, validation and "
                                                           "budget scenarios")
@@ -357,6 +393,9 @@ def main():
         return
     if args.refine_only:
         print(json.dumps(refine_leg(gd, torch, np, args.refine_ligands)), flush=True)
+        return
+    if args.peaks:
+        print(json.dumps(peaks_leg(gd, torch, np)), flush=True)
         return
     if args.tts:
         print(json.dumps(tts_leg(gd, torch, np, records_path=args.tts_records or None)), flush=True)

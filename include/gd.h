@@ -255,6 +255,32 @@ gd_status gd_score_poses(const gd_pocket* pocket, const gd_ligands* topo, int32_
                          int32_t clash_min_bonds, void* stream, int32_t* S_out, uint8_t* clash_out);
 
 /* ------------------------------------------------------------------------ */
+/* Overlap landscapes (peak analysis)                                        */
+
+/*
+ * The overlap landscape of every rotamer side at each ranked pose of the
+ * last gd_dock_prepared call on `batch` (the peak analysis of Section III-B):
+ * the pose is rebuilt in FP64 from that call's stored angles, then each side
+ * of each rotamer is turned about its bond from the pose by t * step degrees,
+ * t = 0 .. 360/step - 1, and evaluated exactly as a sweep's FP64 path does:
+ * the whole-ligand S (Eq. 1 on the lattice) and the feasibility of the
+ * straddling far pairs (strict d < clash_dist).
+ *   recs           device, the n_ligands * top_k records that call wrote
+ *   S_out          device int32[n_ligands * top_k * max_rot * 2 * (360/step)],
+ *                  index ((pose * max_rot + r) * 2 + side) * (360/step) + t
+ *   feasible_out   device uint8, same layout (1 = feasible)
+ *   side_size_out  device int32[n_ligands * top_k * max_rot * 2]: atoms of
+ *                  the turned side (its bond atom included)
+ * Rotamers beyond a ligand's own count, and records whose orientation or
+ * stored angles are out of range (the batch was never docked), give zeros.
+ * The pocket must be the one the batch was docked against.  Asynchronous.
+ * Errors: GD_ERR_ARG (null argument), GD_ERR_KNOB (step not an integer
+ * divisor of 360), GD_ERR_HIP.
+ */
+gd_status gd_sweep_profile(const gd_pocket* pocket, const gd_batch* batch, const gd_pose_rec* recs, int32_t step,
+                           void* stream, int32_t* S_out, uint8_t* feasible_out, int32_t* side_size_out);
+
+/* ------------------------------------------------------------------------ */
 /* Continuous overlap (Eq. 1 without the lattice)                            */
 
 /*

@@ -230,4 +230,4 @@ def dock(pocket: Pocket, ligands, quats, mode=BATCHED, stream=None, **knobs) -> 
     return res
 
 
-from ._ops import score_poses, overlap_continuous, OverlapLayout, refine, surrogate_fwd, surrogate_bwd, SurrogateScore  # noqa: E402,E501
+from ._ops import score_poses, overlap_continuous, OverlapLayout, sweep_profile, refine, surrogate_fwd, surrogate_bwd, SurrogateScore  # noqa: E402,E501

@@ -80,6 +80,24 @@ def overlap_continuous(pocket, counts, px, py, pz, stream=None):
     return min_d2[:n_atoms], s[:n], o[:n]
 
 
+def sweep_profile(pocket, batch, res, step=1, stream=None):
+    """Overlap landscapes of every rotamer side at every ranked pose of the
+    docking result `res` (the last dock call of `batch`).  Returns device
+    tensors S (n, k, max_rot, 2, 360/step) int32, feasible (same, uint8) and
+    side_size (n, k, max_rot, 2) int32."""
+    torch = _torch()
+    if step < 1 or 360 % step:
+        raise ValueError("step must be an integer divisor of 360")
+    n, k, rm = batch.n_ligands, batch.top_k, max(batch.max_rot, 1)
+    na = 360 // step
+    S = torch.empty((n, k, rm, 2, na), dtype=torch.int32, device="cuda")
+    f = torch.empty((n, k, rm, 2, na), dtype=torch.uint8, device="cuda")
+    sz = torch.empty((n, k, rm, 2), dtype=torch.int32, device="cuda")
+    _abi.check(_abi.load().gd_sweep_profile(pocket.handle, batch._h, _dp(res.recs), int(step), _stream_ptr(stream),
+                                            _dp(S), _dp(f), _dp(sz)))
+    return S, f, sz
+
+
 def _prm(t, q, tau, n):
     torch = _torch()
     t = t.contiguous().float()

@@ -201,6 +201,19 @@ gd_status gd_overlap_continuous(const gd_pocket* pocket, int32_t n_poses, const 
     return GD_OK;
 }
 
+gd_status gd_sweep_profile(const gd_pocket* pocket, const gd_batch* batch, const gd_pose_rec* recs, int32_t step,
+                           void* stream, int32_t* S_out, uint8_t* feasible_out, int32_t* side_size_out) {
+    clear_error();
+    if (!pocket || !batch || !recs || !S_out || !feasible_out || !side_size_out)
+        return fail(GD_ERR_ARG, "gd_sweep_profile: null argument");
+    if (step < 1 || step > 360 || 360 % step != 0)
+        return fail(GD_ERR_KNOB, "gd_sweep_profile: step must be an integer divisor of 360");
+    hipError_t e = launch_profile((const PocketDev*)pocket->devcopy.ptr, batch->dev, recs, step, S_out, feasible_out,
+                                  side_size_out, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "gd_sweep_profile");
+    return GD_OK;
+}
+
 gd_status gd_batch_autotune(const gd_pocket* pocket, gd_batch* batch, void* stream, int32_t reps,
                             const char* cache_path, gd_tiling* chosen) {
     clear_error();

@@ -940,6 +940,80 @@ __global__ void __launch_bounds__(256) replay_kernel(PocketDev P, BatchDev B, co
     }
 }
 
+// Overlap landscape of every rotamer side at each ranked pose (the peak
+// analysis of Section III-B).  The pose is rebuilt in FP64 as the replay does;
+// then each side of each rotamer is turned about its bond from that pose by
+// every multiple of `step` degrees and evaluated as a sweep's FP64 path does:
+// whole-ligand S (the turned side's S plus that of the atoms that stay) and
+// the straddling pairs' feasibility.  One wave per ranked pose; a record whose
+// orientation or stored angles are out of range (no docking call before)
+// yields zeros.
+__global__ void __launch_bounds__(256) profile_kernel(const PocketDev* Pp, BatchDev B, const gd_pose_rec* recs,
+                                                      int step, int32_t* S_out, uint8_t* f_out, int32_t* size_out) {
+    extern __shared__ __align__(16) char smem[];
+    const int wave = threadIdx.x / kWave;
+    const int idx = blockIdx.x * (blockDim.x / kWave) + wave;
+    if (idx >= B.n_lig * B.top_k) return;
+    const int lane = lane_id();
+    const int lig = idx / B.top_k;
+    const int nang = 360 / step;
+    WaveLds W{};
+    const int lp = lds_pitch(B.lmax);
+    W.X = (lds_double*)(smem + wave * replay_lds_bytes(B.lmax));
+    W.SW = W.X + 3 * lp;
+    const LigMeta L = ldg_record(B.lig + lig);
+    const int o = recs[idx].orient;
+    const int nrec = B.reps * L.nr * 2;
+    bool ok = o >= 0 && o < B.n_orient;
+    const uint16_t* ang = B.ang + L.ang_off + (size_t)(ok ? o : 0) * nrec;
+    for (int q = 0; q < nrec && ok; q++) ok = ang[q] < 360;
+    if (ok) {
+        place(*Pp, B, L, o, W);
+        for (int rep = 0; rep < B.reps; rep++)
+            for (int r = 0; r < L.nr; r++) {
+                const RotInfo* rp = B.rot + L.rot_off + r;
+                for (int side = 0; side < 2; side++) {
+                    const SideInfo ri = side_info(rp, side);
+                    sweep_axis(W, lp, ri.a, ri.c, ri.piv, side == 1);
+                    commit(B.mv + ri.mv_off, ri.n_mv, W, lp, ang[(rep * L.nr + r) * 2 + side]);
+                }
+            }
+    }
+    for (int r = 0; r < B.rmax; r++)
+        for (int side = 0; side < 2; side++) {
+            const size_t row = ((size_t)idx * B.rmax + r) * 2 + side;
+            int32_t* So = S_out + row * nang;
+            uint8_t* fo = f_out + row * nang;
+            if (!ok || r >= L.nr) {
+                for (int t = lane; t < nang; t += kWave) {
+                    So[t] = 0;
+                    fo[t] = 0;
+                }
+                if (lane == 0) size_out[row] = 0;
+                continue;
+            }
+            const SideInfo si = side_info(B.rot + L.rot_off + r, side);
+            sweep_axis(W, lp, si.a, si.c, si.piv, false);
+            const uint8_t* mvl = B.mv + si.mv_off;
+            int oob = 0, s_all = 0, s_mv = 0;
+            for (int i = lane; i < L.l; i += kWave) s_all += D_exact(*Pp, W.X[i], W.X[lp + i], W.X[2 * lp + i], oob);
+            for (int j = lane; j < si.n_mv; j += kWave) {
+                const int i = ldg(mvl + j);
+                s_mv += D_exact(*Pp, W.X[i], W.X[lp + i], W.X[2 * lp + i], oob);
+            }
+            const int s_fixed = wave_sum(s_all) - wave_sum(s_mv);
+            for (int t = 0; t < nang; t++) {
+                const uint64_t v = eval_fp64(Pp, W.X, W.SW, lp, mvl, si.n_mv, B.pairs + si.pair_off, si.n_pairs, side,
+                                             B.cd2, t * step);
+                if (lane == 0) {
+                    So[t] = s_fixed + (int32_t)(uint32_t)v;
+                    fo[t] = (uint8_t)((v >> 32) & 1);
+                }
+            }
+            if (lane == 0) size_out[row] = si.n_mv;
+        }
+}
+
 // --------------------------------------------------------------------------
 // host-side launchers
 
@@ -1039,6 +1113,16 @@ hipError_t launch_replay(const PocketDev& P, const BatchDev& B, const gd_pose_re
     size_t lds = replay_lds_bytes(B.lmax) * waves;
     hipLaunchKernelGGL(replay_kernel, dim3((n + waves - 1) / waves), dim3(waves * kWave), lds, s, P, B, recs, xyz,
                        nmax);
+    return hipGetLastError();
+}
+
+hipError_t launch_profile(const PocketDev* Pd, const BatchDev& B, const gd_pose_rec* recs, int step, int32_t* S_out,
+                          uint8_t* f_out, int32_t* size_out, hipStream_t s) {
+    const int waves = 4;
+    const int n = B.n_lig * B.top_k;
+    const size_t lds = replay_lds_bytes(B.lmax) * waves;
+    hipLaunchKernelGGL(profile_kernel, dim3((n + waves - 1) / waves), dim3(waves * kWave), lds, s, Pd, B, recs, step,
+                       S_out, f_out, size_out);
     return hipGetLastError();
 }
 

@@ -163,6 +163,8 @@ hipError_t launch_accept(const PoseDev& X, int n_poses, const int32_t* n_atoms, 
                          const uint8_t* c_in, hipStream_t s);
 hipError_t launch_replay(const PocketDev& P, const BatchDev& B, const gd_pose_rec* recs, float* xyz, int nmax,
                          hipStream_t s);
+hipError_t launch_profile(const PocketDev* Pd, const BatchDev& B, const gd_pose_rec* recs, int step, int32_t* S_out,
+                          uint8_t* f_out, int32_t* size_out, hipStream_t s);
 // continuous Eq. 1: pocket points as three FP64 planes of `pitch`, padded to
 // n_pad (a multiple of kOvUnroll) with far points
 constexpr int kOvUnroll = 16;

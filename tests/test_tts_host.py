@@ -111,3 +111,67 @@ def test_floor_of_a_run():
     assert m.predict(p, a, r, 100) == 120.0
     assert m.predict(p, a, r, 10 ** 6) == pytest.approx(10 ** 6 * u(p, a, r), rel=1e-6)
     assert tts.fit_models(recs)[tts.key(cfg)].predict(p, a, r, 100) == pytest.approx(100 * u(p, a, r), rel=1e-6)
+
+
+# --------------------------------------------------------------------------
+# Peak analysis (Section III-B): delta overlap, peaks, widths and heights
+
+def test_circular_runs():
+    from paper_1901_06363_amd import peaks
+    assert peaks.circular_runs([]) == []
+    assert peaks.circular_runs([False, False]) == []
+    assert peaks.circular_runs([True] * 5) == [(0, 5)]
+    # a run across the wrap-around is one run
+    assert sorted(peaks.circular_runs([True, True, False, True])) == [(3, 3)]
+    assert sorted(peaks.circular_runs([True, False, True, False, False, True, True])) == [(2, 1), (5, 3)]
+
+
+def test_analyse_side_closed_forms():
+    from paper_1901_06363_amd import peaks
+    th = np.arange(360)
+    # one smooth bump: o = 2 + cos(theta - 100 deg); above the midpoint over
+    # (10, 190) exclusive -> 179 angles, height 1
+    o = 2 + np.cos(np.radians(th - 100))
+    a = peaks.analyse_side(o, np.ones(360, bool))
+    assert a["delta"] == pytest.approx(2.0) and len(a["peaks"]) == 1
+    w, h, s = a["peaks"][0]
+    assert w == 179 and h == pytest.approx(1.0) and s == 11
+    # a bump across 0 degrees stays one peak
+    a = peaks.analyse_side(2 + np.cos(np.radians(th)), np.ones(360, bool))
+    assert len(a["peaks"]) == 1 and a["peaks"][0][0] == 179
+    # an invalid (bumping) gap splits it; the part without the maximum is lower
+    v = np.ones(360, bool)
+    v[60:70] = False
+    a = peaks.analyse_side(o, v)
+    assert sorted(p[0] for p in a["peaks"]) == [49, 120]
+    assert max(p[1] for p in a["peaks"]) == pytest.approx(1.0) and min(p[1] for p in a["peaks"]) < 1.0
+    # two bumps of different heights: two peaks, heights 1 and (2.6 - 1) / 2;
+    # a bump below half the delta is no peak
+    o2 = np.where(np.abs(th - 90) < 20, 3.0, np.where(np.abs(th - 270) < 10, 2.6, 1.0))
+    o2[200] = 1.9
+    a = peaks.analyse_side(o2, np.ones(360, bool))
+    got = sorted((p[0], round(p[1], 6)) for p in a["peaks"])
+    assert got == [(19, 0.8), (39, 1.0)]
+    # flat landscape: no peak; nothing valid: None; step scales widths
+    assert peaks.analyse_side(np.ones(360), np.ones(360, bool))["peaks"] == []
+    assert peaks.analyse_side(o, np.zeros(360, bool)) is None
+    a5 = peaks.analyse_side(o[::5], np.ones(72, bool), step=5)
+    assert a5["peaks"][0][0] == 5 * 35  # samples 15, 20, ..., 185
+
+
+def test_analyse_and_summary_shapes():
+    from paper_1901_06363_amd import peaks
+    th = np.arange(360)
+    S = np.full((1, 1, 2, 2, 360), 100, np.int64)
+    S[0, 0, 0, 0] = 100 - np.round(20 * np.cos(np.radians(th))).astype(np.int64)  # one peak near 0
+    f = np.ones_like(S, np.uint8)
+    f[0, 0, 1, 1] = 0  # a side with no valid angle is skipped
+    recs = peaks.analyse(S, f, np.array([[[[3, 9], [6, 6]]]]), [12], [2], np.array([[80]]))
+    assert len(recs) == 3
+    r0 = [r for r in recs if r["rotamer"] == 0 and r["side"] == 0][0]
+    assert r0["rel_size"] == 0.25 and r0["n_peaks"] == 1
+    # delta normalised by the final overlap l / (h^2 S_final)
+    o = 12 / (0.25 * S[0, 0, 0, 0])
+    assert r0["delta_norm"] == pytest.approx((o.max() - o.min()) / (12 / (0.25 * 80)))
+    s = peaks.summarize(recs)
+    assert s["sides"] == 3 and sum(b["sides"] for b in s["by_rel_size"]) == 3
