@@ -332,6 +332,11 @@ typedef struct {
     float* kernel_ms;   /* host, may be NULL: when set, gd_refine times the ascent
                            kernel with HIP events on `stream`, waits for it and
                            stores its duration (ms) here                          */
+    float clash_weight; /* >= 0; 0 = the plain surrogate.  Otherwise the ascent
+                           climbs F - clash_weight * sum over the ligand's pairs
+                           at least clash_min_bonds apart with d < clash_dist of
+                           (clash_dist^2 - d^2)^2 (a bump penalty, beyond the
+                           paper); F_out is then that penalised value         */
 } gd_refine_opts;
 
 gd_status gd_surrogate_fwd(const gd_pocket* pocket, const gd_ligands* topo, int32_t n_poses, const int32_t* pose_lig,

@@ -107,10 +107,11 @@ def _load():
         lib.orc_rho_node.restype = D
         lib.orc_rho_interp.argtypes = [P, P, P, P]
         lib.orc_rho_interp.restype = D
-        lib.orc_surrogate.argtypes = [P, P, ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P, P, P, P, P, P]
+        lib.orc_surrogate.argtypes = [P, P, ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P, P, P, D, D, ctypes.c_int,
+                                      P, P, P]
         lib.orc_surrogate.restype = ctypes.c_int
         lib.orc_refine.argtypes = [P, P, ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P, P, ctypes.c_int, D, D, D, D, D,
-                                   P, P, P]
+                                   D, D, ctypes.c_int, P, P, P]
         lib.orc_refine.restype = ctypes.c_int
         lib.orc_torsion_tree.argtypes = [ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P, P, P, P, P]
         lib.orc_torsion_tree.restype = ctypes.c_int
@@ -320,8 +321,9 @@ class OracleBlur:
         v = _load().orc_rho_interp(self.pocket._ptr, self._ptr, _p(x), _p(g))
         return float(v), g
 
-    def surrogate(self, lig: dict, X0, prm, want_grad=True):
-        """(F, dF/dprm, pose) with prm = [t(3), q(4), tau(nr)] (tau in list order)."""
+    def surrogate(self, lig: dict, X0, prm, want_grad=True, clash_weight=0.0, clash_dist=2.0, clash_min_bonds=4):
+        """(F, dF/dprm, pose) with prm = [t(3), q(4), tau(nr)] (tau in list order);
+        with clash_weight > 0 the bump penalty is subtracted from F."""
         bonds = np.ascontiguousarray(lig["bonds"], np.int32).reshape(-1)
         rot = np.ascontiguousarray(lig["rot"], np.int32).reshape(-1)
         X0 = np.ascontiguousarray(X0, np.float64)
@@ -330,12 +332,15 @@ class OracleBlur:
         grad = np.zeros(len(prm)) if want_grad else None
         X = np.zeros_like(X0)
         rc = _load().orc_surrogate(self.pocket._ptr, self._ptr, len(X0), len(bonds) // 2, _p(bonds), len(rot) // 2,
-                                   _p(rot), _p(X0), _p(prm), ctypes.byref(F), _p(grad), _p(X))
+                                   _p(rot), _p(X0), _p(prm), float(np.float32(clash_weight)),
+                                   float(np.float32(clash_dist)), int(clash_min_bonds), ctypes.byref(F), _p(grad),
+                                   _p(X))
         if rc != OK:
             raise OracleError(rc)
         return F.value, grad, X
 
-    def refine(self, lig: dict, X0, steps=50, lr_t=0.002, lr_q=1e-5, lr_tau=5e-4, max_dt=0.1, max_dtau=0.05):
+    def refine(self, lig: dict, X0, steps=50, lr_t=0.002, lr_q=1e-5, lr_tau=5e-4, max_dt=0.1, max_dtau=0.05,
+               clash_weight=0.0, clash_dist=2.0, clash_min_bonds=4):
         bonds = np.ascontiguousarray(lig["bonds"], np.int32).reshape(-1)
         rot = np.ascontiguousarray(lig["rot"], np.int32).reshape(-1)
         X0 = np.ascontiguousarray(X0, np.float64)
@@ -345,8 +350,9 @@ class OracleBlur:
         F = ctypes.c_double(0)
         f32 = lambda v: float(np.float32(v))
         rc = _load().orc_refine(self.pocket._ptr, self._ptr, len(X0), len(bonds) // 2, _p(bonds), nr, _p(rot), _p(X0),
-                                int(steps), f32(lr_t), f32(lr_q), f32(lr_tau), f32(max_dt), f32(max_dtau), _p(prm),
-                                _p(X), ctypes.byref(F))
+                                int(steps), f32(lr_t), f32(lr_q), f32(lr_tau), f32(max_dt), f32(max_dtau),
+                                f32(clash_weight), f32(clash_dist), int(clash_min_bonds), _p(prm), _p(X),
+                                ctypes.byref(F))
         if rc != OK:
             raise OracleError(rc)
         return prm, X, F.value

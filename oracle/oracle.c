@@ -831,18 +831,44 @@ static void dquat(const double* q, double D[4][9]) {
     memcpy(D[0], Dw, sizeof(Dw)); memcpy(D[1], Dx, sizeof(Dx)); memcpy(D[2], Dy, sizeof(Dy)); memcpy(D[3], Dz, sizeof(Dz));
 }
 
+/* Bump penalty of the clash-penalised surrogate (an extension beyond the
+ * paper): pen = lam sum over pairs (i < j) at least minb bonds apart with
+ * d^2 < cd2 of (cd2 - d^2)^2.  Returns pen and subtracts d pen / dX_i from
+ * g (the gradient of F - pen). */
+static double bump_penalty(const orc_topo* T, int l, const double* X, double lam, double cd2, int minb, double* g) {
+    double pen = 0.0;
+    for (int i = 0; i < l; i++)
+        for (int j = i + 1; j < l; j++) {
+            if (T->dist[(size_t)i * l + j] < minb) continue;
+            double d[3] = {X[3 * i] - X[3 * j], X[3 * i + 1] - X[3 * j + 1], X[3 * i + 2] - X[3 * j + 2]};
+            double d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            if (d2 >= cd2) continue;
+            double e = cd2 - d2;
+            pen += e * e;
+            /* d(e^2)/dX_i = -4 e d, so -lam d(e^2)/dX_i = 4 lam e d */
+            for (int a = 0; a < 3; a++) {
+                g[3 * i + a] += 4.0 * lam * e * d[a];
+                g[3 * j + a] -= 4.0 * lam * e * d[a];
+            }
+        }
+    return lam * pen;
+}
+
 /*
  * Surrogate value and analytic gradient.  prm = [t(3), q(4), tau(nr)];
- * grad (may be NULL) gets dF/dprm; X (may be NULL) the pose.
+ * grad (may be NULL) gets dF/dprm; X (may be NULL) the pose.  With lam > 0
+ * the value is F - pen (bump_penalty above).
  */
 static double surrogate_eval(const orc_pocket* P, orc_blur* B, const orc_tree* R, int l, const double* X0,
-                             const double* c0, const double* prm, double* grad, double* Xout) {
+                             const double* c0, const double* prm, double* grad, double* Xout, const orc_topo* T,
+                             double lam, double cd2, int minb) {
     double* Y = (double*)malloc(sizeof(double) * 3 * l);
     double* X = (double*)malloc(sizeof(double) * 3 * l);
     double* g = (double*)malloc(sizeof(double) * 3 * l);
     pose_from_params(R, l, X0, c0, prm, Y, X);
     double F = 0.0;
     for (int i = 0; i < l; i++) F += orc_rho_interp(P, B, X + 3 * i, g + 3 * i);
+    if (lam > 0.0) F -= bump_penalty(T, l, X, lam, cd2, minb, g);
     if (grad) {
         int nr = R->nr;
         for (int k = 0; k < 7 + nr; k++) grad[k] = 0.0;
@@ -895,7 +921,8 @@ static void centroid3(int l, const double* X, double* c) {
 
 /* Public: surrogate value, gradient and pose at given parameters. */
 int orc_surrogate(orc_pocket* P, orc_blur* B, int l, int nb, const int* bonds, int nr, const int* rot,
-                  const double* X0, const double* prm, double* F, double* grad, double* X) {
+                  const double* X0, const double* prm, double lam, double clash_dist, int clash_min_bonds, double* F,
+                  double* grad, double* X) {
     orc_topo T;
     int rc = topo_build(&T, l, nb, bonds, nr, rot);
     if (rc != ORC_OK) { topo_free(&T); return rc; }
@@ -903,7 +930,7 @@ int orc_surrogate(orc_pocket* P, orc_blur* B, int l, int nb, const int* bonds, i
     tree_build(&T, &R);
     double c0[3];
     centroid3(l, X0, c0);
-    *F = surrogate_eval(P, B, &R, l, X0, c0, prm, grad, X);
+    *F = surrogate_eval(P, B, &R, l, X0, c0, prm, grad, X, &T, lam, clash_dist * clash_dist, clash_min_bonds);
     tree_free(&R);
     topo_free(&T);
     return ORC_OK;
@@ -916,8 +943,9 @@ int orc_surrogate(orc_pocket* P, orc_blur* B, int l, int nb, const int* bonds, i
  * Outputs the final parameters, pose and F of the final iterate.
  */
 int orc_refine(orc_pocket* P, orc_blur* B, int l, int nb, const int* bonds, int nr, const int* rot, const double* X0,
-               int steps, double lr_t, double lr_q, double lr_tau, double max_dt, double max_dtau, double* prm_out,
-               double* X_out, double* F_out) {
+               int steps, double lr_t, double lr_q, double lr_tau, double max_dt, double max_dtau, double lam,
+               double clash_dist, int clash_min_bonds, double* prm_out, double* X_out, double* F_out) {
+    const double cd2 = clash_dist * clash_dist;
     orc_topo T;
     int rc = topo_build(&T, l, nb, bonds, nr, rot);
     if (rc != ORC_OK) { topo_free(&T); return rc; }
@@ -930,7 +958,7 @@ int orc_refine(orc_pocket* P, orc_blur* B, int l, int nb, const int* bonds, int 
     double* grad = (double*)calloc(np, sizeof(double));
     prm[3] = 1.0;
     for (int s = 0; s < steps; s++) {
-        surrogate_eval(P, B, &R, l, X0, c0, prm, grad, NULL);
+        surrogate_eval(P, B, &R, l, X0, c0, prm, grad, NULL, &T, lam, cd2, clash_min_bonds);
         double dt[3] = {lr_t * grad[0], lr_t * grad[1], lr_t * grad[2]};
         double n = sqrt(dt[0] * dt[0] + dt[1] * dt[1] + dt[2] * dt[2]);
         double sc = n > max_dt ? max_dt / n : 1.0;
@@ -946,7 +974,7 @@ int orc_refine(orc_pocket* P, orc_blur* B, int l, int nb, const int* bonds, int 
             prm[7 + r] += d;
         }
     }
-    *F_out = surrogate_eval(P, B, &R, l, X0, c0, prm, NULL, X_out);
+    *F_out = surrogate_eval(P, B, &R, l, X0, c0, prm, NULL, X_out, &T, lam, cd2, clash_min_bonds);
     memcpy(prm_out, prm, sizeof(double) * np);
     free(prm); free(grad);
     tree_free(&R);

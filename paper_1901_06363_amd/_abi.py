@@ -51,7 +51,7 @@ class Tiling(ctypes.Structure):
 
 class RefineOpts(ctypes.Structure):
     _fields_ = [("steps", I32), ("lr_t", F32), ("lr_q", F32), ("lr_tau", F32), ("max_dt", F32), ("max_dtau", F32),
-                ("kernel_ms", ctypes.POINTER(F32))]
+                ("kernel_ms", ctypes.POINTER(F32)), ("clash_weight", F32)]
 
 
 # every exported symbol of include/gd.h: (name, restype, argtypes)

@@ -141,18 +141,20 @@ def surrogate_bwd(pocket, ligands, pose_lig, px, py, pz, t, q, tau, dF, stream=N
 
 
 def refine(pocket, ligands, pose_lig, px, py, pz, steps=50, lr_t=0.002, lr_q=1e-5, lr_tau=5e-4, max_dt=0.1,
-           max_dtau=0.05, clash_dist=2.0, clash_min_bonds=4, stream=None, want_iterate=False, time_kernel=False):
+           max_dtau=0.05, clash_dist=2.0, clash_min_bonds=4, stream=None, want_iterate=False, time_kernel=False,
+           clash_weight=0.0):
     """Gradient ascent on the surrogate, then exact rescoring; px/py/pz are
     overwritten with the refined pose where it is accepted.  With time_kernel
     the call waits for the ascent kernel and returns its duration (ms) as
-    out["kernel_ms"]."""
+    out["kernel_ms"].  clash_weight > 0 climbs the clash-penalised surrogate
+    (bump penalty over the far pairs closer than clash_dist)."""
     torch = _torch()
     lg = _lig_desc(ligands)
     pl = np.ascontiguousarray(pose_lig, dtype=np.int32)
     n = len(pl)
     kms = ctypes.c_float(0.0)
     opts = _abi.RefineOpts(int(steps), float(lr_t), float(lr_q), float(lr_tau), float(max_dt), float(max_dtau),
-                           ctypes.pointer(kms) if time_kernel else None)
+                           ctypes.pointer(kms) if time_kernel else None, float(clash_weight))
     F = torch.empty(n, dtype=torch.float32, device="cuda")
     S = torch.empty(n, dtype=torch.int32, device="cuda")
     clash = torch.empty(n, dtype=torch.uint8, device="cuda")

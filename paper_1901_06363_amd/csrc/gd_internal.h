@@ -150,6 +150,12 @@ hipError_t launch_score(const PocketDev& P, const ScoreDev& S, int n_poses, doub
 struct RefineParams {
     int steps;
     float lr_t, lr_q, lr_tau, max_dt, max_dtau;
+    // clash-penalised surrogate: F - clash_weight * sum over whole-ligand far
+    // pairs with d^2 < cd2 of (cd2 - d^2)^2 (no penalty when clash_weight = 0)
+    float clash_weight, cd2;
+    const uint16_t* efar;    // far pairs i | j << 8, per ligand from far_off
+    const int32_t* far_off;
+    const int32_t* n_far;
 };
 hipError_t launch_surrogate(const PocketDev& P, const TreeDev& T, const PoseDev& X, int n_poses, const float* t,
                             const float* q, const float* tau, int tau_stride, const float* dF, float* F_out,

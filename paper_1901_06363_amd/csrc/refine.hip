@@ -91,7 +91,7 @@ __device__ __forceinline__ void quat_mat(const float* q, float* R) {
 
 // Per-wave state of one pose.
 struct PoseState {
-    int l, nr, tree0;
+    int l, nr, tree0, lig;
     float x0[kSlots][3];  // input pose (this lane's atoms)
     float c0[3];          // centroid of the input pose
     uint64_t mv[kSlots];  // bit e: this lane's atom moves with rotamer e (root-first order)
@@ -101,6 +101,7 @@ __device__ void load_pose(const TreeDev& T, const PoseDev& X, int pose, PoseStat
     const int lane = lane_id();
     const int lig = X.pose_lig[pose], off = X.pose_off[pose];
     S.l = T.n_atoms[lig];
+    S.lig = lig;
     S.nr = T.nr[lig];
     S.tree0 = T.tree_off[lig];
     float s[3] = {0.f, 0.f, 0.f};
@@ -185,14 +186,78 @@ __device__ void pose_forward(const TreeDev& T, const PoseState& S, const float* 
     }
 }
 
+// Bump penalty of the clash-penalised surrogate: subtracts clash_weight *
+// (cd2 - d^2)^2 over the ligand's far pairs closer than the bump distance from
+// F (lane partial) and, with GRAD, its derivative from the per-atom gradients
+// g.  Atoms go through this wave's LDS (xs, gs: 3 floats per atom); lanes own
+// pairs and add their gradient contributions with LDS atomics.
+struct Penalty {
+    float w, cd2;  // clash weight (0: none) and bump distance squared
+    const uint16_t* efar;
+    const int32_t* far_off;
+    const int32_t* n_far;
+};
+
+template <bool GRAD>
+__device__ void bump_penalty(const Penalty pen, const PoseState& S, const float Xf[kSlots][3], float g[kSlots][3],
+                             float& F, float* xs, float* gs) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int k = 0; k < kSlots; k++) {
+        const int i = lane + k * kWave;
+        if (i < S.l)
+            for (int a = 0; a < 3; a++) {
+                xs[3 * i + a] = Xf[k][a];
+                gs[3 * i + a] = 0.f;
+            }
+    }
+    wave_sync();
+    const uint16_t* fp = pen.efar + pen.far_off[S.lig];
+    const int nf = pen.n_far[S.lig];
+    float e2 = 0.f;
+    for (int q = lane; q < nf; q += kWave) {
+        const uint32_t pr = fp[q];
+        const int i = pr & 0xff, j = pr >> 8;
+        const float dx = xs[3 * i] - xs[3 * j], dy = xs[3 * i + 1] - xs[3 * j + 1], dz = xs[3 * i + 2] - xs[3 * j + 2];
+        const float d2 = dx * dx + dy * dy + dz * dz;
+        if (d2 < pen.cd2) {
+            const float e = pen.cd2 - d2;
+            e2 += e * e;
+            if (GRAD) {
+                // -w d(e^2)/dX_i = 4 w e (X_i - X_j), the opposite for X_j
+                const float c = 4.f * pen.w * e;
+                atomicAdd(&gs[3 * i], c * dx);
+                atomicAdd(&gs[3 * i + 1], c * dy);
+                atomicAdd(&gs[3 * i + 2], c * dz);
+                atomicAdd(&gs[3 * j], -c * dx);
+                atomicAdd(&gs[3 * j + 1], -c * dy);
+                atomicAdd(&gs[3 * j + 2], -c * dz);
+            }
+        }
+    }
+    F -= pen.w * e2;
+    if (GRAD) {
+        wave_sync();
+#pragma unroll
+        for (int k = 0; k < kSlots; k++) {
+            const int i = lane + k * kWave;
+            if (i < S.l)
+                for (int a = 0; a < 3; a++) g[k][a] += gs[3 * i + a];
+        }
+    }
+    wave_sync();
+}
+
 // F and (optionally) dF/d(t, q, tau) at the given parameters.  tau, gtau and
 // axes (6 floats per rotamer: pivot and unit axis in the torsion frame) are
 // this wave's LDS arrays indexed by rotamer (list order); only lane-uniform
-// values are returned.
+// values are returned.  With pen.w > 0 F is the clash-penalised surrogate;
+// xs and gs are then this wave's LDS scratch (3 floats per atom).
 template <bool GRAD>
 __device__ float surrogate_eval(const PocketDev& P, const TreeDev& T, const PoseState& S, const float* t,
                                 const float* q, const float* tau, float* axes, float* gt, float* gq, float* gtau,
-                                float Xout[kSlots][3]) {
+                                float Xout[kSlots][3], const Penalty pen = Penalty{}, float* xs = nullptr,
+                                float* gs = nullptr) {
     const int lane = lane_id();
     float Ys[kSlots][3], Xf[kSlots][3], g[kSlots][3], Rq[9];
     pose_forward(T, S, t, q, tau, GRAD ? axes : nullptr, Ys, Xf, Rq);
@@ -208,6 +273,7 @@ __device__ float surrogate_eval(const PocketDev& P, const TreeDev& T, const Pose
         if (Xout)
             for (int a = 0; a < 3; a++) Xout[k][a] = Xf[k][a];
     }
+    if (pen.w > 0.f) bump_penalty<GRAD>(pen, S, Xf, g, F, xs, gs);
     F = wsum(F);
     if (!GRAD) return F;
     // translation
@@ -316,10 +382,14 @@ __global__ void __launch_bounds__(256) surrogate_kernel(PocketDev P, TreeDev T, 
 }
 
 // The whole ascent of one pose in one wavefront: parameters stay in
-// registers; the final pose is written to (rx, ry, rz).
+// registers; the final pose is written to (rx, ry, rz).  PEN: the
+// clash-penalised surrogate (its own instance, so that the plain one keeps its
+// registers and LDS).
+template <bool PEN>
 __global__ void __launch_bounds__(256) refine_kernel(PocketDev P, TreeDev T, PoseDev X, int n_poses, RefineParams rp,
                                                      float* rx, float* ry, float* rz, float* F_out) {
     __shared__ float tau_all[4][kMaxRot], gtau_all[4][kMaxRot], axes_all[4][6 * kMaxRot];
+    __shared__ float pen_x[4][PEN ? 3 * kMaxAtoms : 1], pen_g[4][PEN ? 3 * kMaxAtoms : 1];
     const int wave = threadIdx.x / kWave;
     const int pose = blockIdx.x * 4 + wave;
     if (pose >= n_poses) return;
@@ -328,12 +398,14 @@ __global__ void __launch_bounds__(256) refine_kernel(PocketDev P, TreeDev T, Pos
     float* gtau = gtau_all[wave];
     PoseState S;
     load_pose(T, X, pose, S);
+    const Penalty pen = PEN ? Penalty{rp.clash_weight, rp.cd2, rp.efar, rp.far_off, rp.n_far} : Penalty{};
     float t[3] = {0.f, 0.f, 0.f}, q[4] = {1.f, 0.f, 0.f, 0.f};
     float gt[3], gq[4];
     for (int r = lane; r < kMaxRot; r += kWave) tau[r] = gtau[r] = 0.f;
     wave_sync();
     for (int s = 0; s < rp.steps; s++) {
-        surrogate_eval<true>(P, T, S, t, q, tau, axes_all[wave], gt, gq, gtau, nullptr);
+        surrogate_eval<true>(P, T, S, t, q, tau, axes_all[wave], gt, gq, gtau, nullptr, pen, pen_x[wave],
+                             pen_g[wave]);
         float dt[3] = {rp.lr_t * gt[0], rp.lr_t * gt[1], rp.lr_t * gt[2]};
         float n = sqrtf(dt[0] * dt[0] + dt[1] * dt[1] + dt[2] * dt[2]);
         float sc = n > rp.max_dt ? rp.max_dt / n : 1.f;
@@ -350,7 +422,8 @@ __global__ void __launch_bounds__(256) refine_kernel(PocketDev P, TreeDev T, Pos
         wave_sync();
     }
     float Xf[kSlots][3];
-    float F = surrogate_eval<false>(P, T, S, t, q, tau, nullptr, nullptr, nullptr, nullptr, Xf);
+    float F = surrogate_eval<false>(P, T, S, t, q, tau, nullptr, nullptr, nullptr, nullptr, Xf, pen, pen_x[wave],
+                                    pen_g[wave]);
     const int off = X.pose_off[pose];
     for (int k = 0; k < kSlots; k++) {
         int i = lane_id() + k * kWave;
@@ -402,8 +475,12 @@ hipError_t launch_refine(const PocketDev& P, const TreeDev& T, const PoseDev& X,
                          hipStream_t s) {
     (void)lmax;
     if (n_poses <= 0) return hipSuccess;
-    hipLaunchKernelGGL(refine_kernel, dim3((n_poses + 3) / 4), dim3(256), 0, s, P, T, X, n_poses, rp, rx, ry, rz,
-                       F_out);
+    if (rp.clash_weight > 0.f)
+        hipLaunchKernelGGL(refine_kernel<true>, dim3((n_poses + 3) / 4), dim3(256), 0, s, P, T, X, n_poses, rp, rx, ry,
+                           rz, F_out);
+    else
+        hipLaunchKernelGGL(refine_kernel<false>, dim3((n_poses + 3) / 4), dim3(256), 0, s, P, T, X, n_poses, rp, rx,
+                           ry, rz, F_out);
     return hipGetLastError();
 }
 

@@ -77,6 +77,8 @@ gd_status refine(const gd_pocket* P, const gd_ligands* topo, int32_t n_poses, co
         !std::isfinite(o->lr_q) || !std::isfinite(o->lr_tau))
         return fail(GD_ERR_ARG, "%s: bad options", who);
     if (!(clash_dist >= 0.f) || clash_dist > 100.f) return fail(GD_ERR_ARG, "%s: bad clash_dist", who);
+    if (!(o->clash_weight >= 0.f) || !std::isfinite(o->clash_weight))
+        return fail(GD_ERR_ARG, "%s: clash_weight must be finite and >= 0", who);
     AsyncScratch A(s);
     SurrogateCall C;
     gd_status st = setup(P, topo, n_poses, pose_lig, px, py, pz, A, C, who);
@@ -107,7 +109,8 @@ gd_status refine(const gd_pocket* P, const gd_ligands* topo, int32_t n_poses, co
     SD.pz = pz;
     if ((e = launch_score(P->dev, SD, n_poses, cd * cd, (int32_t*)S_in, (uint8_t*)c_in, s)) != hipSuccess)
         return hip_fail(e, who);
-    RefineParams rp{o->steps, o->lr_t, o->lr_q, o->lr_tau, o->max_dt, o->max_dtau};
+    RefineParams rp{o->steps, o->lr_t, o->lr_q, o->lr_tau, o->max_dt, o->max_dtau, o->clash_weight,
+                    (float)(cd * cd), SD.efar, SD.far_off, SD.n_far};
     struct Events {  // optional timing of the ascent kernel
         hipEvent_t ev[2] = {nullptr, nullptr};
         ~Events() {

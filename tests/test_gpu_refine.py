@@ -126,12 +126,15 @@ def test_autograd_function(g, setup):
 
 
 @gpu
-def test_refine_rescoring_and_acceptance(g, setup):
+@pytest.mark.parametrize("cw", [0.0, 10.0])
+def test_refine_rescoring_and_acceptance(g, setup, cw):
+    """cw > 0: the clash-penalised surrogate, against the oracle's penalised
+    ascent."""
     import torch
     S = setup
     ligs, pl = S["ligs"], S["pose_lig"]
     px, py, pz = S["px"].clone(), S["py"].clone(), S["pz"].clone()
-    out = g.refine(S["P"], ligs, pl, px, py, pz, steps=50, want_iterate=True)
+    out = g.refine(S["P"], ligs, pl, px, py, pz, steps=50, want_iterate=True, clash_weight=cw)
     F, Sg, cg, acc = (out[k].cpu().numpy() for k in ("F", "S", "clash", "accepted"))
     X = np.stack([px.cpu().numpy(), py.cpu().numpy(), pz.cpu().numpy()], 1)
     It = np.stack([v.cpu().numpy() for v in out["iterate"]], 1)
@@ -150,15 +153,15 @@ def test_refine_rescoring_and_acceptance(g, setup):
         else:
             assert np.array_equal(Xp, X0) and Sg[p] == s_in[0]
         # trajectory against the FP64 oracle (FP32 arithmetic; kinks can split paths)
-        prm, Xo, Fo = S["B"].refine(lig, X0.astype(np.float64), steps=50)
+        prm, Xo, Fo = S["B"].refine(lig, X0.astype(np.float64), steps=50, clash_weight=cw)
         fdiff.append(abs(F[p] - Fo) / max(abs(Fo), 1.0))
         rms.append(np.sqrt(((Xi - Xo) ** 2).sum(1).mean()))
         if acc[p]:
             assert np.array_equal(Xp, Xi)
     rms = np.array(rms)
-    print("refine: accepted %d/%d; final-iterate RMSD vs the FP64 trajectory: median %.2e, "
+    print("refine (clash weight %g): accepted %d/%d; final-iterate RMSD vs the FP64 trajectory: median %.2e, "
           "fraction <= 1e-3 A %.2f, max %.2e; median |dF|/F %.2e"
-          % (acc.sum(), len(pl), np.median(rms), np.mean(rms <= 1e-3), rms.max(), np.median(fdiff)))
+          % (cw, acc.sum(), len(pl), np.median(rms), np.mean(rms <= 1e-3), rms.max(), np.median(fdiff)))
     assert acc.sum() > 0
     assert np.median(fdiff) < 1e-4
     # the trilinear gradient jumps at lattice faces: an FP32 and an FP64 path

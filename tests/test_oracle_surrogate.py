@@ -175,3 +175,84 @@ def test_ascent_increases_the_surrogate():
         assert np.allclose(np.linalg.norm(X[b[:, 0]] - X[b[:, 1]], axis=1),
                            np.linalg.norm(X0[b[:, 0]] - X0[b[:, 1]], axis=1), atol=1e-9)
     assert ups >= 7
+
+
+# --------------------------------------------------------------------------
+# Clash-penalised surrogate: F - lam sum_{far pairs, d < c} (c^2 - d^2)^2
+
+def _fd_grad_pen(B, lig, X0, prm, h, **kw):
+    # the penalty is C1 in the coordinates; the density part needs the
+    # stencil to stay inside its trilinear cells, as above
+    g = np.zeros(len(prm))
+    crossed = np.zeros(len(prm), bool)
+    _, _, Xc = B.surrogate(lig, X0, prm, want_grad=False, **kw)
+    for k in range(len(prm)):
+        for hh in (h, 1e-7):
+            e = np.zeros(len(prm))
+            e[k] = hh
+            Fp, _, Xp = B.surrogate(lig, X0, prm + e, want_grad=False, **kw)
+            Fm, _, Xm = B.surrogate(lig, X0, prm - e, want_grad=False, **kw)
+            if np.array_equal(_cells(Xp), _cells(Xc)) and np.array_equal(_cells(Xm), _cells(Xc)):
+                g[k] = (Fp - Fm) / (2 * hh)
+                break
+        else:
+            crossed[k] = True
+    return g, crossed
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_clash_penalty_value_and_gradient(seed):
+    pts = configs.SINGLE.pocket_points()
+    P, B = _blur(pts)
+    lig = synth.ligands(4, 10 + seed, 1, 20, 40, 2, 8).ligand(0)
+    rng = np.random.default_rng(50 + seed)
+    X0 = _pose(lig, pts.mean(0).astype(np.float64) + rng.normal(0, 1.0, 3))
+    nr = len(lig["rot"])
+    q = rng.normal(size=4)
+    q /= np.linalg.norm(q)
+    prm = np.concatenate([rng.normal(0, 0.3, 3), q, rng.normal(0, 0.6, nr)])
+    # a wide bump distance puts several far pairs inside the penalty band
+    kw = dict(clash_weight=0.25, clash_dist=4.5, clash_min_bonds=4)
+    F0, _, X = B.surrogate(lig, X0, prm)
+    F1, g1, X1 = B.surrogate(lig, X0, prm, **kw)
+    assert np.array_equal(X, X1)
+    # value: an independent brute force over the bond-count distances
+    _, dist, _ = oracle.topology(lig)
+    iu = np.triu_indices(len(X), 1)
+    far = dist[iu] >= 4
+    d2 = ((X[iu[0]] - X[iu[1]]) ** 2).sum(1)
+    band = far & (d2 < 4.5 ** 2)
+    assert band.sum() >= 1
+    pen = 0.25 * ((4.5 ** 2 - d2[band]) ** 2).sum()
+    assert F1 == pytest.approx(F0 - pen, rel=1e-12, abs=1e-12)
+    # gradient: central differences
+    gfd, crossed = _fd_grad_pen(B, lig, X0, prm, 1e-5, **kw)
+    ok = ~crossed
+    assert ok.sum() >= len(prm) - 2
+    assert np.allclose(g1[ok], gfd[ok], rtol=2e-4, atol=2e-4 * (1 + np.abs(g1).max()))
+    # the weight 0 is the plain surrogate
+    F2, g2, _ = B.surrogate(lig, X0, prm, clash_weight=0.0, clash_dist=4.5)
+    F3, g3, _ = B.surrogate(lig, X0, prm)
+    assert F2 == F3 and np.array_equal(g2, g3)
+
+
+def test_penalised_ascent_has_fewer_bumps():
+    # an aggressive torsion ascent on the plain surrogate ends with bumping
+    # far pairs; the penalised one (weight 10) ends with at most half as many
+    pts = configs.SINGLE.pocket_points()
+    P, B = _blur(pts)
+    plain = pen = 0
+    for seed in range(12):
+        lig = synth.ligands(4, 30 + seed, 1, 30, 50, 4, 8).ligand(0)
+        X0 = _pose(lig, pts.mean(0).astype(np.float64))
+        _, dist, _ = oracle.topology(lig)
+        iu = np.triu_indices(len(X0), 1)
+        far = dist[iu] >= 4
+
+        def bumps(X):
+            return int((far & (((X[iu[0]] - X[iu[1]]) ** 2).sum(1) < 4.0)).sum())
+        _, Xa, _ = B.refine(lig, X0, steps=60, lr_tau=5e-3, max_dtau=0.2)
+        _, Xb, _ = B.refine(lig, X0, steps=60, lr_tau=5e-3, max_dtau=0.2, clash_weight=10.0)
+        plain += bumps(Xa)
+        pen += bumps(Xb)
+    assert plain >= 10 and 2 * pen <= plain
