@@ -14,7 +14,8 @@ Each recipe fixes the generator streams, sizes and knobs of one workload:
              orientations {64,256,1024} x step {30,15,10}.
   refine     4,096 ligands (20-80 atoms, 2-12 rotatable bonds) x top-64 poses
              docked with the 'single' knobs in the 'single' pocket; Gaussian
-             blur sigma 0.6 A on a 0.375 A lattice; 50 ascent steps.
+             blur sigma 0.6 A on a 0.375 A lattice; 50 ascent steps; the
+             clash-penalised variant with weight 1,000.
   large      1,000,000 ligands (atoms U[15,120], rotatable bonds U[0,16], 5 %
              with a rigid 3-6 ring) x 1 pocket (10,000 points, 16/12/9 A);
              1024 orientations, 10-degree steps, chunks of 65,536, top-8
@@ -100,7 +101,7 @@ GRID = Workload("grid", lig_seed=2, n_ligands=100_000, lmin=20, lmax=80, bmin=2,
 REFINE = Workload("refine", lig_seed=4, n_ligands=4096, lmin=20, lmax=80, bmin=2, bmax=12, ring_frac=0.0,
                   pockets=[(1000, 1000, (8.0, 6.0, 5.0))], n_orient=256, hp=10, top_k=64,
                   extra=dict(blur_sigma=0.6, blur_h=0.375, steps=50, lr_t=0.002, lr_q=1e-5, lr_tau=5e-4, max_dt=0.1,
-                             max_dtau=0.05))
+                             max_dtau=0.05, clash_weight=1000.0))
 
 LARGE = Workload("large", lig_seed=5, n_ligands=1_000_000, lmin=15, lmax=120, bmin=0, bmax=16, ring_frac=0.05,
                  pockets=[(1010, 10_000, (16.0, 12.0, 9.0))], n_orient=1024, hp=10, top_k=8, chunk=65_536, pad=20.0)
