@@ -88,3 +88,32 @@ def test_dse_baseline_added_when_missing(g):
     assert len(recs) == 2 and dse.is_baseline(recs[0]) and recs[0]["degradation"] == 0.0
     with pytest.raises(ValueError):
         dse.explore(P, ligs, q, space=dict(hp=[30], repetitions=[1]), include_baseline=False)
+
+
+@gpu
+@pytest.mark.parametrize("cfg", [dict(hp=1, lp=45, threshold=0.0, repetitions=3, refine=False),
+                                 dict(hp=5, lp=90, threshold=0.8, repetitions=1, refine=True)])
+def test_dse_full_size_sampled(g, cfg):
+    """The exploration workload at its full size (20,000 ligands x 32
+    orientations, the launch the exploration times) for the baseline and the
+    fastest full-space configuration; 6 sampled ligands' scores against the
+    oracle pipeline."""
+    import torch
+    from paper_1901_06363_amd import dse
+    w = configs.DSE
+    pts = w.pocket_points()
+    P, O = g.Pocket(pts, 0.5, w.pad), oracle.OraclePocket(pts, 0.5)
+    ligs = w.ligands()
+    q = w.quaternions()
+    got = dse.ligand_scores(P, ligs, q, cfg, top_k=1)
+    assert len(got["score"]) == 20000 and got["feasible"].mean() > 0.99
+    px, py, pz = got["xyz"]
+    Xg = torch.stack([px, py, pz], 1).cpu().numpy()
+    off = np.concatenate([[0], np.cumsum(np.diff(np.asarray(ligs.atom_off)))])
+    rng = np.random.default_rng(3)
+    idx = rng.choice(ligs.n, 6, replace=False)
+    exp, X = _oracle_scores(O, ligs.subset(idx), q, cfg)
+    xo = np.concatenate([[0], np.cumsum([ligs.n_atoms(int(i)) for i in idx])])
+    for t, i in enumerate(idx):
+        assert got["score"][i] == exp[t], i
+        assert np.array_equal(Xg[off[i]:off[i + 1]], X[xo[t]:xo[t + 1]]), i

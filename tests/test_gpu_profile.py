@@ -67,3 +67,36 @@ def test_profile_guards(g):
     assert not S.any().item() and not f.any().item() and not sz.any().item()
     with pytest.raises(ValueError):
         g.sweep_profile(P, B, res, step=7)
+
+
+@gpu
+def test_profile_peaks_workload_sampled(g):
+    """The peak-analysis launch (2,000 exploration ligands at the baseline
+    knobs, 1-degree landscapes of every side at the best pose); 5 sampled
+    ligands against the oracle, every rotamer side."""
+    import torch
+    from paper_1901_06363_amd import dse
+    w = configs.DSE
+    pts = w.pocket_points()
+    P, O = g.Pocket(pts, 0.5, w.pad), oracle.OraclePocket(pts, 0.5)
+    ligs = w.ligands(0, 2000)
+    q = w.quaternions()
+    b = dse.BASELINE
+    B = g.Batch(P, ligs, q, top_k=1, **b)
+    res = B.dock(g.BATCHED)
+    S, f, sz = g.sweep_profile(P, B, res, step=1)
+    torch.cuda.synchronize()
+    S, f, sz = S.cpu().numpy(), f.cpu().numpy(), sz.cpu().numpy()
+    h = res.host()
+    kn = oracle.knobs(**b)
+    rng = np.random.default_rng(4)
+    for i in rng.choice(ligs.n, 5, replace=False):
+        lig = ligs.ligand(int(i))
+        o = int(h["orient"][i, 0])
+        Xo = oracle.dock(O, lig, kn, q[o:o + 1]).xyz[0]
+        for rr in range(ligs.n_rot(int(i))):
+            for side in (0, 1):
+                size, So, fo = oracle.sweep_profile(O, lig, Xo, rr, side, step=1)
+                assert sz[i, 0, rr, side] == size
+                assert np.array_equal(S[i, 0, rr, side], So), (i, rr, side)
+                assert np.array_equal(f[i, 0, rr, side] != 0, fo), (i, rr, side)
