@@ -19,6 +19,11 @@
 #include "device_common.h"
 #include "gd_internal.h"
 
+// The refinement is compared with the FP64 oracle within a tolerance, not bit
+// for bit: let the compiler fuse multiply-adds here (the library is otherwise
+// built without contraction, which the docking kernel's rounding guards need).
+#pragma clang fp contract(fast)
+
 namespace gd {
 
 constexpr int kSlots = kMaxAtoms / kWave;  // atoms per lane
