@@ -110,7 +110,35 @@ class LigandBatch:
 
 def ligands(seed: int, first: int, count: int, lmin: int, lmax: int, bmin: int, bmax: int,
             ring_frac: float = 0.0) -> LigandBatch:
-    """Ligands [first, first+count) of the stream ``seed``."""
+    """Ligands [first, first+count) of the stream ``seed``.  Every ligand has
+    its own generator stream, so large requests are split over threads (the
+    C generator runs without the interpreter lock) with the same result."""
+    parts = min(os.cpu_count() or 1, 16, count // 4096)
+    if parts <= 1:
+        return _ligands_serial(seed, first, count, lmin, lmax, bmin, bmax, ring_frac)
+    from concurrent.futures import ThreadPoolExecutor
+    cut = np.linspace(0, count, parts + 1).astype(np.int64)
+    with ThreadPoolExecutor(parts) as ex:
+        bs = list(ex.map(lambda k: _ligands_serial(seed, first + int(cut[k]), int(cut[k + 1] - cut[k]), lmin, lmax,
+                                                   bmin, bmax, ring_frac), range(parts)))
+    return _concat(bs)
+
+
+def _concat(bs) -> LigandBatch:
+    def offs(name):
+        out, base = [np.zeros(1, np.int32)], 0
+        for b in bs:
+            o = getattr(b, name)
+            out.append((o[1:] + base).astype(np.int32))
+            base += int(o[-1])
+        return np.concatenate(out)
+    cat = lambda name: np.concatenate([getattr(b, name) for b in bs])
+    return LigandBatch(offs("atom_off"), cat("x"), cat("y"), cat("z"), offs("bond_off"), cat("bonds"),
+                       offs("rot_off"), cat("rot"))
+
+
+def _ligands_serial(seed: int, first: int, count: int, lmin: int, lmax: int, bmin: int, bmax: int,
+                    ring_frac: float = 0.0) -> LigandBatch:
     lib = _load()
     atom_off = np.zeros(count + 1, np.int32)
     bond_off = np.zeros(count + 1, np.int32)
