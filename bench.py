@@ -328,18 +328,22 @@ def large_leg(gd, torch, n_chunks):
                 max_dtau=r["max_dtau"])
     n = n_chunks * w.chunk
     poses = atoms = 0
+    dock_ms = 0.0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for item in screen(P, w.ligands, n, w.quaternions(), chunk=w.chunk, refine_poses=ropt, hp=w.hp, top_k=w.top_k):
         poses += item["poses"]
         atoms += int(item["ligands"].atom_off[-1])
+        dock_ms += item["dock_ms"]
         log("large: chunk at %d done (%.1f s)" % (item["first"], time.perf_counter() - t0))
     dt = time.perf_counter() - t0
     return dict(workload="large: %d ligands (15-120 atoms, 0-16 rotatable bonds, 5%% with a ring) x 10,000-point "
                          "pocket, 1024 orientations, 10-degree steps, chunks of %d, top-8 refined" % (n, w.chunk),
                 ligands=n, poses=poses, seconds=dt, poses_per_s=poses / dt, ligands_per_s=n / dt,
-                atoms_per_s=atoms / dt, note="wall clock over the whole stream: generation, preparation, docking, "
-                                             "top-k, refinement and host copies")
+                atoms_per_s=atoms / dt, dock_kernel_s=dock_ms * 1e-3,
+                kernel_poses_per_s=poses / (dock_ms * 1e-3),
+                note="wall clock over the whole stream: generation, preparation, docking, top-k, refinement and host "
+                     "copies; dock_kernel_s is the docking kernels' share (HIP events)")
 
 
 def main():

@@ -51,16 +51,24 @@ def _prepare(slot, pocket, source, first, count, quats, knobs, stream):
 
 def screen(pocket, source, n_ligands, quats, chunk=65536, mode=BATCHED, refine_poses=None, want_xyz=True, **knobs):
     """Dock ligands [0, n_ligands) of ``source`` in chunks; yields one dict per
-    chunk: first, count, ligands, poses, result (host arrays of the top-k
-    poses), and with ``refine_poses`` the refined poses' surrogate, exact S,
-    clash, acceptance and coordinates.  ``knobs`` are the Batch knobs (hp, lp,
-    threshold, repetitions, refine (tile peeling), top_k, clash_dist,
-    clash_min_bonds); the pocket needs a density grid for ``refine_poses``.
+    chunk: first, count, ligands, poses, dock_ms (docking kernel time, HIP
+    events), result (host arrays of the top-k poses), and with ``refine_poses``
+    the refined poses' surrogate, exact S, clash, acceptance and coordinates.
+    ``knobs`` are the Batch knobs (hp, lp, threshold, repetitions, refine (tile
+    peeling), top_k, clash_dist, clash_min_bonds); the pocket needs a density
+    grid for ``refine_poses``.
+
+    The chunks are pipelined: while chunk i docks on the GPU, a host thread
+    prepares chunk i+1, and chunk i-1 is refined on its own stream (after its
+    docking, concurrently with chunk i's) and copied to the host on a third
+    stream that waits for chunk i-1's work only.
     """
     torch = _torch()
     if refine_poses is not None and not want_xyz:
         raise ValueError("refinement needs the pose coordinates (want_xyz=True)")
     side = torch.cuda.Stream()
+    rstream = torch.cuda.Stream()
+    copy = torch.cuda.Stream()
     main = torch.cuda.current_stream()
     starts = list(range(0, n_ligands, chunk))
 
@@ -72,7 +80,32 @@ def screen(pocket, source, n_ligands, quats, chunk=65536, mode=BATCHED, refine_p
         th.start()
         return slot, th
 
+    def finish(p):
+        # refinement of one chunk on its stream after its docking, then the
+        # host copies on the copy stream after both
+        item = p["item"]
+        refined = None
+        if refine_poses is not None:
+            rstream.wait_event(p["event"])
+            with torch.cuda.stream(rstream):
+                pose_lig, px, py, pz = poses_from_topk(p["out"], item["ligands"])
+                r = _refine(pocket, item["ligands"], pose_lig, px, py, pz, stream=rstream, **refine_poses)
+            refined = (pose_lig, px, py, pz, r)
+            copy.wait_stream(rstream)
+        copy.wait_event(p["event"])
+        with torch.cuda.stream(copy):
+            if refined is not None:
+                pose_lig, px, py, pz, r = refined
+                item["refine"] = dict(pose_lig=pose_lig, F=r["F"].cpu().numpy(), S=r["S"].cpu().numpy(),
+                                      clash=r["clash"].cpu().numpy(), accepted=r["accepted"].cpu().numpy(),
+                                      xyz=torch.stack([px, py, pz], 1).cpu().numpy())
+            item["result"] = p["out"].host()
+        copy.synchronize()
+        item["dock_ms"] = float(sum(p["batch"].read_timing()))
+        return item
+
     nxt = launch(0) if starts else None
+    pending = None
     for i, first in enumerate(starts):
         slot, th = nxt
         th.join()
@@ -80,17 +113,16 @@ def screen(pocket, source, n_ligands, quats, chunk=65536, mode=BATCHED, refine_p
             raise slot.error
         B = slot.batch
         out = B.alloc_outputs(want_angles=True, want_xyz=want_xyz)
+        B.enable_timing(True)
         B.dock(mode, out)
+        ev = torch.cuda.Event()
+        ev.record(main)
         # prepare the next chunk while this one docks
         nxt = launch(i + 1) if i + 1 < len(starts) else None
-        item = dict(first=first, count=B.n_ligands, ligands=slot.ligands, poses=B.poses_expected)
-        if refine_poses is not None:
-            pose_lig, px, py, pz = poses_from_topk(out, slot.ligands)
-            r = _refine(pocket, slot.ligands, pose_lig, px, py, pz, **refine_poses)
-            item["refine"] = dict(pose_lig=pose_lig, F=r["F"].cpu().numpy(), S=r["S"].cpu().numpy(),
-                                  clash=r["clash"].cpu().numpy(), accepted=r["accepted"].cpu().numpy(),
-                                  xyz=torch.stack([px, py, pz], 1).cpu().numpy())
-        main.synchronize()
-        item["result"] = out.host()
-        yield item
-        del out, B, slot
+        if pending is not None:
+            yield finish(pending)
+        pending = dict(item=dict(first=first, count=B.n_ligands, ligands=slot.ligands, poses=B.poses_expected),
+                       batch=B, out=out, event=ev)
+        del slot
+    if pending is not None:
+        yield finish(pending)
