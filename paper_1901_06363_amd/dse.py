@@ -25,6 +25,7 @@ from __future__ import annotations
 
 import itertools
 import math
+import threading
 
 import numpy as np
 
@@ -88,17 +89,52 @@ def pareto_front(throughput, degr) -> np.ndarray:
     return keep
 
 
-def ligand_scores(pocket, ligands, quats, cfg, top_k=1, clash_dist=2.0, clash_min_bonds=4, stream=None):
+def _batch(pocket, ligands, quats, cfg, top_k, clash_dist, clash_min_bonds, stream=None):
+    return Batch(pocket, ligands, quats, hp=cfg["hp"], lp=cfg["lp"], threshold=cfg["threshold"],
+                 repetitions=cfg["repetitions"], refine=cfg["refine"], top_k=top_k, clash_dist=clash_dist,
+                 clash_min_bonds=clash_min_bonds, stream=stream)
+
+
+def prepared_batches(pocket, ligands, quats, cfgs, top_k=1, clash_dist=2.0, clash_min_bonds=4):
+    """Yield (cfg, Batch) for every configuration, preparing the next batch on
+    a host thread (uploads on a side stream) while the caller docks the
+    current one."""
+    torch = _torch()
+    side = torch.cuda.Stream()
+
+    def start(c):
+        box = {}
+
+        def run():
+            try:
+                box["b"] = _batch(pocket, ligands, quats, c, top_k, clash_dist, clash_min_bonds, side)
+            except BaseException as e:  # re-raised in the consumer
+                box["e"] = e
+        th = threading.Thread(target=run)
+        th.start()
+        return box, th
+
+    nxt = start(cfgs[0]) if cfgs else None
+    for i, c in enumerate(cfgs):
+        box, th = nxt
+        th.join()
+        if "e" in box:
+            raise box["e"]
+        nxt = start(cfgs[i + 1]) if i + 1 < len(cfgs) else None
+        yield c, box["b"]
+
+
+def ligand_scores(pocket, ligands, quats, cfg, top_k=1, clash_dist=2.0, clash_min_bonds=4, stream=None, batch=None):
     """Dock one configuration and re-score each ligand's top-k poses with the
     continuous Eq. 1.  Returns a dict: score (per ligand: the best continuous
     overlap among its feasible top-k poses, 0 when none is feasible), S and
     grid overlap of the best pose, per-pose continuous overlaps, the pose
-    coordinates (device tensors), dock_ms, rescore_ms."""
+    coordinates (device tensors), dock_ms, rescore_ms.  `batch` may bring
+    the configuration's prepared Batch."""
     torch = _torch()
     from .stream import poses_from_topk
-    B = Batch(pocket, ligands, quats, hp=cfg["hp"], lp=cfg["lp"], threshold=cfg["threshold"],
-              repetitions=cfg["repetitions"], refine=cfg["refine"], top_k=top_k, clash_dist=clash_dist,
-              clash_min_bonds=clash_min_bonds, stream=stream)
+    B = batch if batch is not None else _batch(pocket, ligands, quats, cfg, top_k, clash_dist, clash_min_bonds,
+                                               stream)
     B.enable_timing(True)
     out = B.alloc_outputs(want_angles=False, want_xyz=True)
     B.dock(BATCHED, out, stream=stream)
@@ -132,8 +168,10 @@ def explore(pocket, ligands, quats, space="full", top_k=1, frac=0.01, include_ba
     if include_baseline and not any(is_baseline(c) for c in cfgs):
         cfgs = [dict(BASELINE)] + cfgs
     recs = []
-    for i, c in enumerate(cfgs):
-        r = ligand_scores(pocket, ligands, quats, c, top_k=top_k, **score_kw)
+    kw = {k: v for k, v in score_kw.items() if k in ("clash_dist", "clash_min_bonds")}
+    for i, (c, B) in enumerate(prepared_batches(pocket, ligands, quats, cfgs, top_k=top_k, **kw)):
+        r = ligand_scores(pocket, ligands, quats, c, top_k=top_k, batch=B, **score_kw)
+        del B
         t = r["dock_ms"] + r["rescore_ms"]
         rec = dict(c, dock_ms=r["dock_ms"], rescore_ms=r["rescore_ms"], time_ms=t,
                    atoms_per_s=r["n_atoms"] / (t * 1e-3), ligands_per_s=len(r["score"]) / (t * 1e-3),

@@ -143,17 +143,16 @@ def campaign(pockets, ligand_sets, quats, configs, reps=1, warm=True, progress=N
     docking kernel's time in ms (HIP events around the kernel alone; the
     median of `reps` timed calls, after one untimed call when `warm`).
     `pockets` is a list of (Pocket, n_points)."""
-    from . import BATCHED, Batch, _torch
+    from . import BATCHED, _torch
     torch = _torch()
     recs = []
     n_runs = len(pockets) * len(ligand_sets) * len(configs)
     i = 0
+    from .dse import prepared_batches
     for pi, (P, npts) in enumerate(pockets):
         for li, L in enumerate(ligand_sets):
             a, r = ligand_features(L)
-            for cfg in configs:
-                B = Batch(P, L, quats, hp=cfg["hp"], lp=cfg["lp"], threshold=cfg["threshold"],
-                          repetitions=cfg["repetitions"], refine=cfg["refine"], **batch_kw)
+            for cfg, B in prepared_batches(P, L, quats, configs, **batch_kw):
                 out = B.alloc_outputs(want_angles=False, want_xyz=False)
                 if warm:
                     B.dock(BATCHED, out)
