@@ -339,13 +339,27 @@ typedef struct {
                            paper); F_out is then that penalised value         */
 } gd_refine_opts;
 
+/*
+ * Optional bump penalty of the surrogate (an extension beyond the paper):
+ * F - weight * sum over the ligand's atom pairs at least clash_min_bonds bonds
+ * apart with d < clash_dist of (clash_dist^2 - d^2)^2.  NULL or weight 0: the
+ * plain surrogate.  Errors: GD_ERR_ARG for a negative or non-finite weight or
+ * a clash_dist outside [0, 100].
+ */
+typedef struct {
+    float weight;
+    float clash_dist;
+    int32_t clash_min_bonds;
+} gd_bump_penalty;
+
 gd_status gd_surrogate_fwd(const gd_pocket* pocket, const gd_ligands* topo, int32_t n_poses, const int32_t* pose_lig,
                            const float* px, const float* py, const float* pz, const float* t, const float* q,
-                           const float* tau, int32_t tau_stride, void* stream, float* F_out);
+                           const float* tau, int32_t tau_stride, const gd_bump_penalty* penalty, void* stream,
+                           float* F_out);
 gd_status gd_surrogate_bwd(const gd_pocket* pocket, const gd_ligands* topo, int32_t n_poses, const int32_t* pose_lig,
                            const float* px, const float* py, const float* pz, const float* t, const float* q,
-                           const float* tau, int32_t tau_stride, const float* dF, void* stream, float* dt_out,
-                           float* dq_out, float* dtau_out);
+                           const float* tau, int32_t tau_stride, const gd_bump_penalty* penalty, const float* dF,
+                           void* stream, float* dt_out, float* dq_out, float* dtau_out);
 
 /*
  * Refine poses by `steps` ascent steps on F, then judge each refined pose with

@@ -49,6 +49,10 @@ class Tiling(ctypes.Structure):
     _fields_ = [("waves_per_block", I32), ("angle_block", I32), ("pairs_per_lane", I32)]
 
 
+class BumpPenalty(ctypes.Structure):
+    _fields_ = [("weight", F32), ("clash_dist", F32), ("clash_min_bonds", I32)]
+
+
 class RefineOpts(ctypes.Structure):
     _fields_ = [("steps", I32), ("lr_t", F32), ("lr_q", F32), ("lr_tau", F32), ("max_dt", F32), ("max_dtau", F32),
                 ("kernel_ms", ctypes.POINTER(F32)), ("clash_weight", F32)]
@@ -75,8 +79,8 @@ SIGNATURES = [
     ("gd_score_poses", I32, [P, P, I32, P, P, P, P, F32, I32, P, P, P]),
     ("gd_overlap_continuous", I32, [P, I32, P, ctypes.c_int64, P, P, P, P, P, P, P]),
     ("gd_sweep_profile", I32, [P, P, P, I32, P, P, P, P]),
-    ("gd_surrogate_fwd", I32, [P, P, I32, P, P, P, P, P, P, P, I32, P, P]),
-    ("gd_surrogate_bwd", I32, [P, P, I32, P, P, P, P, P, P, P, I32, P, P, P, P, P]),
+    ("gd_surrogate_fwd", I32, [P, P, I32, P, P, P, P, P, P, P, I32, P, P, P]),
+    ("gd_surrogate_bwd", I32, [P, P, I32, P, P, P, P, P, P, P, I32, P, P, P, P, P, P]),
     ("gd_refine", I32, [P, P, I32, P, P, P, P, P, F32, I32, P, P, P, P, P, P, P, P]),
 ]
 

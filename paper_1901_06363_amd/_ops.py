@@ -108,8 +108,16 @@ def _prm(t, q, tau, n):
     return t, q, tau, tau.shape[1]
 
 
-def surrogate_fwd(pocket, ligands, pose_lig, px, py, pz, t, q, tau, stream=None):
-    """F(t, q, tau) per pose (device float32 (n,))."""
+def _penalty(clash_weight, clash_dist, clash_min_bonds):
+    if not clash_weight:
+        return None
+    return ctypes.byref(_abi.BumpPenalty(float(clash_weight), float(clash_dist), int(clash_min_bonds)))
+
+
+def surrogate_fwd(pocket, ligands, pose_lig, px, py, pz, t, q, tau, stream=None, clash_weight=0.0, clash_dist=2.0,
+                  clash_min_bonds=4):
+    """F(t, q, tau) per pose (device float32 (n,)); clash_weight > 0 subtracts
+    the bump penalty."""
     torch = _torch()
     lg = _lig_desc(ligands)
     pl = np.ascontiguousarray(pose_lig, dtype=np.int32)
@@ -118,11 +126,14 @@ def surrogate_fwd(pocket, ligands, pose_lig, px, py, pz, t, q, tau, stream=None)
     F = torch.empty(n, dtype=torch.float32, device="cuda")
     _abi.check(_abi.load().gd_surrogate_fwd(pocket.handle, ctypes.byref(lg.desc), n,
                                             pl.ctypes.data_as(ctypes.c_void_p), _dp(px), _dp(py), _dp(pz), _dp(t),
-                                            _dp(q), _dp(tau), stride, _stream_ptr(stream), _dp(F)))
+                                            _dp(q), _dp(tau), stride, _penalty(clash_weight, clash_dist,
+                                                                               clash_min_bonds),
+                                            _stream_ptr(stream), _dp(F)))
     return F
 
 
-def surrogate_bwd(pocket, ligands, pose_lig, px, py, pz, t, q, tau, dF, stream=None):
+def surrogate_bwd(pocket, ligands, pose_lig, px, py, pz, t, q, tau, dF, stream=None, clash_weight=0.0,
+                  clash_dist=2.0, clash_min_bonds=4):
     """dF/dt, dF/dq, dF/dtau scaled by the upstream gradient dF (per pose)."""
     torch = _torch()
     lg = _lig_desc(ligands)
@@ -135,8 +146,9 @@ def surrogate_bwd(pocket, ligands, pose_lig, px, py, pz, t, q, tau, dF, stream=N
     dtau = torch.empty((n, stride), dtype=torch.float32, device="cuda")
     _abi.check(_abi.load().gd_surrogate_bwd(pocket.handle, ctypes.byref(lg.desc), n,
                                             pl.ctypes.data_as(ctypes.c_void_p), _dp(px), _dp(py), _dp(pz), _dp(t),
-                                            _dp(q), _dp(tau), stride, _dp(dF), _stream_ptr(stream), _dp(dt), _dp(dq),
-                                            _dp(dtau)))
+                                            _dp(q), _dp(tau), stride,
+                                            _penalty(clash_weight, clash_dist, clash_min_bonds), _dp(dF),
+                                            _stream_ptr(stream), _dp(dt), _dp(dq), _dp(dtau)))
     return dt, dq, dtau
 
 
@@ -180,21 +192,25 @@ def _make_autograd():
 
         ctx_obj = (pocket, ligands, pose_lig, px, py, pz) fixes the poses being
         refined; the backward kernel recomputes the pose from the parameters.
+        A seventh element, a dict (clash_weight, clash_dist, clash_min_bonds),
+        selects the clash-penalised surrogate.
         """
 
         @staticmethod
         def forward(ctx, t, q, tau, spec):
-            pocket, ligands, pose_lig, px, py, pz = spec
+            pocket, ligands, pose_lig, px, py, pz = spec[:6]
+            pen = spec[6] if len(spec) > 6 else {}
             ctx.spec = spec
             ctx.save_for_backward(t, q, tau)
-            return surrogate_fwd(pocket, ligands, pose_lig, px, py, pz, t.detach(), q.detach(), tau.detach())
+            return surrogate_fwd(pocket, ligands, pose_lig, px, py, pz, t.detach(), q.detach(), tau.detach(), **pen)
 
         @staticmethod
         def backward(ctx, dF):
             t, q, tau = ctx.saved_tensors
-            pocket, ligands, pose_lig, px, py, pz = ctx.spec
+            pocket, ligands, pose_lig, px, py, pz = ctx.spec[:6]
+            pen = ctx.spec[6] if len(ctx.spec) > 6 else {}
             dt, dq, dtau = surrogate_bwd(pocket, ligands, pose_lig, px, py, pz, t.detach(), q.detach(), tau.detach(),
-                                         dF)
+                                         dF, **pen)
             return dt, dq, dtau[:, :tau.shape[1]], None
 
     return SurrogateScore

@@ -147,6 +147,14 @@ hipError_t launch_reset(int* head, unsigned long long* counters, hipStream_t s);
 hipError_t launch_topk(const BatchDev& B, gd_pose_rec* out, uint16_t* ang_out, double h, hipStream_t s);
 hipError_t launch_score(const PocketDev& P, const ScoreDev& S, int n_poses, double cd2, int32_t* S_out,
                         uint8_t* clash_out, hipStream_t s);
+// Bump penalty of the clash-penalised surrogate: w * sum over the ligand's far
+// pairs (from far_off) with d^2 < cd2 of (cd2 - d^2)^2; w = 0: none.
+struct Penalty {
+    float w, cd2;
+    const uint16_t* efar;
+    const int32_t* far_off;
+    const int32_t* n_far;
+};
 struct RefineParams {
     int steps;
     float lr_t, lr_q, lr_tau, max_dt, max_dtau;
@@ -159,7 +167,8 @@ struct RefineParams {
 };
 hipError_t launch_surrogate(const PocketDev& P, const TreeDev& T, const PoseDev& X, int n_poses, const float* t,
                             const float* q, const float* tau, int tau_stride, const float* dF, float* F_out,
-                            float* dt_out, float* dq_out, float* dtau_out, int lmax, hipStream_t s);
+                            float* dt_out, float* dq_out, float* dtau_out, const Penalty& pen, int lmax,
+                            hipStream_t s);
 hipError_t launch_refine(const PocketDev& P, const TreeDev& T, const PoseDev& X, int n_poses,
                          const RefineParams& rp, float* rx, float* ry, float* rz, float* F_out, int lmax,
                          hipStream_t s);

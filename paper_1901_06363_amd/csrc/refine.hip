@@ -196,13 +196,6 @@ __device__ void pose_forward(const TreeDev& T, const PoseState& S, const float* 
 // F (lane partial) and, with GRAD, its derivative from the per-atom gradients
 // g.  Atoms go through this wave's LDS (xs, gs: 3 floats per atom); lanes own
 // pairs and add their gradient contributions with LDS atomics.
-struct Penalty {
-    float w, cd2;  // clash weight (0: none) and bump distance squared
-    const uint16_t* efar;
-    const int32_t* far_off;
-    const int32_t* n_far;
-};
-
 template <bool GRAD>
 __device__ void bump_penalty(const Penalty pen, const PoseState& S, const float Xf[kSlots][3], float g[kSlots][3],
                              float& F, float* xs, float* gs) {
@@ -349,11 +342,14 @@ __device__ float surrogate_eval(const PocketDev& P, const TreeDev& T, const Pose
 
 // ---------------------------------------------------------------------------
 
+template <bool PEN>
 __global__ void __launch_bounds__(256) surrogate_kernel(PocketDev P, TreeDev T, PoseDev X, int n_poses,
                                                         const float* t, const float* q, const float* tau,
                                                         int tau_stride, const float* dF, float* F_out, float* dt_out,
-                                                        float* dq_out, float* dtau_out) {
+                                                        float* dq_out, float* dtau_out, Penalty pen_in) {
     __shared__ float tau_all[4][kMaxRot], gtau_all[4][kMaxRot], axes_all[4][6 * kMaxRot];
+    __shared__ float pen_x[4][PEN ? 3 * kMaxAtoms : 1], pen_g[4][PEN ? 3 * kMaxAtoms : 1];
+    const Penalty pen = PEN ? pen_in : Penalty{};
     const int wave = threadIdx.x / kWave;
     const int pose = blockIdx.x * 4 + wave;
     if (pose >= n_poses) return;
@@ -370,12 +366,14 @@ __global__ void __launch_bounds__(256) surrogate_kernel(PocketDev P, TreeDev T, 
     }
     wave_sync();
     if (!dF) {
-        float F = surrogate_eval<false>(P, T, S, tp, qp, tau_l, nullptr, nullptr, nullptr, nullptr, nullptr);
+        float F = surrogate_eval<false>(P, T, S, tp, qp, tau_l, nullptr, nullptr, nullptr, nullptr, nullptr, pen,
+                                        pen_x[wave], pen_g[wave]);
         if (lane == 0) F_out[pose] = F;
         return;
     }
     float gt[3], gq[4];
-    float F = surrogate_eval<true>(P, T, S, tp, qp, tau_l, axes_all[wave], gt, gq, gtau, nullptr);
+    float F = surrogate_eval<true>(P, T, S, tp, qp, tau_l, axes_all[wave], gt, gq, gtau, nullptr, pen, pen_x[wave],
+                                   pen_g[wave]);
     const float up = dF[pose];
     if (lane == 0) {
         if (F_out) F_out[pose] = F;
@@ -467,11 +465,16 @@ __global__ void __launch_bounds__(256) accept_kernel(PoseDev X, int n_poses, con
 
 hipError_t launch_surrogate(const PocketDev& P, const TreeDev& T, const PoseDev& X, int n_poses, const float* t,
                             const float* q, const float* tau, int tau_stride, const float* dF, float* F_out,
-                            float* dt_out, float* dq_out, float* dtau_out, int lmax, hipStream_t s) {
+                            float* dt_out, float* dq_out, float* dtau_out, const Penalty& pen, int lmax,
+                            hipStream_t s) {
     (void)lmax;
     if (n_poses <= 0) return hipSuccess;
-    hipLaunchKernelGGL(surrogate_kernel, dim3((n_poses + 3) / 4), dim3(256), 0, s, P, T, X, n_poses, t, q, tau,
-                       tau_stride, dF, F_out, dt_out, dq_out, dtau_out);
+    if (pen.w > 0.f)
+        hipLaunchKernelGGL(surrogate_kernel<true>, dim3((n_poses + 3) / 4), dim3(256), 0, s, P, T, X, n_poses, t, q,
+                           tau, tau_stride, dF, F_out, dt_out, dq_out, dtau_out, pen);
+    else
+        hipLaunchKernelGGL(surrogate_kernel<false>, dim3((n_poses + 3) / 4), dim3(256), 0, s, P, T, X, n_poses, t, q,
+                           tau, tau_stride, dF, F_out, dt_out, dq_out, dtau_out, pen);
     return hipGetLastError();
 }
 

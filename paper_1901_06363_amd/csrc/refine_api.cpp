@@ -49,8 +49,8 @@ static gd_status setup(const gd_pocket* P, const gd_ligands* topo, int32_t n_pos
 
 gd_status surrogate(const gd_pocket* P, const gd_ligands* topo, int32_t n_poses, const int32_t* pose_lig,
                     const float* px, const float* py, const float* pz, const float* t, const float* q,
-                    const float* tau, int32_t tau_stride, const float* dF, hipStream_t s, float* F_out,
-                    float* dt_out, float* dq_out, float* dtau_out, const char* who) {
+                    const float* tau, int32_t tau_stride, const gd_bump_penalty* pb, const float* dF, hipStream_t s,
+                    float* F_out, float* dt_out, float* dq_out, float* dtau_out, const char* who) {
     if (n_poses > 0 && (!t || !q || (!tau && tau_stride > 0))) return fail(GD_ERR_ARG, "%s: null parameters", who);
     if (dF ? (!dt_out || !dq_out || (tau_stride > 0 && !dtau_out)) : !F_out)
         return fail(GD_ERR_ARG, "%s: null output", who);
@@ -59,11 +59,26 @@ gd_status surrogate(const gd_pocket* P, const gd_ligands* topo, int32_t n_poses,
     gd_status st = setup(P, topo, n_poses, pose_lig, px, py, pz, A, C, who);
     if (st != GD_OK) return st;
     if (tau_stride < C.rmax) return fail(GD_ERR_ARG, "%s: tau_stride %d < rotamers %d", who, tau_stride, C.rmax);
+    Penalty pen{};
+    TopoHost TH;
+    if (pb && pb->weight != 0.f) {
+        if (!(pb->weight > 0.f) || !std::isfinite(pb->weight) || !(pb->clash_dist >= 0.f) || pb->clash_dist > 100.f)
+            return fail(GD_ERR_ARG, "%s: bad bump penalty", who);
+        if ((st = prepare_topology(topo, pb->clash_min_bonds, TH)) != GD_OK) return st;
+        if (n_poses > 0) {
+            hipError_t e;
+            if ((e = A.put(TH.far_off, &pen.far_off)) != hipSuccess || (e = A.put(TH.n_far, &pen.n_far)) != hipSuccess ||
+                (e = A.put(TH.efar, &pen.efar)) != hipSuccess)
+                return hip_fail(e, who);
+        }
+        pen.w = pb->weight;
+        pen.cd2 = (float)((double)pb->clash_dist * (double)pb->clash_dist);
+    }
     if (n_poses == 0) return GD_OK;
     static const float zero = 0.f;
     const float* tau_ok = tau ? tau : &zero;
     hipError_t e = launch_surrogate(P->dev, C.T, C.X, n_poses, t, q, tau_ok, tau_stride, dF, F_out, dt_out, dq_out,
-                                    dtau_out, C.lmax, s);
+                                    dtau_out, pen, C.lmax, s);
     return e == hipSuccess ? GD_OK : hip_fail(e, who);
 }
 
@@ -151,20 +166,21 @@ extern "C" {
 
 gd_status gd_surrogate_fwd(const gd_pocket* pocket, const gd_ligands* topo, int32_t n_poses, const int32_t* pose_lig,
                            const float* px, const float* py, const float* pz, const float* t, const float* q,
-                           const float* tau, int32_t tau_stride, void* stream, float* F_out) {
+                           const float* tau, int32_t tau_stride, const gd_bump_penalty* penalty, void* stream,
+                           float* F_out) {
     clear_error();
-    return surrogate(pocket, topo, n_poses, pose_lig, px, py, pz, t, q, tau, tau_stride, nullptr, (hipStream_t)stream,
-                     F_out, nullptr, nullptr, nullptr, "gd_surrogate_fwd");
+    return surrogate(pocket, topo, n_poses, pose_lig, px, py, pz, t, q, tau, tau_stride, penalty, nullptr,
+                     (hipStream_t)stream, F_out, nullptr, nullptr, nullptr, "gd_surrogate_fwd");
 }
 
 gd_status gd_surrogate_bwd(const gd_pocket* pocket, const gd_ligands* topo, int32_t n_poses, const int32_t* pose_lig,
                            const float* px, const float* py, const float* pz, const float* t, const float* q,
-                           const float* tau, int32_t tau_stride, const float* dF, void* stream, float* dt_out,
-                           float* dq_out, float* dtau_out) {
+                           const float* tau, int32_t tau_stride, const gd_bump_penalty* penalty, const float* dF,
+                           void* stream, float* dt_out, float* dq_out, float* dtau_out) {
     clear_error();
     if (!dF) return fail(GD_ERR_ARG, "gd_surrogate_bwd: null dF");
-    return surrogate(pocket, topo, n_poses, pose_lig, px, py, pz, t, q, tau, tau_stride, dF, (hipStream_t)stream,
-                     nullptr, dt_out, dq_out, dtau_out, "gd_surrogate_bwd");
+    return surrogate(pocket, topo, n_poses, pose_lig, px, py, pz, t, q, tau, tau_stride, penalty, dF,
+                     (hipStream_t)stream, nullptr, dt_out, dq_out, dtau_out, "gd_surrogate_bwd");
 }
 
 gd_status gd_refine(const gd_pocket* pocket, const gd_ligands* topo, int32_t n_poses, const int32_t* pose_lig,

@@ -79,7 +79,10 @@ def _params(n, nrmax, seed):
 
 
 @gpu
-def test_surrogate_value_and_gradient(g, setup):
+@pytest.mark.parametrize("pen", [{}, dict(clash_weight=0.25, clash_dist=4.5, clash_min_bonds=4)])
+def test_surrogate_value_and_gradient(g, setup, pen):
+    """pen: the clash-penalised surrogate (a wide bump distance puts many far
+    pairs in the penalty band)."""
     import torch
     S = setup
     ligs, pl = S["ligs"], S["pose_lig"]
@@ -87,17 +90,17 @@ def test_surrogate_value_and_gradient(g, setup):
     nrmax = max(ligs.n_rot(i) for i in range(ligs.n))
     t, q, tau = _params(n, nrmax, 1)
     T = lambda a: torch.tensor(a, device="cuda")
-    F = g.surrogate_fwd(S["P"], ligs, pl, S["px"], S["py"], S["pz"], T(t), T(q), T(tau)).cpu().numpy()
+    F = g.surrogate_fwd(S["P"], ligs, pl, S["px"], S["py"], S["pz"], T(t), T(q), T(tau), **pen).cpu().numpy()
     dF = np.linspace(0.5, 1.5, n).astype(np.float32)
     dt, dq, dtau = (x.cpu().numpy() for x in
-                    g.surrogate_bwd(S["P"], ligs, pl, S["px"], S["py"], S["pz"], T(t), T(q), T(tau), T(dF)))
+                    g.surrogate_bwd(S["P"], ligs, pl, S["px"], S["py"], S["pz"], T(t), T(q), T(tau), T(dF), **pen))
     bad = 0
     for p in range(n):
         lig = ligs.ligand(pl[p])
         nr = ligs.n_rot(pl[p])
         X0 = S["rows"][p].astype(np.float64)
         prm = np.concatenate([t[p], q[p], tau[p, :nr]]).astype(np.float64)
-        Fo, go, _ = S["B"].surrogate(lig, X0, prm)
+        Fo, go, _ = S["B"].surrogate(lig, X0, prm, **pen)
         assert abs(F[p] - Fo) <= 1e-4 * max(abs(Fo), 1.0), (p, F[p], Fo)
         gg = np.concatenate([dt[p], dq[p], dtau[p, :nr]]) / dF[p]
         for sl in (slice(0, 3), slice(3, 7), slice(7, 7 + nr)):
@@ -123,6 +126,16 @@ def test_autograd_function(g, setup):
     dt, dq, dtau = g.surrogate_bwd(S["P"], ligs, pl, S["px"], S["py"], S["pz"], t.detach(), q.detach(), tau.detach(),
                                    torch.ones(n, device="cuda"))
     assert torch.equal(t.grad, dt) and torch.equal(q.grad, dq) and torch.equal(tau.grad, dtau)
+    # the penalised surrogate through the same autograd function
+    pen = dict(clash_weight=0.25, clash_dist=4.5, clash_min_bonds=4)
+    for v in (t, q, tau):
+        v.grad = None
+    Fp = g.SurrogateScore.apply(t, q, tau, spec + (pen,))
+    Fp.sum().backward()
+    dt, dq, dtau = g.surrogate_bwd(S["P"], ligs, pl, S["px"], S["py"], S["pz"], t.detach(), q.detach(), tau.detach(),
+                                   torch.ones(n, device="cuda"), **pen)
+    assert torch.equal(t.grad, dt) and torch.equal(q.grad, dq) and torch.equal(tau.grad, dtau)
+    assert bool((Fp <= F).all())  # the penalty only subtracts
 
 
 @gpu
