@@ -72,7 +72,8 @@ __device__ __forceinline__ float rho_tri(const PocketDev& P, float x, float y, f
         int jx = ix + (c & 1), jy = iy + ((c >> 1) & 1), jz = iz + (c >> 2);
         bool in = (unsigned)jx < (unsigned)P.bdim[0] && (unsigned)jy < (unsigned)P.bdim[1] &&
                   (unsigned)jz < (unsigned)P.bdim[2];
-        r[c] = in ? P.rho[((size_t)jz * P.bdim[1] + jy) * P.bdim[0] + jx] : 0.f;
+        // at most 1024 nodes per axis (checked at pocket creation): the index fits 32 bits
+        r[c] = in ? P.rho[(jz * P.bdim[1] + jy) * P.bdim[0] + jx] : 0.f;
     }
     float ax = 1.f - fx, ay = 1.f - fy, az = 1.f - fz;
     // interpolate along x, then y, then z
