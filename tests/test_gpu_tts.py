@@ -16,7 +16,7 @@ def g():
 
 @gpu
 def test_campaign_fit_and_choice(g):
-    from paper_1901_06363_amd import dse, tts
+    from paper_1901_06363_amd import tts
     pockets = []
     for k in (0, 1):
         pts = configs.GRID.pocket_points(k)
@@ -35,8 +35,7 @@ def test_campaign_fit_and_choice(g):
     assert set(models) == {tts.key(c) for c in cfgs}
     for m in models.values():
         assert np.isfinite(m.r2) and m.n == 10
-        # the fit reproduces its own observations on average within a factor of two
-        pred = [m.per_ligand(r["p"], r["a"], r["r"]) for r in recs if tts.key(r) == tts.key(cfgs[0])]
+    # the fit reproduces its own observations on average within a factor of two
     obs = [r["ms"] / r["nu"] for r in recs if tts.key(r) == tts.key(cfgs[0])]
     m0 = models[tts.key(cfgs[0])]
     pred = [m0.per_ligand(r["p"], r["a"], r["r"]) for r in recs if tts.key(r) == tts.key(cfgs[0])]
