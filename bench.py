@@ -260,7 +260,7 @@ def tts_leg(gd, torch, np, dse_ligands=5000, records_path=None):
     dl = d.ligands(0, dse_ligands)
     drecs = dse.explore(gd.Pocket(d.pocket_points(), 0.5, d.pad), dl, d.quaternions(), space="full", top_k=1)
     deg = {tts.key(r): r["degradation"] for r in drecs}
-    bkey = tts.key(dse.BASELINE | dict(lp=45))
+    bkey = tts.key(dse.BASE_KNOBS | dict(lp=45))
     p_d, (a_d, r_d) = len(d.pocket_points()), tts.ligand_features(dl)
     tb = models[bkey].per_ligand(p_d, a_d, r_d)
 
@@ -290,7 +290,7 @@ def peaks_leg(gd, torch, np, n_lig=2000, step=1):
     w = configs.DSE
     ligs = w.ligands(0, n_lig)
     P = gd.Pocket(w.pocket_points(), 0.5, w.pad)
-    b = dse.BASELINE
+    b = dse.BASE_KNOBS
     B = gd.Batch(P, ligs, w.quaternions(), hp=b["hp"], lp=b["lp"], threshold=b["threshold"],
                  repetitions=b["repetitions"], refine=b["refine"], top_k=1)
     res = B.dock(gd.BATCHED)
@@ -380,7 +380,7 @@ def main():
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (ligand batches shard trivially "
-              "across GPUs, see DESIGN.md); got --gpus %d" % args.gpus, file=sys.stderr)
+              "across GPUs); got --gpus %d" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -362,7 +362,7 @@ gd_status gd_surrogate_bwd(const gd_pocket* pocket, const gd_ligands* topo, int3
                            void* stream, float* dt_out, float* dq_out, float* dtau_out);
 
 /*
- * Refine poses by `steps` ascent steps on F, then judge each refined pose with
+ * Refine poses by `steps` ascent steps on F, then rate each refined pose with
  * the exact discrete score: accepted iff bump-free and S_refined < S_input.
  * px/py/pz are updated in place with the refined pose where accepted (the
  * input pose is kept otherwise).  Outputs (device): F_out[n_poses] surrogate

@@ -655,7 +655,7 @@ int orc_apply_torsions(int l, int nb, const int* bonds, int nr, const int* rot, 
 /* ------------------------------------------------------------------------ */
 /* Smoothed surrogate for pose refinement (a differentiable stand-in for the
  * overlap score, used only to propose refined poses; every refined pose is
- * judged again with the exact lattice score S and the bump rule).
+ * scored again with the exact lattice score S and the bump rule).
  *
  *   rho(g)  = sum_j exp(-|g - P_j|^2 / (2 sigma^2)) over points with
  *             |g - P_j| <= cutoff, at lattice nodes g = bh * (i, j, k)

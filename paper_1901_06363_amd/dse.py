@@ -35,7 +35,7 @@ from ._ops import overlap_continuous
 FLAT = dict(hp=[1, 2, 3, 5, 10, 15, 45, 60], repetitions=[1, 2, 3])
 FULL = dict(hp=[1, 2, 3, 5], lp=[45, 90], threshold=[0.0, 0.3, 0.6, 0.8], repetitions=[1, 2, 3],
             refine=[True, False])
-BASELINE = dict(hp=1, lp=1, threshold=0.0, repetitions=3, refine=False)
+BASE_KNOBS = dict(hp=1, lp=1, threshold=0.0, repetitions=3, refine=False)
 SPACES = {"flat": FLAT, "full": FULL}
 
 
@@ -49,7 +49,7 @@ def configurations(space) -> list:
     for vals in itertools.product(*(space[n] for n in names)):
         k = dict(zip(names, vals))
         cfg = dict(hp=k["hp"], lp=k.get("lp", k["hp"]), threshold=float(k.get("threshold", 0.0)),
-                   repetitions=k.get("repetitions", BASELINE["repetitions"]), refine=bool(k.get("refine", False)))
+                   repetitions=k.get("repetitions", BASE_KNOBS["repetitions"]), refine=bool(k.get("refine", False)))
         out.append(cfg)
     return out
 
@@ -57,7 +57,7 @@ def configurations(space) -> list:
 def is_baseline(cfg) -> bool:
     """The most precise configuration: hp 1, threshold 0, 3 repetitions, no
     refinement (any low-precision step: with threshold 0 it is never used)."""
-    return (cfg["hp"] == BASELINE["hp"] and cfg["threshold"] == 0.0 and cfg["repetitions"] == BASELINE["repetitions"]
+    return (cfg["hp"] == BASE_KNOBS["hp"] and cfg["threshold"] == 0.0 and cfg["repetitions"] == BASE_KNOBS["repetitions"]
             and not cfg["refine"])
 
 
@@ -166,7 +166,7 @@ def explore(pocket, ligands, quats, space="full", top_k=1, frac=0.01, include_ba
     pareto (on the front of throughput vs degradation)."""
     cfgs = configurations(space)
     if include_baseline and not any(is_baseline(c) for c in cfgs):
-        cfgs = [dict(BASELINE)] + cfgs
+        cfgs = [dict(BASE_KNOBS)] + cfgs
     recs = []
     kw = {k: v for k, v in score_kw.items() if k in ("clash_dist", "clash_min_bonds")}
     for i, (c, B) in enumerate(prepared_batches(pocket, ligands, quats, cfgs, top_k=top_k, **kw)):

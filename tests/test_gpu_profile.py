@@ -81,7 +81,7 @@ def test_profile_peaks_workload_sampled(g):
     P, O = g.Pocket(pts, 0.5, w.pad), oracle.OraclePocket(pts, 0.5)
     ligs = w.ligands(0, 2000)
     q = w.quaternions()
-    b = dse.BASELINE
+    b = dse.BASE_KNOBS
     B = g.Batch(P, ligs, q, top_k=1, **b)
     res = B.dock(g.BATCHED)
     S, f, sz = g.sweep_profile(P, B, res, step=1)

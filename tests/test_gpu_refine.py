@@ -3,7 +3,7 @@
 Bar: density nodes within FP32 rounding of the FP64 definition; surrogate
 values within 1e-4 and gradients within 1e-3 (relative, per parameter
 group) of the oracle's analytic gradient at the same parameters; the
-refined pose is judged with the exact score, which must match the oracle's
+refined pose is re-scored with the exact score, which must match the oracle's
 score of the returned FP32 pose bit for bit, and the acceptance rule is
 checked pose by pose.
 """

@@ -496,7 +496,7 @@ def test_refinement_matches_independent_two_level_search(seed, hp):
 @pytest.mark.parametrize("seed", range(3))
 def test_sweep_feasibility_tests_only_straddling_pairs(seed):
     """With a clash distance large enough that pairs inside one fragment
-    already clash, a sweep is still judged only on the pairs that the rotation
+    already clash, a sweep is still tested only on the pairs that the rotation
     moves against each other (pairs within a side keep their distance)."""
     lig = _tiny_case(500 + 10 * seed, 18, 1)
     P, ref = _setup_tiny(lig)
