@@ -303,26 +303,14 @@ __device__ float surrogate_eval(const PocketDev& P, const TreeDev& T, const Pose
         gq[2] = 2.f * (w * ty + (tz * x - tx * z)) * in;
         gq[3] = 2.f * (w * tz + (tx * y - ty * x)) * in;
     }
-    // torsions, in the final frame: per rotamer the moving atoms' sums of
-    // x x g and g about the pivot and axis of the forward pass, carried into
-    // the final frame
+    // torsions, in the final frame: K . sum over the moving atoms of
+    // (x_i - A) x g_i, with the pivot A and axis K of the forward pass carried
+    // into the final frame.  Per atom that is K . (x_i x g_i) - (K x A) . g_i,
+    // so each lane forms its atoms' scalar terms and one wave sum per rotamer
+    // finishes the job.
     wave_sync();
     for (int e = 0; e < S.nr; e++) {
         const int4 te = T.tree[S.tree0 + e];
-        float sxg[3] = {0, 0, 0}, sg[3] = {0, 0, 0};
-#pragma unroll
-        for (int k = 0; k < kSlots; k++) {
-            if ((S.mv[k] >> e) & 1) {
-                for (int a = 0; a < 3; a++) {
-                    sxg[a] += xg[k][a];
-                    sg[a] += g[k][a];
-                }
-            }
-        }
-        for (int a = 0; a < 3; a++) {
-            sxg[a] = wsum(sxg[a]);
-            sg[a] = wsum(sg[a]);
-        }
         const float* axe = axes + 6 * te.z;
         const float d0 = axe[0] - S.c0[0], d1 = axe[1] - S.c0[1], d2 = axe[2] - S.c0[2];
         const float ax = (Rq[0] * d0 + Rq[1] * d1 + Rq[2] * d2) + S.c0[0] + t[0];
@@ -331,11 +319,16 @@ __device__ float surrogate_eval(const PocketDev& P, const TreeDev& T, const Pose
         const float kx = Rq[0] * axe[3] + Rq[1] * axe[4] + Rq[2] * axe[5];
         const float ky = Rq[3] * axe[3] + Rq[4] * axe[4] + Rq[5] * axe[5];
         const float kz = Rq[6] * axe[3] + Rq[7] * axe[4] + Rq[8] * axe[5];
-        // sum (x_i - A) x g_i = sum x_i x g_i - A x sum g_i
-        float tx = sxg[0] - (ay * sg[2] - az * sg[1]);
-        float ty = sxg[1] - (az * sg[0] - ax * sg[2]);
-        float tz = sxg[2] - (ax * sg[1] - ay * sg[0]);
-        if (lane == 0) gtau[te.z] = kx * tx + ky * ty + kz * tz;
+        const float cx = ky * az - kz * ay, cy = kz * ax - kx * az, cz = kx * ay - ky * ax;  // K x A
+        float v = 0.f;
+#pragma unroll
+        for (int k = 0; k < kSlots; k++) {
+            const float term = (kx * xg[k][0] + ky * xg[k][1] + kz * xg[k][2]) -
+                               (cx * g[k][0] + cy * g[k][1] + cz * g[k][2]);
+            v += ((S.mv[k] >> e) & 1) ? term : 0.f;
+        }
+        v = wsum(v);
+        if (lane == 0) gtau[te.z] = v;
     }
     wave_sync();
     return F;
