@@ -178,6 +178,104 @@ def test_ascent_increases_the_surrogate():
 
 
 # --------------------------------------------------------------------------
+# The ascent's step rule, pinned by its properties: given the gradient g at
+# the current parameters (itself pinned by central differences above), one
+# step moves t by lr_t g_t shortened along its own direction to length
+# max_dt, puts q on the unit sphere in the direction of q + lr_q g_q, and
+# moves each tau_b by lr_tau g_b clamped to [-max_dtau, max_dtau] on its own;
+# a zero learning rate leaves every parameter and the pose unchanged.
+
+def _f32(v):
+    return float(np.float32(v))
+
+
+def _step_cases():
+    pts = configs.SINGLE.pocket_points()
+    P, B = _blur(pts)
+    rng = np.random.default_rng(21)
+    for i in range(6):
+        lig = synth.ligands(4, 80 + i, 1, 20, 48, 4, 10).ligand(0)
+        X0 = _pose(lig, pts.mean(0).astype(np.float64) + rng.normal(0, 1.2, 3))
+        nr = len(lig["rot"])
+        p0 = np.concatenate([[0, 0, 0, 1, 0, 0, 0], np.zeros(nr)])
+        yield B, lig, X0, p0
+
+
+def test_ascent_zero_rate_is_the_identity():
+    for B, lig, X0, p0 in _step_cases():
+        F0, _, _ = B.surrogate(lig, X0, p0, want_grad=False)
+        prm, X, F = B.refine(lig, X0, steps=7, lr_t=0.0, lr_q=0.0, lr_tau=0.0)
+        assert np.array_equal(prm, p0)
+        assert np.allclose(X, X0, rtol=0, atol=1e-12)
+        assert F == pytest.approx(F0, rel=1e-14, abs=1e-300)
+
+
+def test_ascent_translation_is_norm_clipped():
+    n_clip = n_free = 0
+    for B, lig, X0, p0 in _step_cases():
+        _, g, _ = B.surrogate(lig, X0, p0)
+        gt = g[:3]
+        assert np.linalg.norm(gt) > 0
+        # large rate: the step has length max_dt and the direction of g_t (a
+        # per-component clip would bend it towards the diagonal)
+        for lr_t, max_dt in ((10.0, 0.05), (1e-4, 100.0)):
+            prm, _, _ = B.refine(lig, X0, steps=1, lr_t=lr_t, lr_q=0.0, lr_tau=0.0, max_dt=max_dt, max_dtau=0.0)
+            d = prm[:3]
+            want = _f32(lr_t) * gt
+            if np.linalg.norm(want) > _f32(max_dt):
+                n_clip += 1
+                assert np.linalg.norm(d) == pytest.approx(_f32(max_dt), rel=1e-12)
+                assert np.allclose(d / np.linalg.norm(d), gt / np.linalg.norm(gt), rtol=0, atol=1e-12)
+            else:
+                n_free += 1
+                assert np.allclose(d, want, rtol=1e-12, atol=1e-18)
+            assert np.array_equal(prm[3:], p0[3:])
+        # every step of a longer clipped run has length max_dt
+        prev = None
+        for k in range(1, 4):
+            prm, _, _ = B.refine(lig, X0, steps=k, lr_t=10.0, lr_q=0.0, lr_tau=0.0, max_dt=0.05, max_dtau=0.0)
+            step = prm[:3] - (prev if prev is not None else 0.0)
+            assert np.linalg.norm(step) == pytest.approx(_f32(0.05), rel=1e-9)
+            prev = prm[:3].copy()
+    assert n_clip == 6 and n_free == 6
+
+
+def test_ascent_quaternion_is_renormalised():
+    for B, lig, X0, p0 in _step_cases():
+        _, g, _ = B.surrogate(lig, X0, p0)
+        lr = 0.05
+        prm, _, _ = B.refine(lig, X0, steps=1, lr_t=0.0, lr_q=lr, lr_tau=0.0, max_dt=0.0, max_dtau=0.0)
+        q = p0[3:7] + _f32(lr) * g[3:7]
+        assert np.linalg.norm(q) > 1 + 1e-9  # the tangent step leaves the sphere
+        assert np.allclose(prm[3:7], q / np.linalg.norm(q), rtol=0, atol=1e-14)
+        for k in range(1, 5):
+            prm, X, _ = B.refine(lig, X0, steps=k, lr_t=0.0, lr_q=lr, lr_tau=0.0, max_dt=0.0, max_dtau=0.0)
+            assert abs(np.linalg.norm(prm[3:7]) - 1.0) < 1e-14
+            # a pure rotation about the centroid: distances to it are kept
+            c0 = X0.mean(0)
+            assert np.allclose(np.linalg.norm(X - c0, axis=1), np.linalg.norm(X0 - c0, axis=1), atol=1e-10)
+
+
+def test_ascent_torsions_are_clamped_one_by_one():
+    n_clamped = n_free = 0
+    for B, lig, X0, p0 in _step_cases():
+        _, g, _ = B.surrogate(lig, X0, p0)
+        gtau = g[7:]
+        lr = 1.0
+        # a cap between the smallest and the largest |lr g_b|: some clamp, some do not
+        a = np.sort(np.abs(_f32(lr) * gtau[gtau != 0]))
+        assert len(a) >= 2
+        cap = _f32(0.5 * (a[0] + a[-1]))
+        prm, _, _ = B.refine(lig, X0, steps=1, lr_t=0.0, lr_q=0.0, lr_tau=lr, max_dt=0.0, max_dtau=cap)
+        want = np.clip(_f32(lr) * gtau, -cap, cap)
+        assert np.allclose(prm[7:], want, rtol=1e-12, atol=0)
+        n_clamped += int(np.sum(np.abs(_f32(lr) * gtau) > cap))
+        n_free += int(np.sum(np.abs(_f32(lr) * gtau) < cap))
+        assert np.array_equal(prm[:7], p0[:7])
+    assert n_clamped >= 6 and n_free >= 6
+
+
+# --------------------------------------------------------------------------
 # Clash-penalised surrogate: F - lam sum_{far pairs, d < c} (c^2 - d^2)^2
 
 def _fd_grad_pen(B, lig, X0, prm, h, **kw):
