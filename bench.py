@@ -1,20 +1,27 @@
 #!/usr/bin/env python
 """Benchmark of the docking hot path on one MI355X.
 
-Workload (the screening configuration): 10,000 synthetic ligands (20-80 heavy
-atoms, 2-12 rotatable bonds) x one 4,000-point ellipsoid pocket (12/9/7 A,
-0.5 A grid), 512 rigid orientations, 15-degree torsion steps, one repetition,
-top-8 poses per ligand.  One step = one batched docking call over the whole
-batch: queue reset, the persistent docking kernel (placement, greedy sweeps,
-scoring, bump tests, FP64 commits, endpoint), top-k reduction and replay of
-the selected poses.  The batch is prepared (validated, topology and work queue
-built, copied to HBM) before the timed region.
+Headline workload (the large library): 1,000,000 synthetic ligands (15-120
+heavy atoms, 0-16 rotatable bonds, 5 % with a rigid 3-6 ring) against one
+10,000-point ellipsoid pocket (16/12/9 A, 0.5 A grid), 1024 rigid
+orientations, 10-degree torsion steps, one repetition, top-8 poses per
+ligand, streamed in chunks of 65,536 ligands.  One step = one chunk: queue
+reset, the persistent docking kernel (placement, greedy sweeps, scoring, bump
+tests, FP64 commits, endpoint), top-k reduction, replay of the selected poses,
+then 50 ascent steps of the density-surrogate refinement of the chunk's top-8
+poses with exact rescoring and acceptance (on a second stream, overlapping the
+next chunk's docking).  Step s docks chunk s mod 16, so warm-up plus timed
+steps cover the whole library.  Chunks are generated and prepared (validated,
+topology and work queue built, copied to HBM) on a host thread while earlier
+chunks dock; the timed steps start only once every chunk is resident in HBM.
 
 Prints one JSON line: poses scored per second (the knob-determined candidate
-count; every candidate is scored and bump-tested), ligands per second, the
-per-ligand-launch form (one launch per ligand) over the same ligands with a
-check that both forms return identical results, the roofline of the docking
-kernel and the CPU oracle baseline.
+count; every candidate is scored and bump-tested), ligands and atoms per
+second, the per-ligand-launch form on one chunk with a check that both forms
+return identical results, the docking kernel's roofline, a wall-clock rate of
+a true stream (generation, preparation, upload, docking, refinement and host
+copies of chunks), the CPU oracle baseline (one core and all cores), and the
+screening workload (10,000 ligands x 4,000-point pocket) as secondary context.
 """
 from __future__ import annotations
 
@@ -36,6 +43,7 @@ KERNEL_SOURCES = ["dock.hip", "device_common.h", "gd_internal.h"]
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "dock_persistent_kernel.screen.traffic.md")
 OVERLAP_SOURCES = ["overlap.hip", "gd_internal.h"]
 OVERLAP_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "overlap_min_kernel.screen_top8.traffic.md")
+LARGE_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "dock_persistent_kernel.large.traffic.md")
 
 
 def kernel_fingerprint(sources=None):
@@ -69,21 +77,65 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w, ligs, q, n_sample):
-    """The FP64 oracle, single-threaded, on the first n_sample ligands."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_share():
+    """Host cores this process may use, capped at the 16 a one-GPU machine grants."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def oracle_shard(task):
+    """Dock ligands [first, first + count) of a workload with the FP64 oracle
+    (one process, one core); returns (candidate poses, seconds)."""
+    name, first, count = task
     import oracle
-    pts = w.pocket_points()
-    O = oracle.OraclePocket(pts, 0.5)
+    from synth import configs
+    w = configs.ALL[name]
+    O = oracle.OraclePocket(w.pocket_points(), 0.5)
     kn = oracle.knobs(**w.knob_dict())
+    q = w.quaternions()
+    ligs = w.ligands(first, count)
     t0 = time.perf_counter()
     poses = 0
-    for i in range(n_sample):
-        r = oracle.dock(O, ligs.ligand(i), kn, q, want_xyz=False)
-        poses += r.n_cand
-    dt = time.perf_counter() - t0
-    return dict(value=poses / dt, unit="poses/s", cores=1, kind="oracle",
-                sample="first %d ligands of the workload, all %d orientations, %d candidate poses in %.1f s"
-                       % (n_sample, len(q), poses, dt))
+    for i in range(count):
+        poses += oracle.dock(O, ligs.ligand(i), kn, q, want_xyz=False).n_cand
+    return poses, time.perf_counter() - t0
+
+
+def cpu_baseline(pool, workers, name, first, n_single, n_per_worker):
+    """The FP64 oracle as it stands on the host cores: one process on the
+    ligands [first, first + n_single), then `workers` processes at once on
+    disjoint shards of n_per_worker ligands each (the paper's master/slave
+    data parallelism over ligands).  The pool is forked before the GPU is
+    touched; its processes only run the CPU oracle."""
+    poses1, dt1 = pool.apply(oracle_shard, ((name, first, n_single),))
+    shards = [(name, first + n_single + k * n_per_worker, n_per_worker) for k in range(workers)]
+    t0 = time.perf_counter()
+    res = pool.map(oracle_shard, shards, chunksize=1)
+    wall = time.perf_counter() - t0
+    poses_all = sum(p for p, _ in res)
+    return dict(value=poses_all / wall, unit="poses/s", cores=workers, kind="oracle",
+                sample="%s workload: %d oracle processes at once, each on its own %d ligands (ligands %d-%d), all "
+                       "orientations, %d candidate poses in %.1f s of wall clock" % (
+                           name, workers, n_per_worker, first + n_single, first + n_single + workers * n_per_worker - 1,
+                           poses_all, wall),
+                per_core=dict(value=poses1 / dt1, unit="poses/s", cores=1,
+                              sample="ligands %d-%d of the %s workload, %d candidate poses in %.1f s" % (
+                                  first, first + n_single - 1, name, poses1, dt1)),
+                cpu_model=cpu_model(), nproc=os.cpu_count(), host_cores_usable=cpu_share())
 
 
 def refine_leg(gd, torch, np, n_lig):
@@ -315,7 +367,7 @@ def peaks_leg(gd, torch, np, n_lig=2000, step=1):
                 host_analysis_s=time.perf_counter() - t0, summary=summ)
 
 
-def large_leg(gd, torch, n_chunks):
+def large_leg(gd, torch, n_chunks, tiling=None):
     """The large library streamed through the persistent kernel in chunks of
     65,536 ligands (host preparation of the next chunk overlaps docking), with
     the top-8 poses of every chunk refined and re-scored."""
@@ -331,7 +383,8 @@ def large_leg(gd, torch, n_chunks):
     dock_ms = 0.0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for item in screen(P, w.ligands, n, w.quaternions(), chunk=w.chunk, refine_poses=ropt, hp=w.hp, top_k=w.top_k):
+    for item in screen(P, w.ligands, n, w.quaternions(), chunk=w.chunk, refine_poses=ropt, tiling=tiling, hp=w.hp,
+                       top_k=w.top_k):
         poses += item["poses"]
         atoms += int(item["ligands"].atom_off[-1])
         dock_ms += item["dock_ms"]
@@ -346,20 +399,334 @@ def large_leg(gd, torch, n_chunks):
                      "copies; dock_kernel_s is the docking kernels' share (HIP events)")
 
 
+def screen_leg(gd, torch, np, args, steps, warmup, n_lig=0, tiling=""):
+    """The screening workload: 10,000 ligands x 4,000-point pocket, 512
+    orientations, 15-degree steps, top-8; warm-up, then `steps` timed batched
+    docking calls of the resident batch, the per-ligand form on the same
+    ligands and the continuous Eq. 1 rescoring of the top-8 poses."""
+    from synth import configs
+    w = configs.SCREEN
+    n_lig = n_lig or w.n_ligands
+    t = time.perf_counter()
+    ligs = w.ligands(0, n_lig)
+    pts = w.pocket_points()
+    q = w.quaternions()
+    log("screen: inputs generated in %.1f s" % (time.perf_counter() - t))
+    P = gd.Pocket(pts, 0.5, w.pad)
+    t = time.perf_counter()
+    B = gd.Batch(P, ligs, q, hp=w.hp, top_k=w.top_k)
+    prep_s = time.perf_counter() - t
+    log("screen: batch prepared in %.2f s: %d ligands, %d poses per call" % (prep_s, B.n_ligands, B.poses_expected))
+    if tiling:
+        B.set_tiling(*[int(v) for v in tiling.split(",")])
+    if args.autotune:
+        log("screen: autotuned tiling", B.autotune(reps=1))
+    tiling = B.tiling()
+    out = B.alloc_outputs(want_angles=True, want_xyz=True)
+    for _ in range(warmup):
+        B.dock(gd.BATCHED, out)
+    torch.cuda.synchronize()
+    B.enable_timing(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        B.dock(gd.BATCHED, out)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kernel_ms = B.read_timing()
+    B.enable_timing(False)
+    host = out.host()
+    counters = host["counters"]
+    assert counters[0] == B.poses_expected, (counters[0], B.poses_expected)
+    k_ms = float(np.mean(kernel_ms))
+    log("screen: %d steps, %.1f ms/step, docking kernel %.1f ms" % (steps, dt * 1e3 / steps, k_ms))
+    per_lig = None
+    if not args.no_per_ligand:
+        rp = B.dock(gd.PER_LIGAND)
+        torch.cuda.synchronize()
+        tp0 = time.perf_counter()
+        rp = B.dock(gd.PER_LIGAND, rp)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - tp0
+        hp_ = rp.host()
+        same = all(np.array_equal(host[k], hp_[k]) for k in ("orient", "S", "clash", "angles", "xyz"))
+        per_lig = dict(ligands=n_lig, per_ligand_poses_per_s=B.poses_expected / tp, per_ligand_ligands_per_s=n_lig / tp,
+                       batched_poses_per_s=B.poses_expected * steps / dt, batched_over_per_ligand=tp / (dt / steps),
+                       results_identical=bool(same))
+        log("screen: per-ligand launches:", per_lig)
+    cont = None
+    if not args.no_continuous:
+        cont = continuous_leg(gd, torch, np, P, out, ligs, len(pts))
+        log("screen: continuous rescoring:", cont)
+    achieved = B.algo_flops / (k_ms * 1e-3) / 1e12
+    tr = measured_traffic() if n_lig == w.n_ligands else None
+    return dict(
+        workload="screen: %d ligands (20-80 atoms, 2-12 rotatable bonds) x 4,000-point pocket, 512 orientations, "
+                 "15-degree steps, 1 repetition, top-8" % n_lig,
+        ligands=n_lig, orientations=len(q), hp_step_deg=w.hp, poses_per_step=B.poses_expected, tiling=list(tiling),
+        grid_pad_A=w.pad, steps=steps, warmup=warmup, ms_per_step=dt * 1e3 / steps,
+        poses_per_s=B.poses_expected * steps / dt, ligands_per_s=n_lig * steps / dt,
+        atoms_per_s=B.n_atoms_total * steps / dt,
+        fallback_per_pose=float(counters[1]) / float(counters[0]), oob_lookups=int(counters[2]), prep_s=prep_s,
+        per_ligand=per_lig, continuous=cont,
+        roofline=dict(bound="alu", achieved=achieved, peak=FP32_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
+                      frac=achieved / FP32_VECTOR_PEAK_TFLOPS,
+                      traffic=(tr["fetch"] + tr["write"]) if tr else None,
+                      traffic_unit="HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                      kernel="dock_persistent_kernel", kernel_ms=k_ms, algo_flops_per_launch=B.algo_flops,
+                      algo_gather_bytes_per_launch=B.algo_bytes,
+                      gather_GBps=B.algo_bytes / (k_ms * 1e-3) / 1e9))
+
+
+class ChunkOutputs:
+    """Two sets of docking outputs sized for the largest chunk, viewed per
+    chunk: consecutive steps alternate sets so that one chunk's refinement
+    can read its poses while the next chunk docks."""
+
+    def __init__(self, gd, torch, n_max, k, reps, rmax, lmax):
+        dev = torch.device("cuda")
+        self.gd, self.k = gd, k
+        self.sets = [dict(recs=torch.empty(n_max * k * 6, dtype=torch.int32, device=dev),
+                          ang=torch.empty(n_max * k * reps * rmax * 2, dtype=torch.int16, device=dev),
+                          xyz=torch.empty(n_max * k * lmax * 3, dtype=torch.float32, device=dev),
+                          cnt=torch.zeros(4, dtype=torch.int64, device=dev)) for _ in range(2)]
+
+    def view(self, i, B):
+        s = self.sets[i]
+        n, k = B.n_ligands, B.top_k
+        recs = s["recs"][:n * k * 6].view(n * k, 6)
+        ang = s["ang"][:n * k * B.repetitions * B.max_rot * 2].view(n, k, B.repetitions, B.max_rot, 2)
+        xyz = s["xyz"][:n * k * B.max_atoms * 3].view(n, k, B.max_atoms, 3)
+        return self.gd.DockResult(recs, ang, xyz, s["cnt"], n, k)
+
+
+def large_headline(gd, torch, np, args):
+    """Headline: the large library, one chunk of 65,536 ligands per step (see
+    the module docstring)."""
+    import threading
+    from synth import configs
+    from paper_1901_06363_amd.stream import poses_from_topk
+    w = configs.LARGE
+    rx = configs.REFINE.extra
+    n_lib = args.large_ligands or w.n_ligands
+    chunk = args.chunk or w.chunk
+    starts = list(range(0, n_lib, chunk))
+    nch = len(starts)
+    ropt = dict(steps=rx["steps"], lr_t=rx["lr_t"], lr_q=rx["lr_q"], lr_tau=rx["lr_tau"], max_dt=rx["max_dt"],
+                max_dtau=rx["max_dtau"])
+    P = gd.Pocket(w.pocket_points(), 0.5, w.pad, blur_sigma=rx["blur_sigma"], blur_h=rx["blur_h"])
+    q = w.quaternions()
+    side = torch.cuda.Stream()
+    rstream = torch.cuda.Stream()
+    main = torch.cuda.current_stream()
+
+    # host thread: generate and prepare every chunk once, in order; they stay resident in HBM
+    slots = [None] * nch
+    ready = [threading.Event() for _ in range(nch)]
+    prep_s = [0.0] * nch
+    err = []
+
+    def producer():
+        try:
+            for i, first in enumerate(starts):
+                t = time.perf_counter()
+                ligs = w.ligands(first, min(chunk, n_lib - first))
+                slots[i] = gd.Batch(P, ligs, q, stream=side, hp=w.hp, top_k=w.top_k)
+                prep_s[i] = time.perf_counter() - t
+                ready[i].set()
+        except BaseException as e:  # re-raised by the consumer
+            err.append(e)
+            for ev in ready:
+                ev.set()
+
+    t_setup = time.perf_counter()
+    th = threading.Thread(target=producer, daemon=True)
+    th.start()
+
+    def batch(i):
+        ready[i].wait()
+        if err:
+            raise err[0]
+        return slots[i]
+
+    B0 = batch(0)
+    if args.tiling:
+        tiling = tuple(int(v) for v in args.tiling.split(","))
+    else:
+        tiling = B0.autotune(reps=1)
+    log("large: chunk 0 prepared in %.1f s, tiling %s (%s)" % (prep_s[0], tiling,
+                                                                "given" if args.tiling else "autotuned"))
+    lmax = max(w.lmax, B0.max_atoms)
+    outs = ChunkOutputs(gd, torch, chunk, w.top_k, B0.repetitions, 16 if w.bmax <= 16 else w.bmax, lmax)
+    n_steps = args.warmup + args.steps
+    cnt_hist = torch.zeros((n_steps, 4), dtype=torch.int64, device="cuda")
+    acc_hist = torch.zeros(n_steps, dtype=torch.int64, device="cuda")
+    ref_done = [None, None]
+    configured = set()
+    timed_batches = []
+    t0 = None
+
+    def refine_step(p):
+        # the top-8 refinement of a docked chunk on its own stream, enqueued
+        # after the next chunk's docking so that its host-side set-up (and any
+        # pageable upload, which waits for the stream) overlaps that docking
+        s_, B_, o_, ev_ = p
+        rstream.wait_event(ev_)
+        with torch.cuda.stream(rstream):
+            pose_lig, px, py, pz = poses_from_topk(o_, B_.lig)
+            r = gd.refine(P, B_.lig, pose_lig, px, py, pz, stream=rstream, **ropt)
+            acc_hist[s_] = r["accepted"].sum()
+        done = torch.cuda.Event()
+        done.record(rstream)
+        ref_done[s_ % 2] = done
+
+    pending = None
+    for s in range(n_steps):
+        if s == args.warmup:
+            if pending is not None:
+                refine_step(pending)
+                pending = None
+            th.join()  # every chunk resident before the timed region
+            if err:
+                raise err[0]
+            torch.cuda.synchronize()
+            for i in range(nch):
+                slots[i].read_timing()  # drop the warm-up durations
+            t0 = time.perf_counter()
+            log("large: %d warm-up steps done, all %d chunks resident (setup %.1f s)" % (
+                args.warmup, nch, t0 - t_setup))
+        c = s % nch
+        B = batch(c)
+        if c not in configured:
+            B.set_tiling(*tiling)
+            B.enable_timing(True)
+            configured.add(c)
+        if B.max_atoms > lmax or B.max_rot > 16:
+            raise RuntimeError("chunk %d exceeds the output buffers" % c)
+        o = outs.view(s % 2, B)
+        if ref_done[s % 2] is not None:
+            main.wait_event(ref_done[s % 2])  # the refinement two steps back read this output set
+        B.dock(gd.BATCHED, o)
+        cnt_hist[s].copy_(o.counters)
+        ev = torch.cuda.Event()
+        ev.record(main)
+        if pending is not None:
+            refine_step(pending)
+        pending = (s, B, o, ev)
+        if t0 is not None:
+            timed_batches.append(B)
+        if s < args.warmup or (s - args.warmup) % 4 == 3:
+            log("large: step %d (chunk %d) enqueued, %.1f s" % (s, c, time.perf_counter() - t_setup))
+    refine_step(pending)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kms = {}
+    for i in range(nch):
+        kms[i] = slots[i].read_timing()
+    cnt = cnt_hist.cpu().numpy()
+    acc = acc_hist.cpu().numpy()
+    poses = lig_n = atoms = 0
+    flops = 0.0
+    kernel_ms = []
+    for j, B in enumerate(timed_batches):
+        s = args.warmup + j
+        assert cnt[s][0] == B.poses_expected, (s, cnt[s][0], B.poses_expected)
+        poses += B.poses_expected
+        lig_n += B.n_ligands
+        atoms += B.n_atoms_total
+        flops += B.algo_flops
+    for i, v in kms.items():
+        kernel_ms.extend(v)
+    k_s = sum(kernel_ms) * 1e-3
+    fallbacks = int(cnt[args.warmup:, 1].sum())
+    log("large: %d timed steps in %.1f s (%.0f ms/step), docking kernels %.1f s" % (
+        args.steps, dt, dt * 1e3 / args.steps, k_s))
+
+    # per-ligand launches against the batched form on one chunk (or a sample of it)
+    per_lig = None
+    if not args.no_per_ligand:
+        ns = min(args.per_ligand_sample or B0.n_ligands, B0.n_ligands)
+        Bs = B0 if ns == B0.n_ligands else gd.Batch(P, w.ligands(0, ns), q, hp=w.hp, top_k=w.top_k)
+        Bs.set_tiling(*tiling)
+        rb = Bs.dock(gd.BATCHED)
+        torch.cuda.synchronize()
+        tb0 = time.perf_counter()
+        rb = Bs.dock(gd.BATCHED, rb)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - tb0
+        hb = rb.host()
+        del rb
+        tp0 = time.perf_counter()
+        rp = Bs.dock(gd.PER_LIGAND)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - tp0
+        hp_ = rp.host()
+        del rp
+        same = all(np.array_equal(hb[k], hp_[k]) for k in ("orient", "S", "clash", "angles", "xyz"))
+        per_lig = dict(ligands=ns, chunk=0, per_ligand_poses_per_s=Bs.poses_expected / tp,
+                       per_ligand_ligands_per_s=ns / tp, batched_poses_per_s=Bs.poses_expected / tb,
+                       batched_over_per_ligand=tp / tb, results_identical=bool(same),
+                       note="one docking call each (batched: persistent kernel, top-k and replay; per-ligand: one "
+                            "launch per ligand, then top-k and replay), wall clock between synchronisations")
+        log("large: per-ligand launches:", per_lig)
+        del Bs
+    lib_poses = sum(slots[i].poses_expected for i in range(nch))
+    lib_flops = sum(slots[i].algo_flops for i in range(nch))
+    n_launch = len(kernel_ms)
+    n_timed = len(timed_batches)
+    torch.cuda.synchronize()
+    del slots, outs, timed_batches, B0, B, o, pending
+    torch.cuda.empty_cache()
+
+    achieved = flops / k_s / 1e12
+    tr = measured_traffic(LARGE_TRAFFIC_PROFILE) if n_lib == w.n_ligands and chunk == w.chunk else None
+    return dict(
+        value=poses / dt, ms_per_step=dt * 1e3 / args.steps,
+        config=dict(workload="large: %d ligands (15-120 atoms, 0-16 rotatable bonds, 5%% with a rigid 3-6 ring) x "
+                             "10,000-point pocket (16/12/9 A), 1024 orientations, 10-degree steps, 1 repetition, "
+                             "chunks of %d ligands, top-8 poses refined (50 ascent steps) and re-scored" % (n_lib, chunk),
+                    ligands=n_lib, chunk=chunk, chunks=nch, orientations=len(q), hp_step_deg=w.hp, top_k=w.top_k,
+                    poses_per_library=lib_poses, tiling=list(tiling), grid_pad_A=w.pad,
+                    step="one chunk: dock + top-k + replay + top-8 refinement and exact rescoring"),
+        ligands_per_s=lig_n / dt, atoms_per_s=atoms / dt, poses_timed=poses,
+        kernel=dict(docking_kernel_s=k_s, poses_per_s=poses / k_s, ligands_per_s=lig_n / k_s,
+                    note="docking-kernel time only (HIP events on its stream), summed over the timed steps"),
+        refined_poses_accepted_timed=int(acc[args.warmup:].sum()),
+        fallback_per_pose=fallbacks / max(poses, 1),
+        prep=dict(per_chunk_s=prep_s, setup_s=(t0 - t_setup),
+                  note="generation + validation + topology + upload of each chunk on a host thread, overlapping the "
+                       "warm-up steps"),
+        per_ligand=per_lig,
+        roofline=dict(bound="alu", achieved=achieved, peak=FP32_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
+                      frac=achieved / FP32_VECTOR_PEAK_TFLOPS,
+                      traffic=(tr["fetch"] + tr["write"]) if tr else None,
+                      traffic_unit="HBM bytes per launch of one full chunk (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                                   "copy-calibrated)",
+                      kernel="dock_persistent_kernel", kernel_ms=1e3 * k_s / n_launch,
+                      algo_flops_per_launch=flops / n_timed, library_algo_flops=lib_flops))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20, help="timed steps (large: chunks)")
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", choices=("large", "screen"), default="large", help="headline workload")
+    ap.add_argument("--large-ligands", type=int, default=0, help="library size of the large workload (testing only)")
+    ap.add_argument("--chunk", type=int, default=0, help="chunk size of the large workload (testing only)")
     ap.add_argument("--per-ligand-sample", type=int, default=0,
-                    help="ligands of the per-ligand comparison (default: the whole workload)")
-    ap.add_argument("--cpu-sample", type=int, default=48)
+                    help="ligands of the per-ligand comparison (default: a whole chunk / the whole screen)")
+    ap.add_argument("--cpu-single", type=int, default=12, help="ligands of the one-core oracle run")
+    ap.add_argument("--cpu-per-worker", type=int, default=6, help="ligands per oracle process of the all-core run")
+    ap.add_argument("--cpu-workers", type=int, default=0, help="oracle processes (default: usable cores, <= 16)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-ligand", action="store_true")
     ap.add_argument("--no-refine", action="store_true")
+    ap.add_argument("--no-screen", action="store_true", help="skip the secondary screening leg")
+    ap.add_argument("--screen-steps", type=int, default=3)
     ap.add_argument("--refine-only", action="store_true", help="run only the refinement leg (profiling)")
     ap.add_argument("--refine-ligands", type=int, default=4096)
-    ap.add_argument("--large-chunks", type=int, default=0, help="also stream this many chunks of the large library")
+    ap.add_argument("--stream-chunks", type=int, default=2,
+                    help="chunks of the wall-clock stream leg (generation to host copies), 0 = none")
     ap.add_argument("--dse", type=str, default="", help="run only the knob exploration: flat, full or both")
     ap.add_argument("--dse-ligands", type=int, default=0)
     ap.add_argument("--peaks", action="store_true", help="run only the peak analysis of overlap landscapes")
@@ -368,8 +735,8 @@ def main():
                                                           "budget scenarios")
     ap.add_argument("--no-continuous", action="store_true")
     ap.add_argument("--tiling", type=str, default="")
-    ap.add_argument("--autotune", action="store_true")
-    ap.add_argument("--n-ligands", type=int, default=0, help="override the ligand count (testing only)")
+    ap.add_argument("--autotune", action="store_true", help="screen workload: autotune the tiling")
+    ap.add_argument("--n-ligands", type=int, default=0, help="screen ligand count (testing only)")
     ap.add_argument("--fingerprint", action="store_true", help="print the docking kernel's source fingerprint")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (the reference kernel for HBM byte counters)")
@@ -382,12 +749,18 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path (ligand batches shard trivially "
               "across GPUs); got --gpus %d" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    only = args.copy_calibration or args.refine_only or args.peaks or args.tts or args.dse
+    pool = None
+    workers = args.cpu_workers or cpu_share()
+    if not only and not args.no_cpu_baseline:
+        # forked before anything touches the GPU; the processes run the CPU oracle only
+        import multiprocessing
+        pool = multiprocessing.get_context("fork").Pool(workers)
 
     import numpy as np
     import torch
 
     import paper_1901_06363_amd as gd
-    from synth import configs
 
     torch.cuda.set_device(0)
     if args.copy_calibration:
@@ -414,153 +787,53 @@ def main():
         spaces = ["flat", "full"] if args.dse == "both" else [args.dse]
         print(json.dumps(dse_leg(gd, torch, np, spaces, args.dse_ligands)), flush=True)
         return
-    w = configs.SCREEN
-    n_lig = args.n_ligands or w.n_ligands
-    t = time.perf_counter()
-    ligs = w.ligands(0, n_lig)
-    pts = w.pocket_points()
-    q = w.quaternions()
-    log("inputs generated in %.1f s" % (time.perf_counter() - t))
 
-    stream = torch.cuda.current_stream()
-    P = gd.Pocket(pts, 0.5, w.pad)
-    t = time.perf_counter()
-    B = gd.Batch(P, ligs, q, hp=w.hp, top_k=w.top_k)
-    prep_s = time.perf_counter() - t
-    log("batch prepared in %.2f s: %d ligands, %d poses per call" % (prep_s, B.n_ligands, B.poses_expected))
-    if args.tiling:
-        B.set_tiling(*[int(v) for v in args.tiling.split(",")])
-    if args.autotune:
-        log("autotuned tiling", B.autotune(reps=1))
-    tiling = B.tiling()
-
-    out = B.alloc_outputs(want_angles=True, want_xyz=True)
-    for _ in range(args.warmup):
-        B.dock(gd.BATCHED, out)
-    torch.cuda.synchronize()
-    log("warmup done")
-
-    B.enable_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(args.steps):
-        B.dock(gd.BATCHED, out)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    kernel_ms = B.read_timing()
-    B.enable_timing(False)
-    dt = t1 - t0
-    host = out.host()
-    counters = host["counters"]
-    assert counters[0] == B.poses_expected, (counters[0], B.poses_expected)
-    value = B.poses_expected * args.steps / dt
-    ms_per_step = dt * 1e3 / args.steps
-    k_ms = float(np.mean(kernel_ms))
-    log("timed %d steps: %.1f ms/step, docking kernel %.1f ms" % (args.steps, ms_per_step, k_ms))
-
-    # batched vs per-ligand launches (one launch per ligand) on the same ligands, and
-    # exactness between the two forms
-    per_lig = None
-    if not args.no_per_ligand:
-        ns = min(args.per_ligand_sample or n_lig, n_lig)
-        if ns == n_lig:
-            Bs, hb, tb = B, host, dt / args.steps
-        else:
-            Bs = gd.Batch(P, w.ligands(0, ns), q, hp=w.hp, top_k=w.top_k)
-            rb = Bs.dock(gd.BATCHED)
-            torch.cuda.synchronize()
-            tb0 = time.perf_counter()
-            rb = Bs.dock(gd.BATCHED, rb)
-            torch.cuda.synchronize()
-            tb = time.perf_counter() - tb0
-            hb = rb.host()
-        rp = Bs.dock(gd.PER_LIGAND)
-        torch.cuda.synchronize()
-        tp0 = time.perf_counter()
-        rp = Bs.dock(gd.PER_LIGAND, rp)
-        torch.cuda.synchronize()
-        tp = time.perf_counter() - tp0
-        hp_ = rp.host()
-        same = all(np.array_equal(hb[k], hp_[k]) for k in ("orient", "S", "clash", "angles", "xyz"))
-        per_lig = dict(ligands=ns, per_ligand_poses_per_s=Bs.poses_expected / tp,
-                       per_ligand_ligands_per_s=ns / tp, batched_poses_per_s=Bs.poses_expected / tb,
-                       batched_over_per_ligand=tp / tb, results_identical=bool(same))
-        log("per-ligand launches:", per_lig)
-        del rp, hp_
-
-    cont = None
-    if not args.no_continuous:
-        cont = continuous_leg(gd, torch, np, P, out, ligs, len(pts))
-        log("continuous rescoring:", cont)
-
-    ref = None
+    metric = "poses scored/s and ligands docked/s, batched vs per-ligand, same GPU, exact"
+    if args.workload == "screen":
+        sc = screen_leg(gd, torch, np, args, args.steps, args.warmup, args.n_ligands, args.tiling)
+        head = dict(value=sc["poses_per_s"], ms_per_step=sc["ms_per_step"],
+                    config=dict(workload=sc["workload"], ligands=sc["ligands"], orientations=sc["orientations"],
+                                hp_step_deg=sc["hp_step_deg"], poses_per_step=sc["poses_per_step"],
+                                tiling=sc["tiling"], grid_pad_A=sc["grid_pad_A"]),
+                    ligands_per_s=sc["ligands_per_s"], atoms_per_s=sc["atoms_per_s"],
+                    fallback_per_pose=sc["fallback_per_pose"], prep_s=sc["prep_s"], per_ligand=sc["per_ligand"],
+                    continuous=sc["continuous"], roofline=sc["roofline"])
+        cpu_name, cpu_first = "screen", 0
+    else:
+        head = large_headline(gd, torch, np, args)
+        log("large headline:", json.dumps(head))
+        if not args.no_screen:
+            head["screen"] = screen_leg(gd, torch, np, args, args.screen_steps, 1, args.n_ligands)
+        cpu_name, cpu_first = "large", 0
+    if args.stream_chunks > 0 and args.workload == "large":
+        head["stream"] = large_leg(gd, torch, args.stream_chunks, head["config"]["tiling"])
+        log("stream:", head["stream"])
     if not args.no_refine and args.refine_ligands > 0:
-        ref = refine_leg(gd, torch, np, args.refine_ligands)
-        log("refinement:", ref)
-
-    large = None
-    if args.large_chunks > 0:
-        large = large_leg(gd, torch, args.large_chunks)
-        log("large:", large)
-
+        head["refine"] = refine_leg(gd, torch, np, args.refine_ligands)
+        log("refinement:", head["refine"])
     cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(w, ligs, q, min(args.cpu_sample, n_lig))
-        cpu["cores"] = 1
+    if pool is not None:
+        cpu = cpu_baseline(pool, workers, cpu_name, cpu_first, args.cpu_single, args.cpu_per_worker)
+        pool.close()
+        pool.join()
         log("cpu baseline:", cpu)
-
-    achieved = B.algo_flops / (k_ms * 1e-3) / 1e12
-    tr = measured_traffic() if n_lig == w.n_ligands else None
     line = {
-        "metric": "poses scored/s and ligands docked/s, batched vs per-ligand, same GPU, exact",
-        "value": value,
+        "metric": metric,
+        "value": head.pop("value"),
         "unit": "poses/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": head.pop("ms_per_step"),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {
-            "workload": "screen: %d ligands (20-80 atoms, 2-12 rotatable bonds) x 4,000-point pocket, "
-                        "512 orientations, 15-degree steps, 1 repetition, top-8" % n_lig,
-            "ligands": n_lig,
-            "orientations": len(q),
-            "hp_step_deg": w.hp,
-            "poses_per_step": B.poses_expected,
-            "tiling": list(tiling),
-            "grid_pad_A": w.pad,
-        },
-        "ligands_per_s": n_lig * args.steps / dt,
-        "atoms_per_s": B.n_atoms_total * args.steps / dt,
-        "fallback_per_pose": float(counters[1]) / float(counters[0]),
-        "oob_lookups": int(counters[2]),
-        "prep_s": prep_s,
-        "end_to_end_poses_per_s_incl_prep": B.poses_expected / (prep_s + dt / args.steps),
-        "per_ligand": per_lig,
-        "continuous": cont,
-        "refine": ref,
-        "large": large,
-        "roofline": {
-            "bound": "alu",
-            "achieved": achieved,
-            "peak": FP32_VECTOR_PEAK_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
-            "traffic": (tr["fetch"] + tr["write"]) if tr else None,
-            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-            "traffic_GBps": ((tr["fetch"] + tr["write"]) / (k_ms * 1e-3) / 1e9) if tr else None,
-            "kernel": "dock_persistent_kernel",
-            "kernel_ms": k_ms,
-            "algo_flops_per_launch": B.algo_flops,
-            "algo_gather_bytes_per_launch": B.algo_bytes,
-            "gather_GBps": B.algo_bytes / (k_ms * 1e-3) / 1e9,
-        },
-        "cpu_baseline": cpu,
+        "config": head.pop("config"),
     }
+    line.update(head)
+    line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
 
 

@@ -40,23 +40,27 @@ class _Prepared:
         self.error = None
 
 
-def _prepare(slot, pocket, source, first, count, quats, knobs, stream):
+def _prepare(slot, pocket, source, first, count, quats, knobs, stream, tiling):
     try:
         ligs = source(first, count)
         slot.ligands = ligs
         slot.batch = Batch(pocket, ligs, quats, stream=stream, **knobs)
+        if tiling:
+            slot.batch.set_tiling(*tiling)
     except BaseException as e:  # re-raised in the consumer
         slot.error = e
 
 
-def screen(pocket, source, n_ligands, quats, chunk=65536, mode=BATCHED, refine_poses=None, want_xyz=True, **knobs):
+def screen(pocket, source, n_ligands, quats, chunk=65536, mode=BATCHED, refine_poses=None, want_xyz=True, tiling=None,
+           **knobs):
     """Dock ligands [0, n_ligands) of ``source`` in chunks; yields one dict per
     chunk: first, count, ligands, poses, dock_ms (docking kernel time, HIP
     events), result (host arrays of the top-k poses), and with ``refine_poses``
     the refined poses' surrogate, exact S, clash, acceptance and coordinates.
     ``knobs`` are the Batch knobs (hp, lp, threshold, repetitions, refine (tile
     peeling), top_k, clash_dist, clash_min_bonds); the pocket needs a density
-    grid for ``refine_poses``.
+    grid for ``refine_poses``.  ``tiling`` (waves per block, angle block,
+    pairs per lane) is applied to every chunk's batch.
 
     The chunks are pipelined: while chunk i docks on the GPU, a host thread
     prepares chunk i+1, and chunk i-1 is refined on its own stream (after its
@@ -76,7 +80,7 @@ def screen(pocket, source, n_ligands, quats, chunk=65536, mode=BATCHED, refine_p
         slot = _Prepared()
         first = starts[i]
         th = threading.Thread(target=_prepare, args=(slot, pocket, source, first, min(chunk, n_ligands - first),
-                                                     quats, knobs, side))
+                                                     quats, knobs, side, tiling))
         th.start()
         return slot, th
 
