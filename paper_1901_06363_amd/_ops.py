@@ -28,11 +28,68 @@ def _lig_desc(ligands):
     return ligands if isinstance(ligands, _LigandArrays) else _LigandArrays(ligands)
 
 
+def _pose_layout(lg, pose_lig):
+    """(pose_lig as int32, total atoms of the poses, most rotamers of any
+    pose's ligand); raises on a ligand index out of range."""
+    pl = np.ascontiguousarray(pose_lig, dtype=np.int32).reshape(-1)
+    nat = np.diff(np.asarray(lg.atom_off, dtype=np.int64))
+    nrot = np.diff(np.asarray(lg.rot_off, dtype=np.int64))
+    if len(pl) and (pl.min() < 0 or pl.max() >= len(nat)):
+        raise ValueError("pose_lig holds a ligand index outside [0, %d)" % len(nat))
+    if not len(pl):
+        return pl, 0, 0
+    return pl, int(nat[pl].sum()), int(nrot[pl].max())
+
+
+def _check_rows(name, t, n_rows):
+    """Format of a coordinate array the kernels read (and gd_refine writes)
+    in place: contiguous float32 with at least n_rows elements."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    if t.dtype != torch.float32:
+        raise TypeError("%s must be float32, got %s" % (name, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous (a strided view would be read as consecutive rows)" % name)
+    if t.numel() < n_rows:
+        raise ValueError("%s holds %d values, the poses need %d" % (name, t.numel(), n_rows))
+
+
+def _check_coords(px, py, pz, n_atoms):
+    arrays = (("px", px), ("py", py), ("pz", pz))
+    for name, t in arrays:
+        _check_rows(name, t, n_atoms)
+    for name, t in arrays:
+        if not t.is_cuda:
+            raise TypeError("%s must be a CUDA (HIP device) tensor" % name)
+
+
+def _check_param(name, t, n, cols):
+    """A per-pose parameter array on the GPU: shape (n,) when cols is None,
+    (n, cols) for an int, (n, >= cols[0]) for a one-element tuple."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    if not t.dtype.is_floating_point:
+        raise TypeError("%s must be floating point, got %s" % (name, t.dtype))
+    if cols is None:
+        ok, want = t.dim() == 1 and t.shape[0] == n, "(%d,)" % n
+    elif isinstance(cols, tuple):
+        ok, want = t.dim() == 2 and t.shape[0] == n and t.shape[1] >= cols[0], "(%d, >= %d)" % (n, cols[0])
+    else:
+        ok, want = t.dim() == 2 and tuple(t.shape) == (n, cols), "(%d, %d)" % (n, cols)
+    if not ok:
+        raise ValueError("%s must have shape %s, got %s" % (name, want, tuple(t.shape)))
+    if not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP device) tensor" % name)
+
+
 def score_poses(pocket, ligands, pose_lig, px, py, pz, clash_dist=2.0, clash_min_bonds=4, stream=None):
     """Exact S and bump flags of poses (device float32 CSR rows by pose)."""
     torch = _torch()
     lg = _lig_desc(ligands)
-    pl = np.ascontiguousarray(pose_lig, dtype=np.int32)
+    pl, n_atoms, _ = _pose_layout(lg, pose_lig)
+    _check_coords(px, py, pz, n_atoms)
     n = len(pl)
     S = torch.empty(n, dtype=torch.int32, device="cuda")
     clash = torch.empty(n, dtype=torch.uint8, device="cuda")
@@ -98,12 +155,19 @@ def sweep_profile(pocket, batch, res, step=1, stream=None):
     return S, f, sz
 
 
-def _prm(t, q, tau, n):
+def _prm(t, q, tau, n, rmax):
+    """Checked float32 copies of the parameters t (n, 3), q (n, 4) and tau
+    (n, >= rmax; may be None or empty when no pose has a rotamer)."""
     torch = _torch()
+    _check_param("t", t, n, 3)
+    _check_param("q", q, n, 4)
     t = t.contiguous().float()
     q = q.contiguous().float()
     if tau is None or tau.numel() == 0:
+        if rmax > 0:
+            raise ValueError("tau is required: the poses' ligands have up to %d rotamers" % rmax)
         tau = torch.zeros((n, 1), dtype=torch.float32, device="cuda")
+    _check_param("tau", tau, n, (max(rmax, 1),))
     tau = tau.contiguous().float()
     return t, q, tau, tau.shape[1]
 
@@ -120,9 +184,10 @@ def surrogate_fwd(pocket, ligands, pose_lig, px, py, pz, t, q, tau, stream=None,
     the bump penalty."""
     torch = _torch()
     lg = _lig_desc(ligands)
-    pl = np.ascontiguousarray(pose_lig, dtype=np.int32)
+    pl, n_atoms, rmax = _pose_layout(lg, pose_lig)
+    _check_coords(px, py, pz, n_atoms)
     n = len(pl)
-    t, q, tau, stride = _prm(t, q, tau, n)
+    t, q, tau, stride = _prm(t, q, tau, n, rmax)
     F = torch.empty(n, dtype=torch.float32, device="cuda")
     _abi.check(_abi.load().gd_surrogate_fwd(pocket.handle, ctypes.byref(lg.desc), n,
                                             pl.ctypes.data_as(ctypes.c_void_p), _dp(px), _dp(py), _dp(pz), _dp(t),
@@ -137,9 +202,11 @@ def surrogate_bwd(pocket, ligands, pose_lig, px, py, pz, t, q, tau, dF, stream=N
     """dF/dt, dF/dq, dF/dtau scaled by the upstream gradient dF (per pose)."""
     torch = _torch()
     lg = _lig_desc(ligands)
-    pl = np.ascontiguousarray(pose_lig, dtype=np.int32)
+    pl, n_atoms, rmax = _pose_layout(lg, pose_lig)
+    _check_coords(px, py, pz, n_atoms)
     n = len(pl)
-    t, q, tau, stride = _prm(t, q, tau, n)
+    t, q, tau, stride = _prm(t, q, tau, n, rmax)
+    _check_param("dF", dF, n, None)
     dF = dF.contiguous().float()
     dt = torch.empty((n, 3), dtype=torch.float32, device="cuda")
     dq = torch.empty((n, 4), dtype=torch.float32, device="cuda")
@@ -162,7 +229,8 @@ def refine(pocket, ligands, pose_lig, px, py, pz, steps=50, lr_t=0.002, lr_q=1e-
     (bump penalty over the far pairs closer than clash_dist)."""
     torch = _torch()
     lg = _lig_desc(ligands)
-    pl = np.ascontiguousarray(pose_lig, dtype=np.int32)
+    pl, n_atoms, _ = _pose_layout(lg, pose_lig)
+    _check_coords(px, py, pz, n_atoms)  # written in place
     n = len(pl)
     kms = ctypes.c_float(0.0)
     opts = _abi.RefineOpts(int(steps), float(lr_t), float(lr_q), float(lr_tau), float(max_dt), float(max_dtau),
