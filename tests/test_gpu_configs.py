@@ -206,15 +206,29 @@ def test_refine_full_size_sampled(g):
     off = np.concatenate([[0], np.cumsum(np.diff(ligs.atom_off)[pose_lig])])
     rows_acc = np.repeat(acc.astype(bool), np.diff(off))
     assert np.array_equal(Xr[rows_acc], it[rows_acc])
-    # trajectories: FP32 ascent vs the FP64 oracle ascent from the same input pose
-    rms = []
+    # trajectories: FP32 ascent vs the FP64 oracle ascent from the same input
+    # pose, within 1e-3 A unless the paths part at a certified face crossing
+    rms, certified = [], []
     for p in rng.choice(len(pose_lig), 12, replace=False):
         li = int(pose_lig[p])
         sl = slice(off[p], off[p + 1])
         _, Xref, _ = OB.refine(ligs.ligand(li), X0[sl].astype(np.float64), **kw)
-        rms.append(np.sqrt(np.mean(np.sum((it[sl].astype(np.float64) - Xref) ** 2, axis=1))))
+        r = np.sqrt(np.mean(np.sum((it[sl].astype(np.float64) - Xref) ** 2, axis=1)))
+        rms.append(r)
+        if r > 1e-3:
+            def gpu_iterate(k, li=li, sl=sl):
+                q = [torch.tensor(X0[sl, a].copy(), device="cuda") for a in range(3)]
+                o = g.refine(P, ligs, np.array([li]), *q, want_iterate=True, **dict(kw, steps=k))
+                return torch.stack(o["iterate"], 1).cpu().numpy()
+            why, info = gpuutil.certify_split(OB, ligs.ligand(li), X0[sl], gpu_iterate, e["steps"],
+                                              float(np.float32(e["blur_h"])), **{k: v for k, v in kw.items()
+                                                                                if k != "steps"})
+            assert why, ("uncertified split", int(p), info)
+            certified.append((int(p), why, info["step"]))
     rms = np.array(rms)
-    assert np.median(rms) < 1e-5 and np.mean(rms <= 1e-3) >= 0.9, rms
+    print("sampled trajectories: median RMSD %.2e, %d certified split(s) (pose, reason, step): %s"
+          % (np.median(rms), len(certified), certified))
+    assert np.median(rms) < 1e-5
 
 
 @gpu

@@ -1,11 +1,22 @@
 """GPU parity of the density-surrogate refinement against the FP64 oracle.
 
 Bar: density nodes within FP32 rounding of the FP64 definition; surrogate
-values within 1e-4 and gradients within 1e-3 (relative, per parameter
-group) of the oracle's analytic gradient at the same parameters; the
-refined pose is re-scored with the exact score, which must match the oracle's
-score of the returned FP32 pose bit for bit, and the acceptance rule is
-checked pose by pose.
+values within 1e-4 and every gradient component within 1e-3 of its
+parameter group's norm (translation, quaternion, torsions) against the
+oracle's analytic gradient at the same parameters; 50-step trajectories
+within 1e-3 A (RMSD) of the FP64 oracle's; the refined pose is re-scored with
+the exact score, which must match the oracle's score of the returned FP32
+pose bit for bit, and the acceptance rule is checked pose by pose.
+
+The trilinear density's gradient jumps across lattice faces, and the ascent
+map can amplify rounding-size differences.  The gradient check excludes only
+poses whose FP32 and FP64 positions may sit in different trilinear cells, i.e.
+(as decided on the oracle's FP64 positions) an atom within the FP32
+coordinate bound (1e-4 A) of a face of the density lattice.  A trajectory may
+part from the FP64 one only for a reason certified on the oracle where the
+paths first separate: a face crossing, or the map's own sensitivity (oracle
+runs of as many steps from inputs moved by a few FP32 ulps part as far).
+Excluded cases are counted and printed.
 """
 import numpy as np
 import pytest
@@ -32,7 +43,10 @@ def setup(g):
     P = g.Pocket(pts, 0.5, 12.0, blur_sigma=SIG, blur_h=BH, blur_cutoff_sigmas=CUTS, blur_pad=8.0)
     O = oracle.OraclePocket(pts, 0.5)
     B = oracle.OracleBlur(O, SIG, CUTS, BH)
-    ligs = w.ligands(0, 12)
+    # a ragged sample that includes ligands of more than 64 atoms (two atoms
+    # per lane) with 12 or more rotatable bonds (deep torsion trees)
+    pool = w.ligands(0, 200)
+    ligs = pool.subset(list(range(8)) + [37, 39, 85, 128])
     # docked poses as refinement inputs: top-4 of 64 orientations
     q = synth.quaternions(w.quat_seed, 64)
     b = g.Batch(P, ligs, q, hp=w.hp, top_k=4)
@@ -67,6 +81,13 @@ def test_density_grid_matches_definition(g, setup):
         assert rho[iz, iy, ix] == np.float32(want)
 
 
+FP32_XYZ = gpuutil.FP32_XYZ
+
+
+def _face_dist(X):
+    return gpuutil.face_dist(X, float(np.float32(BH)))
+
+
 def _params(n, nrmax, seed):
     rng = np.random.default_rng(seed)
     t = rng.normal(0, 0.3, (n, 3))
@@ -94,22 +115,28 @@ def test_surrogate_value_and_gradient(g, setup, pen):
     dF = np.linspace(0.5, 1.5, n).astype(np.float32)
     dt, dq, dtau = (x.cpu().numpy() for x in
                     g.surrogate_bwd(S["P"], ligs, pl, S["px"], S["py"], S["pz"], T(t), T(q), T(tau), T(dF), **pen))
-    bad = 0
+    excused = 0
     for p in range(n):
         lig = ligs.ligand(pl[p])
         nr = ligs.n_rot(pl[p])
         X0 = S["rows"][p].astype(np.float64)
         prm = np.concatenate([t[p], q[p], tau[p, :nr]]).astype(np.float64)
-        Fo, go, _ = S["B"].surrogate(lig, X0, prm, **pen)
+        Fo, go, Xo = S["B"].surrogate(lig, X0, prm, **pen)
         assert abs(F[p] - Fo) <= 1e-4 * max(abs(Fo), 1.0), (p, F[p], Fo)
         gg = np.concatenate([dt[p], dq[p], dtau[p, :nr]]) / dF[p]
+        ok = True
         for sl in (slice(0, 3), slice(3, 7), slice(7, 7 + nr)):
             a, b = gg[sl], go[sl]
-            if len(a) and np.linalg.norm(a - b) > 1e-3 * max(np.linalg.norm(b), 1e-3):
-                bad += 1
+            if len(a) and np.max(np.abs(a - b)) > 1e-3 * max(np.linalg.norm(b), 1e-3):
+                ok = False
+        if not ok:
+            # certified only if the FP32 and FP64 positions may lie in different trilinear cells
+            assert _face_dist(Xo) < FP32_XYZ, (p, _face_dist(Xo))
+            excused += 1
         assert np.all(dtau[p, nr:] == 0)
-    # FP32 vs FP64 positions can straddle a trilinear face, where the gradient jumps
-    assert bad <= max(1, n // 50), bad
+    print("surrogate gradient%s: %d of %d poses excused (an atom within %.0e A of a trilinear face)"
+          % (" (penalised)" if pen else "", excused, n, FP32_XYZ))
+    assert sum(ligs.n_atoms(i) > 64 and ligs.n_rot(i) >= 12 for i in set(pl.tolist())) >= 2
 
 
 @gpu
@@ -138,28 +165,38 @@ def test_autograd_function(g, setup):
     assert bool((Fp <= F).all())  # the penalty only subtracts
 
 
+def _gpu_iterates(g, S, steps, cw):
+    """The GPU's iterate after every step count 1..steps (one call each)."""
+    ligs, pl = S["ligs"], S["pose_lig"]
+    out = []
+    for k in range(1, steps + 1):
+        px, py, pz = S["px"].clone(), S["py"].clone(), S["pz"].clone()
+        r = g.refine(S["P"], ligs, pl, px, py, pz, steps=k, want_iterate=True, clash_weight=cw)
+        out.append(np.stack([v.cpu().numpy() for v in r["iterate"]], 1))
+    return out
+
+
 @gpu
-@pytest.mark.parametrize("cw,split_ok", [(0.0, 0.9), (10.0, 0.9), (1000.0, 0.8)])
-def test_refine_rescoring_and_acceptance(g, setup, cw, split_ok):
+@pytest.mark.parametrize("cw", [0.0, 10.0, 1000.0])
+def test_refine_rescoring_and_acceptance(g, setup, cw):
     """cw > 0: the clash-penalised surrogate, against the oracle's penalised
-    ascent.  A heavy penalty makes clipped ascent steps flip more often between
-    FP32 and FP64 paths, so at weight 1,000 up to a fifth of the 50-step
-    trajectories may part ways (the single-step test below bounds every pose)."""
+    ascent.  Every 50-step trajectory must stay within 1e-3 A (RMSD) of the
+    FP64 one unless the paths part at a certified face crossing."""
     import torch
     S = setup
     ligs, pl = S["ligs"], S["pose_lig"]
     px, py, pz = S["px"].clone(), S["py"].clone(), S["pz"].clone()
-    out = g.refine(S["P"], ligs, pl, px, py, pz, steps=50, want_iterate=True, clash_weight=cw)
+    steps = 50
+    out = g.refine(S["P"], ligs, pl, px, py, pz, steps=steps, want_iterate=True, clash_weight=cw)
     F, Sg, cg, acc = (out[k].cpu().numpy() for k in ("F", "S", "clash", "accepted"))
     X = np.stack([px.cpu().numpy(), py.cpu().numpy(), pz.cpu().numpy()], 1)
     It = np.stack([v.cpu().numpy() for v in out["iterate"]], 1)
     off = 0
-    rms, fdiff = [], []
+    rms, fdiff, split = [], [], []
     for p in range(len(pl)):
         lig = ligs.ligand(pl[p])
         l = len(lig["x"])
         Xp, X0, Xi = X[off:off + l], S["rows"][p], It[off:off + l]
-        off += l
         s_in, c_in = oracle.score_poses(S["O"], lig, X0[None, :, 0], X0[None, :, 1], X0[None, :, 2])
         s_out, c_out = oracle.score_poses(S["O"], lig, Xp[None, :, 0], Xp[None, :, 1], Xp[None, :, 2])
         assert Sg[p] == s_out[0] and cg[p] == c_out[0]
@@ -167,22 +204,33 @@ def test_refine_rescoring_and_acceptance(g, setup, cw, split_ok):
             assert not c_out[0] and s_out[0] < s_in[0]
         else:
             assert np.array_equal(Xp, X0) and Sg[p] == s_in[0]
-        # trajectory against the FP64 oracle (FP32 arithmetic; kinks can split paths)
-        prm, Xo, Fo = S["B"].refine(lig, X0.astype(np.float64), steps=50, clash_weight=cw)
-        fdiff.append(abs(F[p] - Fo) / max(abs(Fo), 1.0))
-        rms.append(np.sqrt(((Xi - Xo) ** 2).sum(1).mean()))
+        # trajectory against the FP64 oracle
+        prm, Xo, Fo = S["B"].refine(lig, X0.astype(np.float64), steps=steps, clash_weight=cw)
+        r = np.sqrt(((Xi - Xo) ** 2).sum(1).mean())
+        rms.append(r)
+        if r > 1e-3:
+            split.append((p, off, l))
+        else:
+            fdiff.append(abs(F[p] - Fo) / max(abs(Fo), 1.0))
         if acc[p]:
             assert np.array_equal(Xp, Xi)
+        off += l
+    certified = []
+    if split:
+        its = _gpu_iterates(g, S, steps, cw)
+        for p, o, l in split:
+            why, info = gpuutil.certify_split(S["B"], ligs.ligand(pl[p]), S["rows"][p],
+                                              lambda k: its[k - 1][o:o + l], steps, float(np.float32(BH)),
+                                              clash_weight=cw)
+            assert why, ("uncertified split", p, info)
+            certified.append((p, why, info["step"]))
     rms = np.array(rms)
     print("refine (clash weight %g): accepted %d/%d; final-iterate RMSD vs the FP64 trajectory: median %.2e, "
-          "fraction <= 1e-3 A %.2f, max %.2e; median |dF|/F %.2e"
-          % (cw, acc.sum(), len(pl), np.median(rms), np.mean(rms <= 1e-3), rms.max(), np.median(fdiff)))
+          "max over unsplit %.2e; %d certified split(s) (pose, reason, step): %s; median |dF|/F %.2e"
+          % (cw, acc.sum(), len(pl), np.median(rms), max([v for v in rms if v <= 1e-3] or [0.0]), len(certified),
+             certified, np.median(fdiff)))
     assert acc.sum() > 0
     assert np.median(fdiff) < 1e-4
-    # the trilinear gradient jumps at lattice faces: an FP32 and an FP64 path
-    # that straddle a face part ways, so a few trajectories are allowed to split
-    assert np.median(rms) < 1e-5
-    assert np.mean(rms <= 1e-3) >= split_ok
 
 
 @gpu
