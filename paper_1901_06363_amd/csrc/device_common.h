@@ -37,6 +37,18 @@ __device__ __forceinline__ int wave_sum(int v) {
            __builtin_amdgcn_readlane(v, 63);
 }
 
+// 64-bit wave sum (for exact scores of atoms far outside the grid box).
+__device__ __forceinline__ long long wave_sum64(long long v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Scores are reported in 31 bits: a pose whose S reaches 2^31 - 1 (an atom
+// some kilometres from the pocket) saturates there.
+constexpr long long kSMax = 0x7fffffffLL;
+__device__ __forceinline__ int sat_S(long long s) { return s < kSMax ? (int)s : (int)kSMax; }
+
 __device__ __forceinline__ float wave_maxf(float v) {
     // non-negative inputs: the integer order of the bit patterns is the float order
     int b = dpp_row_scan(__float_as_int(v), 0, [](int a, int c) { return a > c ? a : c; });
@@ -68,6 +80,13 @@ __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// The double held by one lane (a wave-uniform lane index), in scalar registers.
+__device__ __forceinline__ double readlane_d(double v, int l) {
+    long long b = __double_as_longlong(v);
+    int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 // A wave-uniform double moved to scalar registers.
 __device__ __forceinline__ double uniform_d(double v) {
     long long b = __double_as_longlong(v);
@@ -97,22 +116,47 @@ __device__ __forceinline__ T ldg_record(const T* p) {
     return v;
 }
 
+// Loads of wave-uniform data that no kernel writes (the batch and pocket
+// tables) through the constant address space: with a uniform address the
+// compiler issues scalar loads and keeps the value in scalar registers rather
+// than a copy in every lane.
+template <class T>
+__device__ __forceinline__ T ldc(const T* p) {
+    return *(const __attribute__((address_space(4))) T*)p;
+}
+
+template <class T>
+__device__ __forceinline__ T ldc_record(const T* p) {
+    static_assert(sizeof(T) % 4 == 0, "whole words");
+    T v;
+    uint32_t* d = reinterpret_cast<uint32_t*>(&v);
+    const uint32_t* s = reinterpret_cast<const uint32_t*>(p);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); i++) d[i] = ldc(s + i);
+    return v;
+}
+
 // --------------------------------------------------------------------------
 // exact distance field lookups
 
-// D by brute force over the occupied cells (cells outside the tabulated box).
-static __device__ int D_brute(const PocketDev& P, int cx, int cy, int cz) {
-    int best = 0x7fffffff;
+// D by brute force over the occupied cells (cells outside the tabulated box),
+// in 64 bits; a cell more than about 46,000 cells from every occupied cell
+// (23 km at h = 0.5 A) saturates at 2^31 - 1, so a sum over at most 128
+// atoms stays below 2^38.
+constexpr long long kDMax = 0x7fffffffLL;
+static __device__ long long D_brute(const PocketDev& P, int cx, int cy, int cz) {
+    long long best = kDMax;
     for (int i = 0; i < P.n_occ; i++) {
-        int dx = cx - ldg(P.occ + 3 * i), dy = cy - ldg(P.occ + 3 * i + 1), dz = cz - ldg(P.occ + 3 * i + 2);
-        int d = dx * dx + dy * dy + dz * dz;
+        long long dx = (long long)cx - ldg(P.occ + 3 * i), dy = (long long)cy - ldg(P.occ + 3 * i + 1),
+                  dz = (long long)cz - ldg(P.occ + 3 * i + 2);
+        long long d = dx * dx + dy * dy + dz * dz;
         best = d < best ? d : best;
     }
     return best;
 }
 
 // D of a box-relative cell; outside the box falls back to brute force.
-__device__ __forceinline__ int D_box(const PocketDev& P, int ix, int iy, int iz, int& oob) {
+__device__ __forceinline__ long long D_box(const PocketDev& P, int ix, int iy, int iz, int& oob) {
     if ((unsigned)ix < (unsigned)P.dim[0] && (unsigned)iy < (unsigned)P.dim[1] && (unsigned)iz < (unsigned)P.dim[2])
         return ldg(P.edt + ((size_t)iz * P.dim[1] + iy) * P.dim[0] + ix);
     oob++;
@@ -121,7 +165,7 @@ __device__ __forceinline__ int D_box(const PocketDev& P, int ix, int iy, int iz,
 
 // D of the cell containing an FP64 point (global frame): floor(x / h) is
 // floor(x * (1/h)) exactly because h is a power of two.
-__device__ __forceinline__ int D_exact(const PocketDev& P, double x, double y, double z, int& oob) {
+__device__ __forceinline__ long long D_exact(const PocketDev& P, double x, double y, double z, int& oob) {
     int cx = (int)floor(x * P.inv_h), cy = (int)floor(y * P.inv_h), cz = (int)floor(z * P.inv_h);
     return D_box(P, cx - P.lo[0], cy - P.lo[1], cz - P.lo[2], oob);
 }

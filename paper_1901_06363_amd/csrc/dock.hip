@@ -32,8 +32,9 @@ namespace gd {
 
 __constant__ double c_cos64[360];
 __constant__ double c_sin64[360];
-__constant__ float c_cos32[360];
-__constant__ float c_sin32[360];
+// FP32 roundings of the same tables, cos then sin, read with per-lane
+// indices (once per angle block, outside the atom loops) from global memory
+__device__ float c_trig32[720];
 
 // --------------------------------------------------------------------------
 // FP64 kinematics (same formulas and operation order everywhere)
@@ -68,6 +69,8 @@ typedef __attribute__((address_space(3))) double lds_double;
 typedef __attribute__((address_space(3))) float lds_float;
 typedef float f4 __attribute__((ext_vector_type(4)));  // plain 16-byte vector (copyable from LDS)
 typedef __attribute__((address_space(3))) f4 lds_float4;
+typedef float f2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) f2 lds_float2;
 
 __device__ __forceinline__ f4 mk4(float a, float b, float c, float d) {
     f4 v;
@@ -82,27 +85,43 @@ typedef __attribute__((address_space(3))) uint8_t lds_u8;
 typedef __attribute__((address_space(3))) uint16_t lds_u16;
 
 constexpr int kSurvCap = 128;  // straddling pairs that can still bump in one sweep (LDS list)
-constexpr int kMvPad = 32;     // sentinel rows after the moving list (cover one step of the score pass)
+constexpr int kMvPad = 8;      // sentinel rows after the moving list (cover one step of the score pass)
 
+// The per-wave slice is sized for the batch's largest ligand and decides how
+// many waves fit a CU, so the moving-atom rows are packed to 36 bytes (no
+// padding lane) and the survivors' coefficients to 12 bytes.
 struct WaveLds {
-    lds_double* X;   // [3][lp] FP64 master coordinates (x, y, z planes)
-    lds_double* SW;  // [8] FP64 axis k (3), pivot p (3) and |X_c - X_a| of the sweep in progress
-    lds_float4* AD;  // [lp][2] per-atom sweep data: (u, k.u), (k x u, |u|^2), u = X - p (A); set-up only
-    lds_float4* MV;  // [lp + kMvPad][3] moving atoms: P0, U, V in cell units (w unused), then sentinel
-                     // rows; written after the prune over the same memory as AD
-    lds_int* Slo;    // [nmax] lower bound of each candidate's S over the moving atoms
-    lds_int* Shi;    // [nmax] upper bound
+    lds_double* X;     // [3][lp] FP64 master coordinates (x, y, z planes)
+    lds_double* SW;    // [8] FP64 axis k (3), pivot p (3) and |X_c - X_a| of the sweep in progress
+    lds_float4* AD;    // [lmax][2] per-atom sweep data: (u, k.u), (k x u, |u|^2), u = X - p (A); set-up only
+    // moving atoms in cell units, rows [0, m) then sentinel rows, written after
+    // the prune over the memory of AD: P0 = (a.x, a.y, a.z), U = (a.w, b.x,
+    // b.y), V = (b.z, b.w, c)
+    lds_float4* MVa;   // [lmax + kMvPad]
+    lds_float4* MVb;   // [lmax + kMvPad]
+    lds_float* MVc;    // [lmax + kMvPad]
+    lds_int* Slo;      // [nmax] lower bound of each candidate's S over the moving atoms
+    lds_int* Shi;      // [nmax] upper bound
     lds_u16* surv_pr;  // [kSurvCap] the surviving pairs (left | right << 8)
-    lds_u8* st;      // [nmax] bit0: certain bump, bit1: possible bump
-    lds_float4* surv;  // [kSurvCap] (A, B, C, -) of the pairs that survive the sweep's prune
+    lds_u8* st;        // [nmax] bit0: certain bump, bit1: possible bump
+    lds_float* survA;  // [kSurvCap] A of d^2 = A + 2B cos + 2C sin for the pairs that survive the prune
+    lds_float2* survBC;  // [kSurvCap] (B, C)
 };
 
-__host__ __device__ inline int lds_pitch(int lmax) { return (lmax + 15) & ~15; }
+// FP64 plane pitch: even, so that the FP32 arrays after the planes stay 16-byte aligned
+__host__ __device__ inline int lds_pitch(int lmax) { return (lmax + 1) & ~1; }
+__host__ __device__ inline int mv_rows(int lmax) { return lmax + kMvPad; }
+// the moving-atom rows over the per-atom data, rounded to 16 bytes
+__host__ __device__ inline size_t mv_region_bytes(int lmax) {
+    const size_t rows = (size_t)mv_rows(lmax) * (2 * sizeof(f4) + sizeof(float));
+    const size_t ad = (size_t)lmax * 2 * sizeof(f4);
+    return ((rows > ad ? rows : ad) + 15) & ~(size_t)15;
+}
 __host__ __device__ inline size_t wave_lds_bytes(int lmax, int nmax) {
-    int lp = lds_pitch(lmax);
-    int np = (nmax + 15) & ~15;
-    size_t b = sizeof(double) * 3 * lp + sizeof(double) * 8 + sizeof(f4) * (3 * (lp + kMvPad) + kSurvCap) +
-               sizeof(int) * 2 * np + np + sizeof(uint16_t) * kSurvCap;
+    const int lp = lds_pitch(lmax);
+    const int np = (nmax + 15) & ~15;
+    size_t b = sizeof(double) * 3 * lp + sizeof(double) * 8 + mv_region_bytes(lmax) +
+               (sizeof(f2) + sizeof(float)) * kSurvCap + sizeof(int) * 2 * np + np + sizeof(uint16_t) * kSurvCap;
     return (b + 15) & ~(size_t)15;
 }
 __host__ __device__ inline size_t replay_lds_bytes(int lmax) {
@@ -110,15 +129,19 @@ __host__ __device__ inline size_t replay_lds_bytes(int lmax) {
 }
 
 __device__ inline WaveLds carve(char* base, int lmax, int nmax) {
-    int lp = lds_pitch(lmax);
-    int np = (nmax + 15) & ~15;
+    const int lp = lds_pitch(lmax), R = mv_rows(lmax);
+    const int np = (nmax + 15) & ~15;
     WaveLds W;
     W.X = (lds_double*)base;
     W.SW = W.X + 3 * lp;
-    W.AD = (lds_float4*)(W.SW + 8);
-    W.MV = W.AD;
-    W.surv = W.MV + 3 * (lp + kMvPad);
-    W.Slo = (lds_int*)(W.surv + kSurvCap);
+    char* region = (char*)(W.SW + 8);
+    W.AD = (lds_float4*)region;
+    W.MVa = (lds_float4*)region;
+    W.MVb = W.MVa + R;
+    W.MVc = (lds_float*)(W.MVb + R);
+    W.survBC = (lds_float2*)(region + mv_region_bytes(lmax));
+    W.survA = (lds_float*)(W.survBC + kSurvCap);
+    W.Slo = (lds_int*)(W.survA + kSurvCap);
     W.Shi = W.Slo + np;
     W.st = (lds_u8*)(W.Shi + np);
     W.surv_pr = (lds_u16*)(W.st + np);
@@ -148,8 +171,9 @@ struct Sweep {
 
 // Kept out of line (it runs for a small fraction of candidates); every
 // argument is a value or a pointer so that nothing of the caller's state has
-// to live in scratch memory.  Returns S in the low 32 bits, feasibility in
-// bit 32 and this lane's count of out-of-box lookups from bit 40.
+// to live in scratch memory.  Returns S (< 2^38: at most 128 atoms of
+// D < 2^31) in the low 40 bits, feasibility in bit 40 and this lane's count
+// of out-of-box lookups from bit 41.
 __device__ __noinline__ uint64_t eval_fp64(const PocketDev* Pp, const lds_double* X, const lds_double* SWp, int lp,
                                            const uint8_t* mvl, int m, const uint16_t* pairs, int npairs, int side,
                                            double cd2, int deg) {
@@ -161,14 +185,15 @@ __device__ __noinline__ uint64_t eval_fp64(const PocketDev* Pp, const lds_double
     const lds_double* Xx = X;
     const lds_double* Xy = X + lp;
     const lds_double* Xz = X + 2 * lp;
-    int S = 0, oob = 0;
+    long long S = 0;
+    int oob = 0;
     for (int j = lane; j < m; j += kWave) {
         int i = ldg(mvl + j);
         double yx, yy, yz;
         rotate_about(px, py, pz, R, Xx[i], Xy[i], Xz[i], yx, yy, yz);
         S += D_exact(P, yx, yy, yz, oob);
     }
-    S = wave_sum(S);
+    S = wave_sum64(S);
     bool clash = false;
     for (int q = lane; q < npairs; q += kWave) {
         uint16_t pr = ldg(pairs + q);
@@ -179,7 +204,7 @@ __device__ __noinline__ uint64_t eval_fp64(const PocketDev* Pp, const lds_double
         clash |= dist2(yx, yy, yz, Xx[fx], Xy[fx], Xz[fx]) < cd2;
     }
     clash = __ballot(clash) != 0;
-    return (uint64_t)(uint32_t)S | ((uint64_t)(!clash) << 32) | ((uint64_t)(uint32_t)oob << 40);
+    return (uint64_t)S | ((uint64_t)(!clash) << 40) | ((uint64_t)(uint32_t)oob << 41);
 }
 
 // An atom within the guard of a cell face, or outside the tabulated grid,
@@ -189,16 +214,18 @@ constexpr int kOpenHi = 0x20000000;
 
 // FP32 coefficients of d^2(theta) = A + 2 B cos(theta) + 2 C sin(theta) for a
 // straddling pair (li on the left, ri on the right) in the frame of the
-// current sweep, from the per-atom data u = X - p, k.u, k x u, |u|^2:
-//   A = |u_l|^2 + |u_r|^2 - 2 (k.u_l)(k.u_r),   B = (k.u_l)(k.u_r) - u_l.u_r,
+// current sweep, from the per-atom data u = X - p, z = k.u, k x u and
+// rho = |k x u| (axial and radial coordinates about the rotamer's axis):
+//   A = (z_l - z_r)^2 + rho_l^2 + rho_r^2  (= |u_l|^2 + |u_r|^2 - 2 z_l z_r),
+//   B = z_l z_r - u_l.u_r,
 //   C = -(k x u_l).u_r when the left side turns; turning the right side
 //   instead flips the sign of C (csign = -1 left, +1 right).
 __device__ __forceinline__ f4 pair_coeffs_from(f4 ul, f4 wl, f4 ur, f4 wr, float csign) {
-    const float kk = ul.w * ur.w;
-    const float A = fmaf(-2.f, kk, wl.w + wr.w);
+    const float dz = ul.w - ur.w;
+    const float A = fmaf(dz, dz, fmaf(wl.w, wl.w, wr.w * wr.w));
     const float uv = fmaf(ul.z, ur.z, fmaf(ul.y, ur.y, ul.x * ur.x));
     const float vw = fmaf(ur.z, wl.z, fmaf(ur.y, wl.y, ur.x * wl.x));
-    return mk4(A, kk - uv, csign * vw, 0.f);
+    return mk4(A, fmaf(ul.w, ur.w, -uv), csign * vw, 0.f);
 }
 
 __device__ __forceinline__ f4 pair_coeffs(const WaveLds& W, uint32_t pr, float csign) {
@@ -206,18 +233,23 @@ __device__ __forceinline__ f4 pair_coeffs(const WaveLds& W, uint32_t pr, float c
     return pair_coeffs_from(W.AD[2 * li], W.AD[2 * li + 1], W.AD[2 * ri], W.AD[2 * ri + 1], csign);
 }
 
-// Per-atom sweep data of atom i: (u, k.u) and (k x u, |u|^2) with u = X_i - p,
-// in FP64 and rounded once to FP32 (the values the set-up stores in W.AD).
+// Per-atom sweep data of atom i (the values the set-up stores in W.AD):
+// (u, z) and (k x u, rho) with u = X_i - p, z = k.u and rho = |k x u|.  u, z
+// and k x u are formed in FP64 and rounded once to FP32; rho is the FP32 norm
+// of the rounded k x u (v_sqrt_f32, 1 ulp), within 5 u rho of the exact one
+// (u = 2^-24).
 struct Frame {
     double kx, ky, kz, px, py, pz;
 };
 
 __device__ __forceinline__ void atom_data(const WaveLds& W, int lp, const Frame& f, int i, f4& a0, f4& a1) {
     const double ux = W.X[i] - f.px, uy = W.X[lp + i] - f.py, uz = W.X[2 * lp + i] - f.pz;
-    const double ku = f.kx * ux + f.ky * uy + f.kz * uz;
-    const double uu = ux * ux + uy * uy + uz * uz;
+    const double ku = fma(f.kz, uz, fma(f.ky, uy, f.kx * ux));
+    const float wx = (float)fma(f.ky, uz, -f.kz * uy), wy = (float)fma(f.kz, ux, -f.kx * uz),
+                wz = (float)fma(f.kx, uy, -f.ky * ux);
+    const float rho = __builtin_amdgcn_sqrtf(fmaf(wz, wz, fmaf(wy, wy, wx * wx)));
     a0 = mk4((float)ux, (float)uy, (float)uz, (float)ku);
-    a1 = mk4((float)(f.ky * uz - f.kz * uy), (float)(f.kz * ux - f.kx * uz), (float)(f.kx * uy - f.ky * ux), (float)uu);
+    a1 = mk4(wx, wy, wz, rho);
 }
 
 // K pairs per lane starting at q0 (lanes = straddling pairs), then for each
@@ -296,7 +328,7 @@ __device__ __forceinline__ int group_sum(int v) {
 }
 
 template <int NB, bool BOX>
-__device__ __forceinline__ void score_pass(const PocketDev& P, const Sweep& sw, const WaveLds& W, const lds_float* trig,
+__device__ __forceinline__ void score_pass(const PocketDev& P, const Sweep& sw, const WaveLds& W, const float* trig,
                                            int base, int stride, int n) {
     constexpr int G = kWave / NB;
     constexpr int KANG = NB == 8 ? 4 : NB == 16 ? 2 : 1;
@@ -319,8 +351,8 @@ __device__ __forceinline__ void score_pass(const PocketDev& P, const Sweep& sw, 
         for (int a = 0; a < KANG; a++) {
             const int k = kb + k0 + NB * a;
             const int deg = base + ((a < A) & (k < n) ? k : 0) * stride;
-            c[a] = trig[deg];
-            s[a] = trig[360 + deg];
+            c[a] = ldg(trig + deg);
+            s[a] = ldg(trig + 360 + deg);
         }
         int sum[KANG];
         uint64_t badm[KANG];
@@ -329,20 +361,21 @@ __device__ __forceinline__ void score_pass(const PocketDev& P, const Sweep& sw, 
             sum[a] = 0;
             badm[a] = 0;
         }
-        const lds_float4* row = W.MV + 3 * g;
-        for (int j = g; j < m; j += KATU * G, row += 3 * KATU * G) {
+        for (int j = g; j < m; j += KATU * G) {
             uint32_t off[KATU][KANG];
 #pragma unroll
             for (int t = 0; t < KATU; t++) {
-                const f4 p0 = row[3 * t * G], u = row[3 * t * G + 1], v = row[3 * t * G + 2];
-                const bool live = BOX ? (j + t * G < m) : true;
+                const int r = j + t * G;  // at most m + KATU * G - 2: within the sentinel rows
+                const f4 ra = W.MVa[r], rb = W.MVb[r];
+                const float rc = W.MVc[r];
+                const bool live = BOX ? (r < m) : true;
 #pragma unroll
                 for (int a = 0; a < KANG; a++) {
                     off[t][a] = 0;
                     if (a < A) {
-                        const float yx = fmaf(s[a], v.x, fmaf(c[a], u.x, p0.x));
-                        const float yy = fmaf(s[a], v.y, fmaf(c[a], u.y, p0.y));
-                        const float yz = fmaf(s[a], v.z, fmaf(c[a], u.z, p0.z));
+                        const float yx = fmaf(s[a], rb.z, fmaf(c[a], ra.w, ra.x));
+                        const float yy = fmaf(s[a], rb.w, fmaf(c[a], rb.x, ra.y));
+                        const float yz = fmaf(s[a], rc, fmaf(c[a], rb.y, ra.z));
                         const float fx = floorf(yx), fy = floorf(yy), fz = floorf(yz);
                         const float rx = __builtin_amdgcn_fractf(yx), ry = __builtin_amdgcn_fractf(yy),
                                     rz = __builtin_amdgcn_fractf(yz);
@@ -387,7 +420,7 @@ __device__ __forceinline__ void score_pass(const PocketDev& P, const Sweep& sw, 
 // on ties) or -1 when none is feasible.
 template <int NB, int PPL>
 __device__ int eval_candidates(const PocketDev& P, const BatchDev& B, const Sweep& sw, const WaveLds& W,
-                               const lds_float* trig, int base, int stride, int n, Acc& acc) {
+                               const float* trig, int base, int stride, int n, Acc& acc) {
     const int lane = lane_id();
     constexpr int G = kWave / NB;
     acc.poses += n;
@@ -407,17 +440,18 @@ __device__ int eval_candidates(const PocketDev& P, const BatchDev& B, const Swee
         for (int w0 = 0; w0 < n; w0 += kWave) {
             const int k = w0 + lane;
             const int deg = base + (k < n ? k : 0) * stride;
-            const float c = 2.f * trig[deg], s = 2.f * trig[360 + deg];
+            const float c = 2.f * ldg(trig + deg), s = 2.f * ldg(trig + 360 + deg);
             float d0 = 3.0e38f, d1 = 3.0e38f;
             int q = 0;
             for (; q + 1 < sw.nsurv; q += 2) {
-                const f4 e0 = W.surv[q], e1 = W.surv[q + 1];
-                d0 = fminf(d0, fmaf(e0.z, s, fmaf(e0.y, c, e0.x)));
-                d1 = fminf(d1, fmaf(e1.z, s, fmaf(e1.y, c, e1.x)));
+                const f2 e0 = W.survBC[q], e1 = W.survBC[q + 1];
+                const float a0 = W.survA[q], a1 = W.survA[q + 1];
+                d0 = fminf(d0, fmaf(e0.y, s, fmaf(e0.x, c, a0)));
+                d1 = fminf(d1, fmaf(e1.y, s, fmaf(e1.x, c, a1)));
             }
             if (q < sw.nsurv) {
-                const f4 e0 = W.surv[q];
-                d0 = fminf(d0, fmaf(e0.z, s, fmaf(e0.y, c, e0.x)));
+                const f2 e0 = W.survBC[q];
+                d0 = fminf(d0, fmaf(e0.y, s, fmaf(e0.x, c, W.survA[q])));
             }
             const float d = fminf(d0, d1);
             if (k < n) W.st[k] = (uint8_t)((d < sw.thr_lo ? 1 : 0) | (d < sw.thr_hi ? 2 : 0));
@@ -428,8 +462,8 @@ __device__ int eval_candidates(const PocketDev& P, const BatchDev& B, const Swee
             float cl = 0.f, sl = 0.f;
             if (lane < nw) {
                 int deg = base + (w0 + lane) * stride;
-                cl = 2.f * trig[deg];
-                sl = 2.f * trig[360 + deg];
+                cl = 2.f * ldg(trig + deg);
+                sl = 2.f * ldg(trig + 360 + deg);
             }
             uint64_t cert = 0, maybe = 0;
             const int nq = sw.npairs;
@@ -443,26 +477,31 @@ __device__ int eval_candidates(const PocketDev& P, const BatchDev& B, const Swee
     }
     wave_sync();
 
-    // ---- decision: key = S << 9 | position (S of at most 128 moving atoms of
-    // D <= 65535 is below 2^23; a schedule has at most 360 positions): the
-    // lowest certain key, then the uncertain contenders whose lower bound could
-    // still win, re-evaluated in FP64 in position order
-    static_assert(kMaxAtoms * 65535 < (1 << 23), "moving-atom S must fit 23 bits");
-    uint32_t best = 0xffffffffu;
+    // ---- decision: key = S << 9 | position (a schedule has at most 360
+    // positions).  The certain candidates' S comes from in-box cells only (at
+    // most 128 moving atoms of D <= 65535, below 2^23), so their keys fit 32
+    // bits; an FP64 re-evaluation may score atoms far outside the box (S below
+    // 2^38), so the running best is a 64-bit key.  The lowest certain key
+    // first, then the uncertain contenders whose lower bound could still win,
+    // re-evaluated in FP64 in position order.
+    static_assert(kMaxAtoms * 65535 < (1 << 23), "in-box moving-atom S must fit 23 bits");
+    uint32_t best32 = 0xffffffffu;
     for (int k0 = 0; k0 < n; k0 += kWave) {
         const int k = k0 + lane;
         if (k < n) {
             const int lo = W.Slo[k], hi = W.Shi[k];
-            if (!(W.st[k] & 2) && lo == hi) best = min(best, ((uint32_t)lo << 9) | (uint32_t)k);
+            if (!(W.st[k] & 2) && lo == hi) best32 = min(best32, ((uint32_t)lo << 9) | (uint32_t)k);
         }
     }
-    best = wave_min_u32(best);
+    best32 = wave_min_u32(best32);
+    const uint64_t kNone = ~0ull;
+    uint64_t best = best32 == 0xffffffffu ? kNone : (uint64_t)best32;
     for (int k0 = 0; k0 < n; k0 += kWave) {
         const int k = k0 + lane;
         bool need = false;
         if (k < n) {
             const int st = W.st[k], lo = W.Slo[k], hi = W.Shi[k];
-            need = !(st & 1) && ((st & 2) || lo != hi) && (((uint32_t)lo << 9) | (uint32_t)k) < best;
+            need = !(st & 1) && ((st & 2) || lo != hi) && ((((uint64_t)(uint32_t)lo) << 9) | (uint64_t)k) < best;
         }
         uint64_t mask = __ballot(need);
         while (mask) {
@@ -472,12 +511,13 @@ __device__ int eval_candidates(const PocketDev& P, const BatchDev& B, const Swee
             const uint64_t r = eval_fp64(&P, W.X, W.SW, sw.lp, sw.mvl, sw.m, sw.pairs, sw.npairs, sw.side, B.cd2,
                                          base + kk * stride);
             acc.fallback++;
-            acc.oob += (int)(r >> 40);
-            if ((r >> 32) & 1) best = min(best, ((uint32_t)r << 9) | (uint32_t)kk);
+            acc.oob += (int)(r >> 41);
+            const uint64_t S = r & ((1ull << 40) - 1);
+            if ((r >> 40) & 1) best = min(best, (S << 9) | (uint64_t)kk);
         }
     }
     wave_sync();
-    return best == 0xffffffffu ? -1 : (int)(best & 511u);
+    return best == kNone ? -1 : (int)(best & 511u);
 }
 
 // Axis k = (X_c - X_a)/|X_c - X_a| and pivot of one fragment sweep (FP64,
@@ -485,23 +525,19 @@ __device__ int eval_candidates(const PocketDev& P, const BatchDev& B, const Swee
 // rotamer follows its left side: the left commit leaves X_a exactly in place
 // (p + R 0 = p) and does not move X_c, so the axis in W.SW is already the
 // bit-exact result and only the pivot changes (keep_axis).
+// Lanes 0-2 hold one component each, so the three divisions are one.
 __device__ __forceinline__ void sweep_axis(const WaveLds& W, int lp, int a, int c, int piv, bool keep_axis) {
-    if (lane_id() == 0) {
-        const lds_double* Xx = W.X;
-        const lds_double* Xy = W.X + lp;
-        const lds_double* Xz = W.X + 2 * lp;
-        if (!keep_axis) {
-            double ax = Xx[c] - Xx[a], ay = Xy[c] - Xy[a], az = Xz[c] - Xz[a];
-            double nrm = sqrt(ax * ax + ay * ay + az * az);
-            W.SW[0] = ax / nrm;
-            W.SW[1] = ay / nrm;
-            W.SW[2] = az / nrm;
-            W.SW[6] = nrm;
-        }
-        W.SW[3] = Xx[piv];
-        W.SW[4] = Xy[piv];
-        W.SW[5] = Xz[piv];
+    const int lane = lane_id();
+    const int comp = lane < 3 ? lane : 0;
+    if (!keep_axis) {
+        const double d = W.X[comp * lp + c] - W.X[comp * lp + a];
+        const double ax = readlane_d(d, 0), ay = readlane_d(d, 1), az = readlane_d(d, 2);
+        const double nrm = sqrt(ax * ax + ay * ay + az * az);
+        const double k = d / nrm;
+        if (lane < 3) W.SW[lane] = k;
+        if (lane == 0) W.SW[6] = nrm;
     }
+    if (lane < 3) W.SW[3 + lane] = W.X[comp * lp + piv];
     wave_sync();
 }
 
@@ -515,17 +551,17 @@ struct SideInfo {
 
 __device__ __forceinline__ SideInfo side_info(const RotInfo* rp, int side) {
     SideInfo si;
-    si.a = ldg(&rp->a);
-    si.c = ldg(&rp->c);
+    si.a = ldc(&rp->a);
+    si.c = ldc(&rp->c);
     si.piv = side == 0 ? si.a : si.c;
-    si.pair_off = ldg(&rp->pair_off);
-    si.n_pairs = ldg(&rp->n_pairs);
-    si.mv_off = ldg(rp->mv_off + side);
-    si.n_mv = ldg(rp->n_mv + side);
-    si.mode = ldg(rp->mode + side);
-    si.step = ldg(rp->step + side);
-    si.tile = ldg(rp->tile + side);
-    si.off = ldg(rp->off + side);
+    si.pair_off = ldc(&rp->pair_off);
+    si.n_pairs = ldc(&rp->n_pairs);
+    si.mv_off = ldc(rp->mv_off + side);
+    si.n_mv = ldc(rp->n_mv + side);
+    si.mode = ldc(rp->mode + side);
+    si.step = ldc(rp->step + side);
+    si.tile = ldc(rp->tile + side);
+    si.off = ldc(rp->off + side);
     return si;
 }
 
@@ -547,7 +583,7 @@ __device__ __forceinline__ void sweep_setup(const PocketDev& P, const BatchDev& 
     const double kx = uniform_d(W.SW[0]), ky = uniform_d(W.SW[1]), kz = uniform_d(W.SW[2]);
     const double px = uniform_d(W.SW[3]), py = uniform_d(W.SW[4]), pz = uniform_d(W.SW[5]);
 
-    // per-atom data of every atom, for the pair coefficients
+    // per-atom data of every atom, for the prune and the pair coefficients
     const Frame fr{kx, ky, kz, px, py, pz};
     float r2max = 0.f;
     for (int i = lane; i < L.l; i += kWave) {
@@ -555,46 +591,49 @@ __device__ __forceinline__ void sweep_setup(const PocketDev& P, const BatchDev& 
         atom_data(W, lp, fr, i, a0, a1);
         W.AD[2 * i] = a0;
         W.AD[2 * i + 1] = a1;
-        r2max = fmaxf(r2max, a1.w);
+        r2max = fmaxf(r2max, fmaf(a0.w, a0.w, a1.w * a1.w));  // |u|^2 = z^2 + rho^2
     }
     r2max = wave_maxf(r2max);
     // Rounding guards (u = 2^-24), each doubled for safety and with the maxima
     // rounded up by 1 %:
     //  cell: Y = fma(s, V, fma(c, U, P0)) from P0, U, V rounded once from FP64
     //        deviates by <= u (3|P0| + 4|U| + 3|V|) cell units;
-    //  bump: A, 2B, 2C formed in FP32 from per-atom data rounded from FP64
-    //        (|u| <= R) carry <= 18, 20 and 10 u R^2; their evaluation with
-    //        the rounded cos/sin adds <= u (3|A| + 4|2B| + 3|2C|) <= 26 u R^2:
-    //        74 u R^2 in all.
+    //  bump: with every per-atom value within 5 u R of its exact one (|u| <=
+    //        R), A = dz^2 + rho_l^2 + rho_r^2, 2B and 2C formed in FP32 carry
+    //        <= 45, 18 and 10 u R^2; their evaluation with the rounded cos/sin
+    //        adds <= u (3|A| + 4|2B| + 3|2C|) <= 26 u R^2: 99 u R^2 in all.
     const double u32 = 1.0 / 16777216.0;
-    const double gc = 2.0 * u32 * 74.0 * 1.01 * (double)r2max + 1e-6;
+    const double gc = 2.0 * u32 * 100.0 * 1.01 * (double)r2max + 1e-6;
     sw.thr_lo = (float)(B.cd2 - gc);
     sw.thr_hi = (float)(B.cd2 + gc);
     wave_sync();
-    // Prune: a pair whose smallest d^2 over a full turn, A - 2 sqrt(B^2 + C^2),
-    // clears the bump distance by more than twice the guard never bumps.
+    // Prune: over a full turn the pair's smallest d^2, A - 2 sqrt(B^2 + C^2),
+    // is the squared distance of the two atoms in the (axial, radial) plane,
+    // (z_l - z_r)^2 + (rho_l - rho_r)^2 (the radial parts' dot and cross
+    // products are B and C); a pair for which it clears the bump distance by
+    // more than twice the guard never bumps.
     //
-    // That smallest d^2 depends only on the two atoms' radial and axial
-    // coordinates about the rotamer's axis, which neither the left commit nor
-    // the change of pivot along the axis alters, so the right sweep reuses the
-    // left sweep's survivors (left_nsurv >= 0) and only recomputes their
-    // coefficients.  For that the left prune clears twice the larger of its own
-    // guard and a bound on the right one (R_right <= R_left + |X_c - X_a|):
-    // the computed A - 2 sqrt(B^2 + C^2) errs by less than a third of a guard,
-    // and an evaluation by half a guard, so an excluded pair stays above
-    // cd^2 + guard at every angle of either sweep.
+    // It depends only on the two atoms' radial and axial coordinates about the
+    // rotamer's axis, which neither the left commit nor the change of pivot
+    // along the axis alters, so the right sweep reuses the left sweep's
+    // survivors (left_nsurv >= 0) and only recomputes their coefficients.  For
+    // that the left prune clears twice the larger of its own guard and a bound
+    // on the right one (R_right <= R_left + |X_c - X_a|): the computed squared
+    // distance errs by <= 44 u R^2, less than half a guard, and an evaluation
+    // by half a guard, so an excluded pair stays above cd^2 + guard at every
+    // angle of either sweep.
     const float csign = side == 0 ? -1.f : 1.f;
     int nsurv = 0;
     if (left_nsurv >= 0) {
         nsurv = left_nsurv;
-        for (int q = lane; q < nsurv; q += kWave) W.surv[q] = pair_coeffs(W, W.surv_pr[q], csign);
     } else {
         double gp = gc;
         if (side == 0) {
             const double Rr = sqrt(1.01 * (double)r2max) + uniform_d(W.SW[6]);
-            gp = fmax(gp, 2.0 * u32 * 74.0 * 1.01 * Rr * Rr + 1e-6);
+            gp = fmax(gp, 2.0 * u32 * 100.0 * 1.01 * Rr * Rr + 1e-6);
         }
         const float T = (float)(B.cd2 + 2.0 * gp);
+        const lds_float* zr = (const lds_float*)W.AD;  // z of atom i at 8 i + 3, rho at 8 i + 7
         for (int q0 = 0; q0 < sw.npairs; q0 += 4 * kWave) {
             uint16_t prs[4];
 #pragma unroll
@@ -605,68 +644,68 @@ __device__ __forceinline__ void sweep_setup(const PocketDev& P, const BatchDev& 
 #pragma unroll
             for (int t = 0; t < 4; t++) {
                 const int q = q0 + t * kWave + lane;
-                bool keep = false;
-                f4 e = mk4(0.f, 0.f, 0.f, 0.f);
-                if (q < sw.npairs) {
-                    e = pair_coeffs(W, prs[t], csign);
-                    const float Am = e.x - T;
-                    keep = !((Am > 0.f) & (Am * Am > 4.0004f * fmaf(e.z, e.z, e.y * e.y)));
-                }
+                const int li = prs[t] & 0xff, ri = prs[t] >> 8;
+                const float dz = zr[8 * li + 3] - zr[8 * ri + 3], dr = zr[8 * li + 7] - zr[8 * ri + 7];
+                const bool keep = (q < sw.npairs) & (fmaf(dz, dz, dr * dr) < T);
                 const uint64_t mk = __ballot(keep);
                 const int pos = nsurv + __builtin_amdgcn_mbcnt_hi((uint32_t)(mk >> 32),
                                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0));
-                if (keep && pos < kSurvCap) {
-                    W.surv[pos] = e;
-                    W.surv_pr[pos] = prs[t];
-                }
+                if (keep && pos < kSurvCap) W.surv_pr[pos] = prs[t];
                 nsurv += __popcll(mk);
             }
         }
+        wave_sync();
+    }
+    // coefficients of the survivors in this sweep's frame
+    for (int q = lane; q < min(nsurv, kSurvCap); q += kWave) {
+        const f4 e = pair_coeffs(W, W.surv_pr[q], csign);
+        W.survA[q] = e.x;
+        W.survBC[q] = f2{e.y, e.z};
     }
     sw.nsurv = nsurv;
     sw.pruned = nsurv <= kSurvCap;
     // moving-atom rows for the score pass, over the memory of the per-atom data
-    // (no longer read: the prune is done)
+    // (no longer read: the prune and the coefficients are done).  Cell units,
+    // box-relative: P0 = (p + z k) / h - lo, U = (u - z k) / h, V = (k x u) / h.
     wave_sync();
-    float amax = 0.f, umax = 0.f;
-    bool outside = false;
     const double ih = P.inv_h;
-    const double bx = (double)P.dim[0] - 0.01, by = (double)P.dim[1] - 0.01, bz = (double)P.dim[2] - 0.01;
+    const double kxh = kx * ih, kyh = ky * ih, kzh = kz * ih;  // exact: h is a power of two
+    const double qx = px * ih - (double)P.lo[0], qy = py * ih - (double)P.lo[1], qz = pz * ih - (double)P.lo[2];
+    const float ex = (float)P.dim[0] - 0.01f, ey = (float)P.dim[1] - 0.01f, ez = (float)P.dim[2] - 0.01f;
+    float gterm = 0.f;
+    bool outside = false;
     for (int j = lane; j < sw.m; j += kWave) {
-        int i = ldg(sw.mvl + j);
-        double ux = Xx[i] - px, uy = Xy[i] - py, uz = Xz[i] - pz;
-        double ku = kx * ux + ky * uy + kz * uz;
-        double ax0 = (px + ku * kx) * ih - (double)P.lo[0];
-        double ay0 = (py + ku * ky) * ih - (double)P.lo[1];
-        double az0 = (pz + ku * kz) * ih - (double)P.lo[2];
-        double Ux = (ux - ku * kx) * ih, Uy = (uy - ku * ky) * ih, Uz = (uz - ku * kz) * ih;
-        double Vx = (ky * uz - kz * uy) * ih, Vy = (kz * ux - kx * uz) * ih, Vz = (kx * uy - ky * ux) * ih;
-        W.MV[3 * j] = mk4((float)ax0, (float)ay0, (float)az0, 0.f);
-        W.MV[3 * j + 1] = mk4((float)Ux, (float)Uy, (float)Uz, 0.f);
-        W.MV[3 * j + 2] = mk4((float)Vx, (float)Vy, (float)Vz, 0.f);
-        // the circle's extent along axis a is P0_a +- sqrt(U_a^2 + V_a^2): keep it
-        // 0.01 cell inside the box on both sides
-        const double ex2 = Ux * Ux + Vx * Vx, ey2 = Uy * Uy + Vy * Vy, ez2 = Uz * Uz + Vz * Vz;
-        const double lx = ax0 - 0.01, ly = ay0 - 0.01, lz = az0 - 0.01;
-        const double hx = bx - ax0, hy = by - ay0, hz = bz - az0;
-        outside |= !(lx >= 0.0 && ly >= 0.0 && lz >= 0.0 && hx >= 0.0 && hy >= 0.0 && hz >= 0.0 && ex2 <= lx * lx &&
-                     ey2 <= ly * ly && ez2 <= lz * lz && ex2 <= hx * hx && ey2 <= hy * hy && ez2 <= hz * hz);
-        amax = fmaxf(amax, (float)fmax(fabs(ax0), fmax(fabs(ay0), fabs(az0))));
-        umax = fmaxf(umax, (float)fmax(fmax(fabs(Ux), fmax(fabs(Uy), fabs(Uz))),
-                                       fmax(fabs(Vx), fmax(fabs(Vy), fabs(Vz)))));
+        const int i = ldg(sw.mvl + j);
+        const double ux = Xx[i] - px, uy = Xy[i] - py, uz = Xz[i] - pz;
+        const double ku = fma(kz, uz, fma(ky, uy, kx * ux));
+        const float ax0 = (float)fma(ku, kxh, qx), ay0 = (float)fma(ku, kyh, qy), az0 = (float)fma(ku, kzh, qz);
+        const float Ux = (float)fma(-ku, kxh, ux * ih), Uy = (float)fma(-ku, kyh, uy * ih),
+                    Uz = (float)fma(-ku, kzh, uz * ih);
+        const float Vx = (float)fma(kyh, uz, -kzh * uy), Vy = (float)fma(kzh, ux, -kxh * uz),
+                    Vz = (float)fma(kxh, uy, -kyh * ux);
+        W.MVa[j] = mk4(ax0, ay0, az0, Ux);
+        W.MVb[j] = mk4(Uy, Uz, Vx, Vy);
+        W.MVc[j] = Vz;
+        // the atom's circle lies in the ball of radius |U| (= |V|) about P0:
+        // keep that ball 0.01 cell inside the box on every side (the FP32
+        // test errs by far less than the margin)
+        const float r = __builtin_amdgcn_sqrtf(fmaf(Uz, Uz, fmaf(Uy, Uy, Ux * Ux)));
+        const float lo = fminf(fminf(ax0, ay0), az0) - r;
+        const float hi = fmaxf(fmaxf(ax0 - ex, ay0 - ey), az0 - ez) + r;
+        outside |= !((lo >= 0.01f) & (hi <= 0.f));
+        // components of U and V are at most r
+        gterm = fmaxf(gterm, fmaf(3.f, fmaxf(fmaxf(fabsf(ax0), fabsf(ay0)), fabsf(az0)), 7.f * r));
     }
     sw.inside = __ballot(outside) == 0;
-    amax = wave_maxf(amax);
-    umax = wave_maxf(umax);
+    gterm = wave_maxf(gterm);
     // sentinel rows after the list: U = V = 0 at the centre of cell (0, 0, nz),
     // whose linear index is the zero sentinel cell
     if (lane < kMvPad) {
-        const f4 z4 = mk4(0.f, 0.f, 0.f, 0.f);
-        W.MV[3 * (sw.m + lane)] = mk4(0.5f, 0.5f, (float)P.dim[2] + 0.5f, 0.f);
-        W.MV[3 * (sw.m + lane) + 1] = z4;
-        W.MV[3 * (sw.m + lane) + 2] = z4;
+        W.MVa[sw.m + lane] = mk4(0.5f, 0.5f, (float)P.dim[2] + 0.5f, 0.f);
+        W.MVb[sw.m + lane] = mk4(0.f, 0.f, 0.f, 0.f);
+        W.MVc[sw.m + lane] = 0.f;
     }
-    sw.gcell = (float)(2.0 * u32 * (3.0 * 1.01 * amax + 7.0 * 1.01 * umax) + 1e-6);
+    sw.gcell = (float)(2.0 * u32 * 1.01 * (double)gterm + 1e-6);
 
     wave_sync();
 }
@@ -696,7 +735,7 @@ __device__ __forceinline__ void commit(const uint8_t* mvl, int m, const WaveLds&
 __device__ void place(const PocketDev& P, const BatchDev& B, const LigMeta& L, int o, const WaveLds& W) {
     const int lane = lane_id();
     const int lp = lds_pitch(B.lmax);
-    const __attribute__((address_space(1))) double* R = (const __attribute__((address_space(1))) double*)(B.qmat + 9 * (size_t)o);
+    const __attribute__((address_space(4))) double* R = (const __attribute__((address_space(4))) double*)(B.qmat + 9 * (size_t)o);
     for (int i = lane; i < L.l; i += kWave) {
         double d0 = (double)ldg(B.x + L.atom_off + i) - L.cL[0];
         double d1 = (double)ldg(B.y + L.atom_off + i) - L.cL[1];
@@ -716,9 +755,9 @@ __device__ __forceinline__ void endpoint(const PocketDev& P, const BatchDev& B, 
     const lds_double* Xx = W.X;
     const lds_double* Xy = W.X + lp;
     const lds_double* Xz = W.X + 2 * lp;
-    int s = 0;
+    long long s = 0;
     for (int i = lane; i < L.l; i += kWave) s += D_exact(P, Xx[i], Xy[i], Xz[i], acc.oob);
-    S = wave_sum(s);
+    S = sat_S(wave_sum64(s));
     // whole-ligand bump flag: any far pair closer than the bump distance (the
     // scan stops at the first word of pairs that holds one)
     const uint16_t* fp = B.efar + L.far_off;
@@ -739,8 +778,8 @@ __device__ __forceinline__ void endpoint(const PocketDev& P, const BatchDev& B, 
 // The greedy sweep of one orientation (Alg. 2).
 template <int NB, int PPL>
 __device__ void dock_orientation(const PocketDev& P, const BatchDev& B, int lig, int o, const WaveLds& W,
-                                 const lds_float* trig, Acc& acc) {
-    const LigMeta L = ldg_record(B.lig + lig);
+                                 const float* trig, Acc& acc) {
+    const LigMeta L = ldc_record(B.lig + lig);
     place(P, B, L, o, W);
     const int nrec = B.reps * L.nr * 2;
     uint16_t* ang = B.ang + L.ang_off + (size_t)o * nrec;
@@ -801,17 +840,11 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) d
     const PocketDev& P = *Pp;
     const BatchDev& B = *Bp;
     extern __shared__ __align__(16) char smem[];
-    __shared__ float trig[720];  // FP32 cos, then sin, of integer degrees
-    for (int d = threadIdx.x; d < 360; d += blockDim.x) {
-        trig[d] = c_cos32[d];
-        trig[360 + d] = c_sin32[d];
-    }
-    __syncthreads();
     const int wave = threadIdx.x / kWave;
     const WaveLds W = carve(smem + wave * wave_lds_bytes(B.lmax, nmax), B.lmax, nmax);
     const int o = uniform(blockIdx.x * (blockDim.x / kWave) + wave);
     Acc acc;
-    if (o < B.n_orient) dock_orientation<NB, PPL>(P, B, lig, o, W, (const lds_float*)trig, acc);
+    if (o < B.n_orient) dock_orientation<NB, PPL>(P, B, lig, o, W, c_trig32, acc);
     flush(counters, acc);
 }
 
@@ -824,12 +857,6 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) d
     const PocketDev& P = *Pp;
     const BatchDev& B = *Bp;
     extern __shared__ __align__(16) char smem[];
-    __shared__ float trig[720];  // FP32 cos, then sin, of integer degrees
-    for (int d = threadIdx.x; d < 360; d += blockDim.x) {
-        trig[d] = c_cos32[d];
-        trig[360 + d] = c_sin32[d];
-    }
-    __syncthreads();
     const int wave = threadIdx.x / kWave;
     const WaveLds W = carve(smem + wave * wave_lds_bytes(B.lmax, nmax), B.lmax, nmax);
     Acc acc;
@@ -838,9 +865,9 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) d
         if (lane_id() == 0) item = atomicAdd(B.head, 1);
         item = uniform(__shfl(item, 0));
         if (item >= B.n_items) break;
-        const int lig = uniform(ldg(B.items + 2 * item)), o0 = uniform(ldg(B.items + 2 * item + 1));
+        const int lig = ldc(B.items + 2 * item), o0 = ldc(B.items + 2 * item + 1);
         const int o1 = min(o0 + B.orient_per_item, B.n_orient);
-        for (int o = o0; o < o1; o++) dock_orientation<NB, PPL>(P, B, lig, o, W, (const lds_float*)trig, acc);
+        for (int o = o0; o < o1; o++) dock_orientation<NB, PPL>(P, B, lig, o, W, c_trig32, acc);
     }
     flush(counters, acc);
 }
@@ -995,19 +1022,20 @@ __global__ void __launch_bounds__(256) profile_kernel(const PocketDev* Pp, Batch
             const SideInfo si = side_info(B.rot + L.rot_off + r, side);
             sweep_axis(W, lp, si.a, si.c, si.piv, false);
             const uint8_t* mvl = B.mv + si.mv_off;
-            int oob = 0, s_all = 0, s_mv = 0;
+            int oob = 0;
+            long long s_all = 0, s_mv = 0;
             for (int i = lane; i < L.l; i += kWave) s_all += D_exact(*Pp, W.X[i], W.X[lp + i], W.X[2 * lp + i], oob);
             for (int j = lane; j < si.n_mv; j += kWave) {
                 const int i = ldg(mvl + j);
                 s_mv += D_exact(*Pp, W.X[i], W.X[lp + i], W.X[2 * lp + i], oob);
             }
-            const int s_fixed = wave_sum(s_all) - wave_sum(s_mv);
+            const long long s_fixed = wave_sum64(s_all) - wave_sum64(s_mv);
             for (int t = 0; t < nang; t++) {
                 const uint64_t v = eval_fp64(Pp, W.X, W.SW, lp, mvl, si.n_mv, B.pairs + si.pair_off, si.n_pairs, side,
                                              B.cd2, t * step);
                 if (lane == 0) {
-                    So[t] = s_fixed + (int32_t)(uint32_t)v;
-                    fo[t] = (uint8_t)((v >> 32) & 1);
+                    So[t] = sat_S(s_fixed + (long long)(v & ((1ull << 40) - 1)));
+                    fo[t] = (uint8_t)((v >> 40) & 1);
                 }
             }
             if (lane == 0) size_out[row] = si.n_mv;
@@ -1026,8 +1054,12 @@ hipError_t upload_trig_tables() {
     hipError_t e;
     if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_cos64), c64, sizeof(c64))) != hipSuccess) return e;
     if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_sin64), s64, sizeof(s64))) != hipSuccess) return e;
-    if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_cos32), c32, sizeof(c32))) != hipSuccess) return e;
-    if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_sin32), s32, sizeof(s32))) != hipSuccess) return e;
+    float t32[720];
+    for (int d = 0; d < 360; d++) {
+        t32[d] = c32[d];
+        t32[360 + d] = s32[d];
+    }
+    if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_trig32), t32, sizeof(t32))) != hipSuccess) return e;
     done = true;
     return hipSuccess;
 }

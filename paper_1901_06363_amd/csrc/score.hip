@@ -19,14 +19,15 @@ __global__ void __launch_bounds__(256) score_kernel(PocketDev P, ScoreDev Sd, in
     const int off = Sd.pose_off[pose];
     const int l = Sd.n_atoms[lig];
     const float inv_h = (float)P.inv_h;
-    int oob = 0, s = 0;
+    int oob = 0;
+    long long s = 0;
     for (int i = lane; i < l; i += kWave) {
         int cx = (int)floorf(Sd.px[off + i] * inv_h) - P.lo[0];
         int cy = (int)floorf(Sd.py[off + i] * inv_h) - P.lo[1];
         int cz = (int)floorf(Sd.pz[off + i] * inv_h) - P.lo[2];
         s += D_box(P, cx, cy, cz, oob);
     }
-    s = wave_sum(s);
+    s = wave_sum64(s);
     bool c = false;
     const uint16_t* fp = Sd.efar + Sd.far_off[lig];
     const int nf = Sd.n_far[lig];
@@ -38,7 +39,7 @@ __global__ void __launch_bounds__(256) score_kernel(PocketDev P, ScoreDev Sd, in
     }
     c = __ballot(c) != 0;
     if (lane == 0) {
-        S_out[pose] = s;
+        S_out[pose] = sat_S(s);
         clash_out[pose] = (uint8_t)c;
     }
 }
