@@ -254,6 +254,29 @@ gd_status gd_score_poses(const gd_pocket* pocket, const gd_ligands* topo, int32_
                          const float* px, const float* py, const float* pz, float clash_dist,
                          int32_t clash_min_bonds, void* stream, int32_t* S_out, uint8_t* clash_out);
 
+/*
+ * gd_score_poses for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation).
+ * Same arguments, outputs and errors as gd_score_poses, plus
+ * GD_ERR_CAPACITY when the call's tables exceed GD_NOALLOC_SCRATCH_BYTES.
+ * The per-call tables (each pose's ligand and first row, the ligands' atom
+ * counts and far-pair lists, about 8 bytes per pose plus 12 per ligand plus
+ * 2 per far pair) are copied from host memory into a static device buffer of
+ * GD_NOALLOC_SCRATCH_BYTES that the library holds on every device it runs on
+ * until the process ends; the call makes no device allocation (host-side
+ * validation uses ordinary host memory).  Every call on one device uses that
+ * device's buffer, which keeps the last call's contents: calls that overlap
+ * on one device (several host threads, or a stream running a call while
+ * another call is enqueued on a different stream) race on it and must be
+ * serialised by the caller.  The copy and the scoring kernel are enqueued on
+ * `stream`.
+ */
+#define GD_NOALLOC_SCRATCH_BYTES (16u << 20)
+gd_status gd_score_poses_noalloc(const gd_pocket* pocket, const gd_ligands* topo, int32_t n_poses,
+                                 const int32_t* pose_lig, const float* px, const float* py, const float* pz,
+                                 float clash_dist, int32_t clash_min_bonds, void* stream, int32_t* S_out,
+                                 uint8_t* clash_out);
+
 /* ------------------------------------------------------------------------ */
 /* Overlap landscapes (peak analysis)                                        */
 

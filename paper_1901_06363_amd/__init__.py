@@ -15,8 +15,8 @@ import numpy as np
 from . import _abi
 from ._abi import GdError  # noqa: F401
 
-__all__ = ["Pocket", "Batch", "DockResult", "dock", "score_poses", "refine", "surrogate_fwd", "surrogate_bwd",
-           "SurrogateScore", "GdError", "lib_path"]
+__all__ = ["Pocket", "Batch", "DockResult", "dock", "score_poses", "score_poses_noalloc", "refine", "surrogate_fwd",
+           "surrogate_bwd", "SurrogateScore", "GdError", "lib_path"]
 
 PER_LIGAND, BATCHED = 0, 1
 CNT_POSES, CNT_FALLBACK, CNT_OOB, CNT_SWEEPS = 0, 1, 2, 3
@@ -230,4 +230,4 @@ def dock(pocket: Pocket, ligands, quats, mode=BATCHED, stream=None, **knobs) -> 
     return res
 
 
-from ._ops import score_poses, overlap_continuous, OverlapLayout, sweep_profile, refine, surrogate_fwd, surrogate_bwd, SurrogateScore  # noqa: E402,E501
+from ._ops import score_poses, score_poses_noalloc, overlap_continuous, OverlapLayout, sweep_profile, refine, surrogate_fwd, surrogate_bwd, SurrogateScore  # noqa: E402,E501

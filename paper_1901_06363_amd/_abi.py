@@ -77,6 +77,7 @@ SIGNATURES = [
     ("gd_dock_prepared", I32, [P, P, I32, P, P, P, P, P]),
     ("gd_dock_batch", I32, [P, P, P, I32, P, P, P, P, P]),
     ("gd_score_poses", I32, [P, P, I32, P, P, P, P, F32, I32, P, P, P]),
+    ("gd_score_poses_noalloc", I32, [P, P, I32, P, P, P, P, F32, I32, P, P, P]),
     ("gd_overlap_continuous", I32, [P, I32, P, ctypes.c_int64, P, P, P, P, P, P, P]),
     ("gd_sweep_profile", I32, [P, P, P, I32, P, P, P, P]),
     ("gd_surrogate_fwd", I32, [P, P, I32, P, P, P, P, P, P, P, I32, P, P, P]),

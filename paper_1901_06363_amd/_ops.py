@@ -99,6 +99,26 @@ def score_poses(pocket, ligands, pose_lig, px, py, pz, clash_dist=2.0, clash_min
     return S, clash
 
 
+def score_poses_noalloc(pocket, ligands, pose_lig, px, py, pz, S_out, clash_out, clash_dist=2.0, clash_min_bonds=4,
+                        stream=None):
+    """score_poses into caller-owned device outputs (int32 S_out, uint8
+    clash_out, one entry per pose) through the allocation-free entry point:
+    the call's tables are staged in the library's static device scratch."""
+    torch = _torch()
+    lg = _lig_desc(ligands)
+    pl, n_atoms, _ = _pose_layout(lg, pose_lig)
+    _check_coords(px, py, pz, n_atoms)
+    n = len(pl)
+    for name, t, dt in (("S_out", S_out, torch.int32), ("clash_out", clash_out, torch.uint8)):
+        if not isinstance(t, torch.Tensor) or t.dtype != dt or not t.is_cuda or not t.is_contiguous() or t.numel() < n:
+            raise ValueError("%s must be a contiguous %s CUDA tensor of at least %d elements" % (name, dt, n))
+    _abi.check(_abi.load().gd_score_poses_noalloc(pocket.handle, ctypes.byref(lg.desc), n,
+                                                  pl.ctypes.data_as(ctypes.c_void_p), _dp(px), _dp(py), _dp(pz),
+                                                  float(clash_dist), int(clash_min_bonds), _stream_ptr(stream),
+                                                  _dp(S_out), _dp(clash_out)))
+    return S_out, clash_out
+
+
 class OverlapLayout:
     """Device pose offsets of a fixed list of pose sizes, reusable across
     calls of overlap_continuous (no host-to-device copy per call)."""

@@ -59,6 +59,56 @@ gd_status score_poses(const gd_pocket* P, const gd_ligands* topo, int32_t n_pose
     return GD_OK;
 }
 
+// The same scoring with the call's tables staged in the library's static
+// device scratch (no device allocation).  The host tables are packed into one
+// buffer at 16-byte aligned offsets and copied with one stream-ordered copy.
+gd_status score_poses_noalloc(const gd_pocket* P, const gd_ligands* topo, int32_t n_poses, const int32_t* pose_lig,
+                              const float* px, const float* py, const float* pz, float clash_dist, int32_t min_bonds,
+                              hipStream_t s, int32_t* S_out, uint8_t* clash_out) {
+    const char* who = "gd_score_poses_noalloc";
+    if (!P || !topo || !S_out || !clash_out) return fail(GD_ERR_ARG, "%s: null argument", who);
+    if (n_poses > 0 && (!px || !py || !pz)) return fail(GD_ERR_ARG, "%s: null coordinates", who);
+    if (!(clash_dist >= 0.f) || clash_dist > 100.f) return fail(GD_ERR_ARG, "%s: bad clash_dist", who);
+    TopoHost T;
+    gd_status st;
+    if ((st = prepare_topology(topo, min_bonds, T)) != GD_OK) return st;
+    std::vector<int32_t> lig, off;
+    if ((st = pose_layout(topo, n_poses, pose_lig, T.n_atoms, lig, off)) != GD_OK) return st;
+    if (n_poses == 0) return GD_OK;
+    auto al = [](size_t b) { return (b + 15) & ~(size_t)15; };
+    const size_t b_lig = al(lig.size() * 4), b_off = al(off.size() * 4), b_nat = al(T.n_atoms.size() * 4),
+                 b_foff = al(T.far_off.size() * 4), b_nfar = al(T.n_far.size() * 4), b_efar = al(T.efar.size() * 2);
+    const size_t total = b_lig + b_off + b_nat + b_foff + b_nfar + b_efar;
+    if (total > kNoAllocScratch)
+        return fail(GD_ERR_CAPACITY, "%s: the call's tables take %zu bytes, the scratch holds %zu", who, total,
+                    (size_t)kNoAllocScratch);
+    void* base = nullptr;
+    hipError_t e = noalloc_scratch(&base);
+    if (e != hipSuccess) return hip_fail(e, who);
+    std::vector<uint8_t> host(total, 0);
+    size_t o = 0;
+    auto put = [&](const void* src, size_t n, size_t span) {
+        if (n) memcpy(host.data() + o, src, n);
+        const size_t at = o;
+        o += span;
+        return (const void*)((const uint8_t*)base + at);
+    };
+    ScoreDev D;
+    D.pose_lig = (const int32_t*)put(lig.data(), lig.size() * 4, b_lig);
+    D.pose_off = (const int32_t*)put(off.data(), off.size() * 4, b_off);
+    D.n_atoms = (const int32_t*)put(T.n_atoms.data(), T.n_atoms.size() * 4, b_nat);
+    D.far_off = (const int32_t*)put(T.far_off.data(), T.far_off.size() * 4, b_foff);
+    D.n_far = (const int32_t*)put(T.n_far.data(), T.n_far.size() * 4, b_nfar);
+    D.efar = (const uint16_t*)put(T.efar.data(), T.efar.size() * 2, b_efar);
+    D.px = px;
+    D.py = py;
+    D.pz = pz;
+    if ((e = hipMemcpyAsync(base, host.data(), total, hipMemcpyHostToDevice, s)) != hipSuccess) return hip_fail(e, who);
+    const double cd = (double)clash_dist;
+    if ((e = launch_score(P->dev, D, n_poses, cd * cd, S_out, clash_out, s)) != hipSuccess) return hip_fail(e, who);
+    return GD_OK;
+}
+
 // --------------------------------------------------------------------------
 // autotuner
 

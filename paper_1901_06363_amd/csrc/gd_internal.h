@@ -147,6 +147,11 @@ hipError_t launch_reset(int* head, unsigned long long* counters, hipStream_t s);
 hipError_t launch_topk(const BatchDev& B, gd_pose_rec* out, uint16_t* ang_out, double h, hipStream_t s);
 hipError_t launch_score(const PocketDev& P, const ScoreDev& S, int n_poses, double cd2, int32_t* S_out,
                         uint8_t* clash_out, hipStream_t s);
+// Allocation-free scoring: the static device scratch of GD_NOALLOC_SCRATCH_BYTES
+// and its address on the current device (score.hip).
+constexpr size_t kNoAllocScratch = GD_NOALLOC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
+hipError_t noalloc_scratch(void** out);
 // Bump penalty of the clash-penalised surrogate: w * sum over the ligand's far
 // pairs (from far_off) with d^2 < cd2 of (cd2 - d^2)^2; w = 0: none.
 struct Penalty {

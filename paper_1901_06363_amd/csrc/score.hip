@@ -4,6 +4,8 @@
 // distances are formed in FP64 from the widened coordinates.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "device_common.h"
 #include "gd_internal.h"
 
@@ -42,6 +44,33 @@ __global__ void __launch_bounds__(256) score_kernel(PocketDev P, ScoreDev Sd, in
         S_out[pose] = sat_S(s);
         clash_out[pose] = (uint8_t)c;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Device scratch of the allocation-free scoring call: one static array per
+// device the library runs on (each holds it until the process ends).  Host
+// code must not use the array's name as a device address; the per-device
+// address comes from hipGetSymbolAddress, taken once per device with that
+// device current.
+
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratch];
+
+hipError_t noalloc_scratch(void** out) {
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return hipSuccess;
 }
 
 hipError_t launch_score(const PocketDev& P, const ScoreDev& S, int n_poses, double cd2, int32_t* S_out,
