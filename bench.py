@@ -138,7 +138,62 @@ def cpu_baseline(pool, workers, name, first, n_single, n_per_worker):
                 cpu_model=cpu_model(), nproc=os.cpu_count(), host_cores_usable=cpu_share())
 
 
-def refine_leg(gd, torch, np, n_lig):
+def l2_gather_peak(torch):
+    """Reference peak of random gathers from an L2-resident table (the
+    measurement-only probe library): GB/s gathered for 2-byte and 4-byte
+    elements, tables of 2 and 4 MB, the best of each."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_1901_06363_amd", "libgdprobe.so"))
+    lib.gd_probe_gather.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                    ctypes.c_void_p, ctypes.POINTER(ctypes.c_float)]
+    lib.gd_probe_gather.restype = ctypes.c_int
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    blocks, iters, reps = 256 * 16, 256, 5
+    out = {}
+    for eb, name in ((2, "u16"), (4, "f32")):
+        best = 0.0
+        for mb in (2, 4):
+            log2 = {2: 20, 4: 19}[eb] + (mb // 4)
+            ms = ctypes.c_float(0.0)
+            rc = lib.gd_probe_gather(eb, log2, blocks, iters, reps, stream, ctypes.byref(ms))
+            if rc != 0:
+                raise RuntimeError("gather probe failed (HIP error %d)" % rc)
+            gbps = blocks * 256.0 * iters * 8 * eb / (ms.value * 1e-3) / 1e9
+            out["%s_%dMB_GBps" % (name, mb)] = gbps
+            best = max(best, gbps)
+        out["%s_GBps" % name] = best
+    out["note"] = ("random gathers, 8 independent index chains per lane, %d blocks of 256 lanes: the reference peak "
+                   "for grid lookups that hit in L2" % blocks)
+    return out
+
+
+def torsion_subtree_atoms(np, ligs):
+    """Per ligand, the atoms each rotamer's forward kinematics moves (the side
+    without atom 0), summed over its rotamers."""
+    out = np.zeros(ligs.n, np.int64)
+    for i in range(ligs.n):
+        lig = ligs.ligand(i)
+        l = len(lig["x"])
+        adj = [[] for _ in range(l)]
+        for a, b in lig["bonds"]:
+            adj[a].append(b)
+            adj[b].append(a)
+        tot = 0
+        for a, b in lig["rot"]:
+            seen = {0}
+            stack = [0]
+            while stack:
+                u = stack.pop()
+                for v in adj[u]:
+                    if v not in seen and {u, v} != {int(a), int(b)}:
+                        seen.add(v)
+                        stack.append(v)
+            tot += l - len(seen)
+        out[i] = tot
+    return out
+
+
+def refine_leg(gd, torch, np, n_lig, l2=None):
     """The refinement workload: top-64 docked poses of n_lig ligands, 50 ascent
     steps on the blurred-density surrogate, exact rescoring and acceptance."""
     from synth import configs
@@ -170,14 +225,31 @@ def refine_leg(gd, torch, np, n_lig):
     outp = gd.refine(P, ligs, pose_lig, *inputs, time_kernel=True, clash_weight=cw, **kw)
     atoms = int(pa.sum())
     passes = e["steps"] + 1
-    gather_bytes = atoms * passes * 8 * 4  # 8 trilinear corners of 4 B per atom per pass
+    # algorithmic work per pass (e["steps"] forward + backward passes, one final forward):
+    #   bytes: 8 trilinear corners of 4 B per atom
+    #   flops: forward kinematics 21 per moved atom of every rotamer's subtree and 32 per rotamer (axis and
+    #          matrix), rigid motion 21 per atom, trilinear value and gradient 40 per atom; backward: 15 per atom
+    #          (x x g and sums) and 10 per moved atom of every subtree (torsion terms)
+    sub = torsion_subtree_atoms(np, ligs)[pose_lig]
+    nrot = np.diff(np.asarray(ligs.rot_off))[pose_lig]
+    fwd = 21.0 * sub.sum() + 32.0 * nrot.sum() + 61.0 * atoms
+    bwd = 15.0 * atoms + 10.0 * sub.sum()
+    flops = e["steps"] * (fwd + bwd) + fwd
+    gather_bytes = atoms * passes * 8 * 4
+    gbps = gather_bytes / (kms * 1e-3) / 1e9
+    peak = l2["f32_GBps"] if l2 else None
     return dict(workload="refine: %d ligands x top-%d poses (%d poses, %d atoms), %d ascent steps, sigma %.2f A on a "
                          "%.3f A lattice" % (n_lig, k, len(pose_lig), atoms, e["steps"], e["blur_sigma"], e["blur_h"]),
                 poses=len(pose_lig), steps=e["steps"], kernel="refine_kernel", kernel_ms=kms,
                 pose_steps_per_s=len(pose_lig) * e["steps"] / (kms * 1e-3),
                 refined_poses_per_s_end_to_end=len(pose_lig) / wall,
                 accepted=int(out["accepted"].sum().item()),
-                gather_GBps=gather_bytes / (kms * 1e-3) / 1e9,
+                gather_GBps=gbps,
+                roofline=dict(bound="l2", achieved=gbps, peak=peak, unit="GB/s", frac=(gbps / peak) if peak else None,
+                              algo_gather_bytes_per_launch=gather_bytes, algo_flops_per_launch=flops,
+                              flops_TFLOPs=flops / (kms * 1e-3) / 1e12,
+                              flops_frac_of_fp32_peak=flops / (kms * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS,
+                              peak_source="l2_gather_peak.f32_GBps (random 4-byte gathers from an L2-resident table)"),
                 penalised=dict(clash_weight=cw, kernel_ms=outp["kernel_ms"],
                                accepted=int(outp["accepted"].sum().item())))
 
@@ -330,6 +402,83 @@ def tts_leg(gd, torch, np, dse_ligands=5000, records_path=None):
                 train_runs=len(recs), r2_adj_mean=float(np.mean(r2)), r2_adj_min=float(np.min(r2)),
                 validation_error=val, baseline_ms_per_ligand=tb,
                 scenario1_budget_1h=s1, scenario2_500M_ligands=s2, wall_s=time.perf_counter() - t0)
+
+
+def grid_leg(gd, torch, np, n_lig=2000):
+    """The knob grid: for each of the 4 pockets x orientations {64, 256, 1024}
+    x steps {30, 15, 10} degrees, the same n_lig ligands spread over the
+    100,000-ligand stream docked in one batched call (persistent kernel) and
+    with one launch per ligand; wall clock of each call between
+    synchronisations, and whether both forms return identical results."""
+    import synth
+    from synth import configs
+    w = configs.GRID
+    idx = np.linspace(0, w.n_ligands - 1, n_lig).astype(int)
+    ligs = synth.LigandBatch.from_list([w.ligands(int(i), 1).ligand(0) for i in idx])
+    rows = []
+    t_all = time.perf_counter()
+    for pk in range(len(w.pockets)):
+        P = gd.Pocket(w.pocket_points(pk), 0.5, 20.0)
+        for n_o in w.extra["orient_grid"]:
+            q = synth.quaternions(w.quat_seed, n_o)
+            for hp in w.extra["step_grid"]:
+                B = gd.Batch(P, ligs, q, hp=hp, top_k=w.top_k)
+                times = {}
+                res = {}
+                for mode, name in ((gd.BATCHED, "batched"), (gd.PER_LIGAND, "per_ligand")):
+                    out = B.dock(mode)  # warm-up (and graph capture for the batched form)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    B.dock(mode, out)
+                    torch.cuda.synchronize()
+                    times[name] = time.perf_counter() - t0
+                    res[name] = out.host()
+                same = all(np.array_equal(res["batched"][k], res["per_ligand"][k])
+                           for k in ("orient", "S", "clash", "angles", "xyz"))
+                rows.append(dict(pocket=pk, points=len(P.xyz), orientations=n_o, step=hp, poses=B.poses_expected,
+                                 batched_s=times["batched"], per_ligand_s=times["per_ligand"],
+                                 batched_poses_per_s=B.poses_expected / times["batched"],
+                                 per_ligand_poses_per_s=B.poses_expected / times["per_ligand"],
+                                 ratio=times["per_ligand"] / times["batched"], results_identical=bool(same)))
+                log("grid pocket %d, %4d orientations, %2d deg: batched %.1f ms, per-ligand %.1f ms, %.2fx, same %s"
+                    % (pk, n_o, hp, 1e3 * times["batched"], 1e3 * times["per_ligand"], rows[-1]["ratio"], same))
+                del B
+    r = np.array([x["ratio"] for x in rows])
+    return dict(workload="grid: %d ligands spread over the 100,000-ligand stream x 4 pockets (1,000-8,000 points) x "
+                         "orientations {64, 256, 1024} x steps {30, 15, 10} degrees, top-8" % n_lig,
+                rows=rows, ratio_min=float(r.min()), ratio_median=float(np.median(r)), ratio_max=float(r.max()),
+                all_identical=all(x["results_identical"] for x in rows), wall_s=time.perf_counter() - t_all)
+
+
+def tiling_sweep(gd, torch, np, workload, n_lig=0, tilings=None):
+    """Docking-kernel time of one full batch (a 65,536-ligand chunk of the
+    large library, or the screening workload) under every tiling the library
+    offers (waves per block x angle block x pairs per lane), HIP events."""
+    from synth import configs
+    w = configs.LARGE if workload == "large" else configs.SCREEN
+    n_lig = n_lig or (w.chunk if workload == "large" else w.n_ligands)
+    P = gd.Pocket(w.pocket_points(), 0.5, w.pad)
+    B = gd.Batch(P, w.ligands(0, n_lig), w.quaternions(), hp=w.hp, top_k=w.top_k)
+    out = B.alloc_outputs(want_angles=True, want_xyz=True)
+    rows = []
+    tilings = tilings or [(w_, nb, ppl) for w_ in (2, 4, 8) for nb in (8, 16, 32) for ppl in (2, 4, 8)]
+    for wpb, nb, ppl in tilings:
+        B.set_tiling(wpb, nb, ppl)
+        B.dock(gd.BATCHED, out)
+        torch.cuda.synchronize()
+        B.read_timing()
+        B.enable_timing(True)
+        B.dock(gd.BATCHED, out)
+        ms = float(B.read_timing()[0])
+        B.enable_timing(False)
+        rows.append(dict(waves_per_block=wpb, angle_block=nb, pairs_per_lane=ppl, kernel_ms=ms))
+        log("tiling %d,%d,%d: %.1f ms" % (wpb, nb, ppl, ms))
+    best = min(rows, key=lambda r: r["kernel_ms"])
+    auto = B.autotune(reps=1)
+    hit = [r["kernel_ms"] for r in rows
+           if (r["waves_per_block"], r["angle_block"], r["pairs_per_lane"]) == tuple(auto)]
+    return dict(workload="%s: %d ligands" % (workload, n_lig), rows=rows, best=best, autotuned=list(auto),
+                autotuned_ms=hit[0] if hit else None)
 
 
 def peaks_leg(gd, torch, np, n_lig=2000, step=1):
@@ -625,7 +774,7 @@ def large_headline(gd, torch, np, args):
     cnt = cnt_hist.cpu().numpy()
     acc = acc_hist.cpu().numpy()
     poses = lig_n = atoms = 0
-    flops = 0.0
+    flops = gbytes = 0.0
     kernel_ms = []
     for j, B in enumerate(timed_batches):
         s = args.warmup + j
@@ -634,6 +783,7 @@ def large_headline(gd, torch, np, args):
         lig_n += B.n_ligands
         atoms += B.n_atoms_total
         flops += B.algo_flops
+        gbytes += B.algo_bytes
     for i, v in kms.items():
         kernel_ms.extend(v)
     k_s = sum(kernel_ms) * 1e-3
@@ -702,7 +852,8 @@ def large_headline(gd, torch, np, args):
                       traffic_unit="HBM bytes per launch of one full chunk (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
                                    "copy-calibrated)",
                       kernel="dock_persistent_kernel", kernel_ms=1e3 * k_s / n_launch,
-                      algo_flops_per_launch=flops / n_timed, library_algo_flops=lib_flops))
+                      algo_flops_per_launch=flops / n_timed, library_algo_flops=lib_flops,
+                      algo_gather_bytes_per_launch=gbytes / n_timed, gather_GBps=gbytes / k_s / 1e9))
 
 
 def main():
@@ -730,6 +881,10 @@ def main():
     ap.add_argument("--dse", type=str, default="", help="run only the knob exploration: flat, full or both")
     ap.add_argument("--dse-ligands", type=int, default=0)
     ap.add_argument("--peaks", action="store_true", help="run only the peak analysis of overlap landscapes")
+    ap.add_argument("--grid", action="store_true", help="run only the knob-grid leg (batched vs per-ligand)")
+    ap.add_argument("--tiling-sweep", type=str, default="", help="time every tiling on one batch: large or screen")
+    ap.add_argument("--sweep-tilings", type=str, default="", help="tilings of the sweep, e.g. 2,8,4;8,32,4")
+    ap.add_argument("--grid-ligands", type=int, default=2000)
     ap.add_argument("--tts-records", type=str, default="", help="also write the campaign's raw records (JSON)")
     ap.add_argument("--tts", action="store_true", help="run only the time-to-solution campaign, validation and "
                                                           "budget scenarios")
@@ -749,7 +904,8 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path (ligand batches shard trivially "
               "across GPUs); got --gpus %d" % args.gpus, file=sys.stderr)
         sys.exit(2)
-    only = args.copy_calibration or args.refine_only or args.peaks or args.tts or args.dse
+    only = (args.copy_calibration or args.refine_only or args.peaks or args.tts or args.dse or args.grid
+            or args.tiling_sweep)
     pool = None
     workers = args.cpu_workers or cpu_share()
     if not only and not args.no_cpu_baseline:
@@ -775,10 +931,17 @@ def main():
         log("copy calibration: read %d B, wrote %d B" % (n, n))
         return
     if args.refine_only:
-        print(json.dumps(refine_leg(gd, torch, np, args.refine_ligands)), flush=True)
+        print(json.dumps(refine_leg(gd, torch, np, args.refine_ligands, l2_gather_peak(torch))), flush=True)
         return
     if args.peaks:
         print(json.dumps(peaks_leg(gd, torch, np)), flush=True)
+        return
+    if args.grid:
+        print(json.dumps(grid_leg(gd, torch, np, args.grid_ligands)), flush=True)
+        return
+    if args.tiling_sweep:
+        til = [tuple(int(v) for v in t.split(",")) for t in args.sweep_tilings.split(";") if t]
+        print(json.dumps(tiling_sweep(gd, torch, np, args.tiling_sweep, tilings=til or None)), flush=True)
         return
     if args.tts:
         print(json.dumps(tts_leg(gd, torch, np, records_path=args.tts_records or None)), flush=True)
@@ -789,6 +952,8 @@ def main():
         return
 
     metric = "poses scored/s and ligands docked/s, batched vs per-ligand, same GPU, exact"
+    l2 = l2_gather_peak(torch)
+    log("l2 gather peak:", l2)
     if args.workload == "screen":
         sc = screen_leg(gd, torch, np, args, args.steps, args.warmup, args.n_ligands, args.tiling)
         head = dict(value=sc["poses_per_s"], ms_per_step=sc["ms_per_step"],
@@ -809,8 +974,12 @@ def main():
         head["stream"] = large_leg(gd, torch, args.stream_chunks, head["config"]["tiling"])
         log("stream:", head["stream"])
     if not args.no_refine and args.refine_ligands > 0:
-        head["refine"] = refine_leg(gd, torch, np, args.refine_ligands)
+        head["refine"] = refine_leg(gd, torch, np, args.refine_ligands, l2)
         log("refinement:", head["refine"])
+    head["l2_gather_peak"] = l2
+    rf = head["roofline"]
+    if rf.get("gather_GBps"):
+        rf["gather_frac_of_l2_peak"] = rf["gather_GBps"] / l2["u16_GBps"]
     cpu = None
     if pool is not None:
         cpu = cpu_baseline(pool, workers, cpu_name, cpu_first, args.cpu_single, args.cpu_per_worker)

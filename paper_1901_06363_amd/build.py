@@ -13,6 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgd.so")
+PROBE_LIB = os.path.join(HERE, "libgdprobe.so")
 SOURCES = ["dock.hip", "score.hip", "refine.hip", "overlap.hip", "runtime.cpp", "api_extra.cpp", "refine_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -53,6 +54,11 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs + ["-lpthread"]
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
+    # the measurement-only gather probe (bench.py's L2 reference), a library of its own
+    tmp = PROBE_LIB + ".tmp%d" % os.getpid()
+    subprocess.check_call([HIPCC] + FLAGS + ["-shared", "-o", tmp, os.path.join(CSRC, "probe.hip")],
+                          stdout=subprocess.DEVNULL, stderr=subprocess.DEVNULL)
+    os.replace(tmp, PROBE_LIB)
     return LIB
 
 

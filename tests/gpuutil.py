@@ -25,6 +25,23 @@ def oracle_dock_batch(opocket, ligs, kn, quats):
     return [oracle.dock(opocket, ligs.ligand(i), kn, quats) for i in range(ligs.n)]
 
 
+def oracle_dock_parallel(pts, ligs, kn, quats, threads=None):
+    """oracle_dock_batch over host threads (the oracle runs outside the
+    interpreter lock), each thread with its own oracle pocket."""
+    import os
+    import threading
+    from concurrent.futures import ThreadPoolExecutor
+    threads = threads or max(1, min(16, os.cpu_count() or 1, ligs.n))
+    local = threading.local()
+
+    def one(i):
+        if not hasattr(local, "pocket"):
+            local.pocket = oracle.OraclePocket(pts, 0.5)
+        return oracle.dock(local.pocket, ligs.ligand(i), kn, quats)
+    with ThreadPoolExecutor(threads) as ex:
+        return list(ex.map(one, range(ligs.n)))
+
+
 def compare_full_ranking(res_host, orc, ligs, atol_xyz=1e-4):
     """GPU top-k == oracle ranking of all orientations: orientation, S, clash,
     chosen angles and coordinates (FP32 vs FP64 within atol)."""

@@ -95,7 +95,7 @@ def test_screen_full_size_sampled(g):
 def test_grid_knob_points(g, pk):
     """Every (orientations, step) point of the knob grid on one pocket: 128
     ligands spread over the 100,000-ligand stream, batched == per-ligand, and
-    two of them against the oracle."""
+    16 of them (a different 16 at every point) against the oracle."""
     w = configs.GRID
     pts = w.pocket_points(pk)
     P, O = g.Pocket(pts, 0.5, PAD), oracle.OraclePocket(pts, 0.5)
@@ -109,10 +109,11 @@ def test_grid_knob_points(g, pk):
             rp = b.dock(g.PER_LIGAND).host()
             _assert_same(rb, rp)
             assert rb["counters"][0] == rp["counters"][0] == b.poses_expected
-            two = [(pk * 37 + n_o + hp) % ligs.n, (pk * 53 + 3 * hp + 1) % ligs.n]
-            sub = ligs.subset(two)
-            orc = gpuutil.oracle_dock_batch(O, sub, oracle.knobs(hp=hp), q)
-            gpuutil.compare_full_ranking({k: v[two] for k, v in rb.items() if k != "counters"}, orc, sub)
+            rng = np.random.default_rng(1000 * pk + 10 * hp + n_o)
+            pick = sorted(rng.choice(ligs.n, 16, replace=False).tolist())
+            sub = ligs.subset(pick)
+            orc = gpuutil.oracle_dock_parallel(pts, sub, oracle.knobs(hp=hp), q)
+            gpuutil.compare_full_ranking({k: v[pick] for k, v in rb.items() if k != "counters"}, orc, sub)
 
 
 @gpu
