@@ -156,11 +156,17 @@ gd_status autotune(const gd_pocket* P, gd_batch* B, hipStream_t s, int reps, con
     const std::string key = tune_key(P, B);
     Tiling best = B->tiling;
     if (!cache_lookup(cache, key, best)) {
-        // a strided sample of the work queue keeps the LPT mix of costs
+        // a strided sample of the work queue keeps the LPT mix of costs; 16
+        // items per resident wave, so that a run measures throughput rather
+        // than the latency of its costliest item
         std::vector<int32_t> items(2 * (size_t)B->dev.n_items);
         hipError_t e = hipMemcpy(items.data(), B->dev.items, items.size() * 4, hipMemcpyDeviceToHost);
         if (e != hipSuccess) return hip_fail(e, "gd_batch_autotune");
-        const int want = 4096;
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        hipDeviceProp_t prop;
+        (void)hipGetDeviceProperties(&prop, dev);
+        const int want = 16 * 16 * std::max(1, prop.multiProcessorCount);
         int stride = std::max(1, B->dev.n_items / want);
         std::vector<int32_t> sample;
         for (int i = 0; i < B->dev.n_items; i += stride) {
@@ -231,6 +237,15 @@ gd_status gd_score_poses(const gd_pocket* pocket, const gd_ligands* topo, int32_
     clear_error();
     return score_poses(pocket, topo, n_poses, pose_lig, px, py, pz, clash_dist, clash_min_bonds, (hipStream_t)stream,
                        S_out, clash_out);
+}
+
+gd_status gd_score_poses_noalloc(const gd_pocket* pocket, const gd_ligands* topo, int32_t n_poses,
+                                 const int32_t* pose_lig, const float* px, const float* py, const float* pz,
+                                 float clash_dist, int32_t clash_min_bonds, void* stream, int32_t* S_out,
+                                 uint8_t* clash_out) {
+    clear_error();
+    return score_poses_noalloc(pocket, topo, n_poses, pose_lig, px, py, pz, clash_dist, clash_min_bonds,
+                               (hipStream_t)stream, S_out, clash_out);
 }
 
 gd_status gd_overlap_continuous(const gd_pocket* pocket, int32_t n_poses, const int32_t* pose_off, int64_t n_atoms,
