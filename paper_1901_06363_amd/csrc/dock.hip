@@ -158,7 +158,7 @@ struct Sweep {
     const uint8_t* mvl;       // moving atoms
     const uint16_t* pairs;    // straddling far pairs (left | right << 8)
     int m, npairs, side, lp;
-    float gcell;              // guard for cell decisions (cell units)
+    float gface;              // a lookup is certain when every coordinate is within gface of its cell centre
     float thr_lo, thr_hi;     // bump thresholds on FP32 d^2
     int nsurv;                // pairs that can bump at some angle of this sweep
     bool pruned;              // survivors listed in LDS (else test every pair)
@@ -297,12 +297,16 @@ __device__ __forceinline__ void bump_block(const Sweep& sw, const WaveLds& W, in
 // distance-grid gathers are in flight.  (NB, KANG, KATU) = (8, 4, 1),
 // (16, 2, 2) or (32, 1, 4): up to 32 angles per block and 8 atoms per step
 // over the groups.  The moving list is followed by kMvPad rows
-// whose position is the zero sentinel cell (certain, D = 0), so the steps
-// need no end-of-list masking; an atom whose cell is not certain reads the
-// sentinel too and marks its candidate uncertain (a ballot mask in scalar
-// registers).  With BOX the grid bounds are tested per atom, otherwise the
-// sweep set-up has proven that every moving atom stays inside the box.
-// Writes W.Slo / W.Shi per candidate.
+// whose position is the zero sentinel cell (certain, D = 0), so every lane
+// runs the same steps (a wave-uniform loop) with no end-of-list masking; an
+// atom whose cell is not certain reads the sentinel too and marks its
+// candidate uncertain (a ballot mask in scalar registers).  Positions are
+// relative to the centre of the box's first cell, so an atom's cell is its
+// position rounded to the nearest integers and the lookup is certain when
+// every coordinate lies within gface of that integer (one max3 of absolute
+// differences and one compare).  With BOX the grid bounds are tested per
+// atom, otherwise the sweep set-up has proven that every moving atom stays
+// inside the box.  Writes W.Slo / W.Shi per candidate.
 template <int NB>
 __device__ __forceinline__ uint32_t fold_groups(uint64_t m) {
     // OR together the bits of lanes k0 + NB*g over g: result bit k0
@@ -341,7 +345,7 @@ __device__ __forceinline__ void score_pass(const PocketDev& P, const Sweep& sw, 
     // even integer below 2^25, hence exact
     const float fsy2 = 2.f * fnx, fsz2 = 2.f * fnx * fny;
     const float fsent2 = 2.f * (float)P.n_cells;
-    const float glo = sw.gcell, ghi = 1.f - sw.gcell;
+    const float thr = sw.gface;
     const int m = sw.m;
     const __attribute__((address_space(1))) char* edt = (const __attribute__((address_space(1))) char*)P.edt;
     for (int kb = 0; kb < n; kb += NB * KANG) {
@@ -361,11 +365,13 @@ __device__ __forceinline__ void score_pass(const PocketDev& P, const Sweep& sw, 
             sum[a] = 0;
             badm[a] = 0;
         }
-        for (int j = g; j < m; j += KATU * G) {
-            uint32_t off[KATU][KANG];
+        // byte offsets of the KATU x KANG lookups of the step at row j0 (the
+        // sentinel's for an uncertain cell, whose candidate is flagged)
+        uint32_t off[KATU][KANG];
+        auto offsets = [&](int j0) {
 #pragma unroll
             for (int t = 0; t < KATU; t++) {
-                const int r = j + t * G;  // at most m + KATU * G - 2: within the sentinel rows
+                const int r = j0 + g + t * G;  // at most m + KATU * G - 2: within the sentinel rows
                 const f4 ra = W.MVa[r], rb = W.MVb[r];
                 const float rc = W.MVc[r];
                 const bool live = BOX ? (r < m) : true;
@@ -376,10 +382,11 @@ __device__ __forceinline__ void score_pass(const PocketDev& P, const Sweep& sw, 
                         const float yx = fmaf(s[a], rb.z, fmaf(c[a], ra.w, ra.x));
                         const float yy = fmaf(s[a], rb.w, fmaf(c[a], rb.x, ra.y));
                         const float yz = fmaf(s[a], rc, fmaf(c[a], rb.y, ra.z));
-                        const float fx = floorf(yx), fy = floorf(yy), fz = floorf(yz);
-                        const float rx = __builtin_amdgcn_fractf(yx), ry = __builtin_amdgcn_fractf(yy),
-                                    rz = __builtin_amdgcn_fractf(yz);
-                        bool sure = (fminf(fminf(rx, ry), rz) >= glo) & (fmaxf(fmaxf(rx, ry), rz) <= ghi);
+                        // nearest integers (ties to even: a tie is never certain); the
+                        // differences are exact
+                        const float fx = __builtin_rintf(yx), fy = __builtin_rintf(yy), fz = __builtin_rintf(yz);
+                        const float e = fmaxf(fmaxf(fabsf(yx - fx), fabsf(yy - fy)), fabsf(yz - fz));
+                        bool sure = e <= thr;
                         if (BOX)
                             sure = sure & (fx >= 0.f) & (fx < fnx) & (fy >= 0.f) & (fy < fny) & (fz >= 0.f) &
                                    (fz < fnz);
@@ -389,15 +396,22 @@ __device__ __forceinline__ void score_pass(const PocketDev& P, const Sweep& sw, 
                     }
                 }
             }
+        };
+        // software pipeline: the gathers of a step are in flight while the
+        // next step's offsets are computed (an empty list reads only sentinel rows)
+        offsets(0);
+        for (int j0 = 0; j0 < m; j0 += KATU * G) {
+            int v[KATU][KANG];
+#pragma unroll
+            for (int t = 0; t < KATU; t++)
+#pragma unroll
+                for (int a = 0; a < KANG; a++)
+                    v[t][a] = a < A ? (int)*(const __attribute__((address_space(1))) uint16_t*)(edt + off[t][a]) : 0;
+            if (j0 + KATU * G < m) offsets(j0 + KATU * G);
 #pragma unroll
             for (int a = 0; a < KANG; a++)
-                if (a < A) {
-                    int d = 0;
 #pragma unroll
-                    for (int t = 0; t < KATU; t++)
-                        d += (int)*(const __attribute__((address_space(1))) uint16_t*)(edt + off[t][a]);
-                    sum[a] += d;
-                }
+                for (int t = 0; t < KATU; t++) sum[a] += v[t][a];
         }
         // sum the groups of each angle across lanes; uncertain flags folded from the ballots
 #pragma unroll
@@ -665,13 +679,16 @@ __device__ __forceinline__ void sweep_setup(const PocketDev& P, const BatchDev& 
     sw.nsurv = nsurv;
     sw.pruned = nsurv <= kSurvCap;
     // moving-atom rows for the score pass, over the memory of the per-atom data
-    // (no longer read: the prune and the coefficients are done).  Cell units,
-    // box-relative: P0 = (p + z k) / h - lo, U = (u - z k) / h, V = (k x u) / h.
+    // (no longer read: the prune and the coefficients are done).  Cell units
+    // relative to the centre of the box's first cell: P0 = (p + z k) / h - lo
+    // - 1/2, U = (u - z k) / h, V = (k x u) / h; the cell of a position is its
+    // nearest integer point.
     wave_sync();
     const double ih = P.inv_h;
     const double kxh = kx * ih, kyh = ky * ih, kzh = kz * ih;  // exact: h is a power of two
-    const double qx = px * ih - (double)P.lo[0], qy = py * ih - (double)P.lo[1], qz = pz * ih - (double)P.lo[2];
-    const float ex = (float)P.dim[0] - 0.01f, ey = (float)P.dim[1] - 0.01f, ez = (float)P.dim[2] - 0.01f;
+    const double qx = px * ih - ((double)P.lo[0] + 0.5), qy = py * ih - ((double)P.lo[1] + 0.5),
+                 qz = pz * ih - ((double)P.lo[2] + 0.5);
+    const float ex = (float)P.dim[0] - 0.51f, ey = (float)P.dim[1] - 0.51f, ez = (float)P.dim[2] - 0.51f;
     float gterm = 0.f;
     bool outside = false;
     for (int j = lane; j < sw.m; j += kWave) {
@@ -687,12 +704,13 @@ __device__ __forceinline__ void sweep_setup(const PocketDev& P, const BatchDev& 
         W.MVb[j] = mk4(Uy, Uz, Vx, Vy);
         W.MVc[j] = Vz;
         // the atom's circle lies in the ball of radius |U| (= |V|) about P0:
-        // keep that ball 0.01 cell inside the box on every side (the FP32
-        // test errs by far less than the margin)
+        // keep that ball 0.01 cell inside the box on every side, [-0.49,
+        // dim - 0.51] about the first cell's centre (the FP32 test errs by far
+        // less than the margin)
         const float r = __builtin_amdgcn_sqrtf(fmaf(Uz, Uz, fmaf(Uy, Uy, Ux * Ux)));
         const float lo = fminf(fminf(ax0, ay0), az0) - r;
         const float hi = fmaxf(fmaxf(ax0 - ex, ay0 - ey), az0 - ez) + r;
-        outside |= !((lo >= 0.01f) & (hi <= 0.f));
+        outside |= !((lo >= -0.49f) & (hi <= 0.f));
         // components of U and V are at most r
         gterm = fmaxf(gterm, fmaf(3.f, fmaxf(fmaxf(fabsf(ax0), fabsf(ay0)), fabsf(az0)), 7.f * r));
     }
@@ -701,11 +719,17 @@ __device__ __forceinline__ void sweep_setup(const PocketDev& P, const BatchDev& 
     // sentinel rows after the list: U = V = 0 at the centre of cell (0, 0, nz),
     // whose linear index is the zero sentinel cell
     if (lane < kMvPad) {
-        W.MVa[sw.m + lane] = mk4(0.5f, 0.5f, (float)P.dim[2] + 0.5f, 0.f);
+        W.MVa[sw.m + lane] = mk4(0.f, 0.f, (float)P.dim[2], 0.f);
         W.MVb[sw.m + lane] = mk4(0.f, 0.f, 0.f, 0.f);
         W.MVc[sw.m + lane] = 0.f;
     }
-    sw.gcell = (float)(2.0 * u32 * 1.01 * (double)gterm + 1e-6);
+    // a lookup is certain when each coordinate is more than the guard away from
+    // a cell face, i.e. within 1/2 - guard of the cell centre; the FP32
+    // threshold is rounded down
+    const double face = 0.5 - (2.0 * u32 * 1.01 * (double)gterm + 1e-6);
+    float tf = (float)face;
+    if ((double)tf > face) tf = __int_as_float(__float_as_int(tf) - 1);
+    sw.gface = tf;
 
     wave_sync();
 }
