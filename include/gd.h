@@ -106,10 +106,21 @@ gd_status gd_pocket_read_density(const gd_pocket* pocket, float* host_out);
 /* Ligands and knobs                                                         */
 
 /*
- * A ragged batch in CSR form with ligand-local atom indices (host memory).
- * Atoms, bond graph and rotamers as in Section II: a rotamer is a bond whose
- * removal splits the ligand into two non-empty fragments.  For rotamer (a,b)
- * the "left" fragment is the side of a; the list order is the sweep order.
+ * A ragged batch in CSR form with ligand-local atom indices: the ligand
+ * database of Section III-A.  Atoms, bond graph and rotamers as in Section
+ * II: a rotamer is a bond whose removal splits the ligand into two non-empty
+ * fragments.  For rotamer (a,b) the "left" fragment is the side of a; the
+ * list order is the sweep order.
+ *
+ * on_device = 0: the arrays are host memory, read during the call only.
+ * on_device = 1: the arrays are device memory of the current device (for
+ * instance a chunk already resident in HBM).  Validation and preparation run
+ * on the host, so a call first copies the arrays to host memory on its stream,
+ * after the stream's earlier work (that copy waits for it); the docking
+ * kernels then read the coordinates in place: gd_dock_batch uses the
+ * caller's arrays until its work on the stream has completed,
+ * gd_prepare_batch copies them device to device into the batch.  Other
+ * values: GD_ERR_ARG.  Zero-initialising the struct gives host arrays.
  */
 typedef struct {
     int32_t n_ligands;
@@ -121,6 +132,7 @@ typedef struct {
     const int32_t* bonds;     /* 2 per bond */
     const int32_t* rot_off;   /* n_ligands+1 */
     const int32_t* rot;       /* 2 per rotamer: (a, b) */
+    int32_t on_device;        /* 0: host arrays, 1: device arrays (see above) */
 } gd_ligands;
 
 /*
@@ -216,7 +228,20 @@ gd_status gd_batch_read_timing(gd_batch* batch, float* ms_out, int32_t max_n, in
 gd_status gd_dock_prepared(const gd_pocket* pocket, gd_batch* batch, gd_mode mode, void* stream,
                            gd_pose_rec* out, uint16_t* angles, float* pose_xyz, int64_t* counters);
 
-/* gd_prepare_batch + gd_dock_prepared + gd_destroy_batch; synchronous. */
+/*
+ * Prepare and dock a batch in one call (Alg. 2 per orientation, then top-k
+ * per ligand), outputs as for gd_dock_prepared.  When every given output is
+ * device memory the call is asynchronous on `stream`: it validates and
+ * prepares on the host, enqueues the upload of the batch tables (from pinned
+ * staging buffers the library keeps for reuse), the docking kernels and the
+ * outputs, and returns; the batch tables live in a stream-ordered allocation
+ * freed on the stream after the last kernel.  Host inputs may be reused when
+ * the call returns; device inputs (on_device) and the outputs belong to the
+ * stream's work until it completes.  When any output is host memory the
+ * results go through device scratch and the call returns after they have
+ * been copied to the host (synchronous).  Errors as gd_prepare_batch and
+ * gd_dock_prepared, reported before any device work.
+ */
 gd_status gd_dock_batch(const gd_pocket* pocket, const gd_ligands* ligands, const gd_knobs* knobs, gd_mode mode,
                         void* stream, gd_pose_rec* out, uint16_t* angles, float* pose_xyz, int64_t* counters);
 

@@ -15,8 +15,8 @@ import numpy as np
 from . import _abi
 from ._abi import GdError  # noqa: F401
 
-__all__ = ["Pocket", "Batch", "DockResult", "dock", "score_poses", "score_poses_noalloc", "refine", "surrogate_fwd",
-           "surrogate_bwd", "SurrogateScore", "GdError", "lib_path"]
+__all__ = ["Pocket", "Batch", "DockResult", "dock", "dock_batch", "DeviceLigands", "score_poses", "score_poses_noalloc",
+           "refine", "surrogate_fwd", "surrogate_bwd", "SurrogateScore", "GdError", "lib_path"]
 
 PER_LIGAND, BATCHED = 0, 1
 CNT_POSES, CNT_FALLBACK, CNT_OOB, CNT_SWEEPS = 0, 1, 2, 3
@@ -109,7 +109,7 @@ class _LigandArrays:
             self.rot = np.zeros(2, np.int32)
         p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
         self.desc = _abi.Ligands(len(self.atom_off) - 1, p(self.atom_off), p(self.x), p(self.y), p(self.z),
-                                 p(self.bond_off), p(self.bonds), p(self.rot_off), p(self.rot))
+                                 p(self.bond_off), p(self.bonds), p(self.rot_off), p(self.rot), 0)
 
     @property
     def n(self):
@@ -117,6 +117,23 @@ class _LigandArrays:
 
     def n_atoms(self):
         return np.diff(self.atom_off)
+
+
+class DeviceLigands(_LigandArrays):
+    """A ligand set whose CSR arrays live in device memory (gd_ligands with
+    on_device = 1): the library reads them there.  The host copies of the
+    offsets stay for the binding's own shape checks."""
+
+    def __init__(self, ligs, stream=None):
+        super().__init__(ligs)
+        torch = _torch()
+        dev = torch.device("cuda")
+        self.dev = {k: torch.from_numpy(getattr(self, k).copy()).to(dev)
+                    for k in ("atom_off", "x", "y", "z", "bond_off", "bonds", "rot_off", "rot")}
+        torch.cuda.synchronize()
+        d = lambda k: ctypes.c_void_p(self.dev[k].data_ptr())
+        self.desc = _abi.Ligands(self.n, d("atom_off"), d("x"), d("y"), d("z"), d("bond_off"), d("bonds"),
+                                 d("rot_off"), d("rot"), 1)
 
 
 class DockResult:
@@ -151,7 +168,7 @@ class Batch:
                  top_k=10, clash_dist=2.0, clash_min_bonds=4, stream=None):
         lib = _abi.load()
         self.pocket = pocket
-        self.lig = _LigandArrays(ligands)
+        self.lig = ligands if isinstance(ligands, _LigandArrays) else _LigandArrays(ligands)
         self.quats = np.ascontiguousarray(quats, dtype=np.float64).reshape(-1, 4)
         k = _abi.Knobs(int(hp), int(lp if lp is not None else hp), float(threshold), int(repetitions), int(bool(refine)),
                        len(self.quats), self.quats.ctypes.data_as(ctypes.c_void_p), int(top_k), float(clash_dist),
@@ -228,6 +245,34 @@ def dock(pocket: Pocket, ligands, quats, mode=BATCHED, stream=None, **knobs) -> 
     res = b.dock(mode, stream=stream)
     _torch().cuda.synchronize()
     return res
+
+
+def dock_batch(pocket: Pocket, ligands, quats, mode=BATCHED, out: DockResult = None, want_angles=True, want_xyz=True,
+               stream=None, hp=10, lp=None, threshold=0.0, repetitions=1, refine=False, top_k=10, clash_dist=2.0,
+               clash_min_bonds=4) -> DockResult:
+    """gd_dock_batch: prepare and dock in one call.  With device outputs (the
+    default) the call returns once the work is enqueued on `stream`; the
+    results are there when the stream has reached it."""
+    lib = _abi.load()
+    lg = ligands if isinstance(ligands, _LigandArrays) else _LigandArrays(ligands)
+    q = np.ascontiguousarray(quats, dtype=np.float64).reshape(-1, 4)
+    k = _abi.Knobs(int(hp), int(lp if lp is not None else hp), float(threshold), int(repetitions), int(bool(refine)),
+                   len(q), q.ctypes.data_as(ctypes.c_void_p), int(top_k), float(clash_dist), int(clash_min_bonds))
+    if out is None:
+        torch = _torch()
+        dev = torch.device("cuda")
+        n, kk = lg.n, int(top_k)
+        lmax = max(int(lg.n_atoms().max()), 1)
+        rmax = max(int(np.diff(lg.rot_off).max()), 1)
+        recs = torch.empty((n * kk, 6), dtype=torch.int32, device=dev)
+        ang = torch.empty((n, kk, int(repetitions), rmax, 2), dtype=torch.int16, device=dev) if want_angles else None
+        xyz = torch.empty((n, kk, lmax, 3), dtype=torch.float32, device=dev) if want_xyz else None
+        cnt = torch.empty(4, dtype=torch.int64, device=dev)
+        out = DockResult(recs, ang, xyz, cnt, n, kk)
+    _abi.check(lib.gd_dock_batch(pocket.handle, ctypes.byref(lg.desc), ctypes.byref(k), int(mode), _stream_ptr(stream),
+                                 _dptr(out.recs), _dptr(out.angles), _dptr(out.xyz), _dptr(out.counters)))
+    out._keep = (lg, q)  # host arrays of the call (already consumed) and device inputs (read by the stream)
+    return out
 
 
 from ._ops import score_poses, score_poses_noalloc, overlap_continuous, OverlapLayout, sweep_profile, refine, surrogate_fwd, surrogate_bwd, SurrogateScore  # noqa: E402,E501

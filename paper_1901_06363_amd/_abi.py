@@ -30,7 +30,7 @@ class PocketInfo(ctypes.Structure):
 
 class Ligands(ctypes.Structure):
     _fields_ = [("n_ligands", I32), ("atom_off", P), ("x", P), ("y", P), ("z", P), ("bond_off", P), ("bonds", P),
-                ("rot_off", P), ("rot", P)]
+                ("rot_off", P), ("rot", P), ("on_device", I32)]
 
 
 class Knobs(ctypes.Structure):

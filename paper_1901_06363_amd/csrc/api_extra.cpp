@@ -31,14 +31,17 @@ gd_status pose_layout(const gd_ligands* topo, int32_t n_poses, const int32_t* po
     return GD_OK;
 }
 
-gd_status score_poses(const gd_pocket* P, const gd_ligands* topo, int32_t n_poses, const int32_t* pose_lig,
+gd_status score_poses(const gd_pocket* P, const gd_ligands* topo0, int32_t n_poses, const int32_t* pose_lig,
                       const float* px, const float* py, const float* pz, float clash_dist, int32_t min_bonds,
                       hipStream_t s, int32_t* S_out, uint8_t* clash_out) {
-    if (!P || !topo || !S_out || !clash_out) return fail(GD_ERR_ARG, "gd_score_poses: null argument");
+    if (!P || !topo0 || !S_out || !clash_out) return fail(GD_ERR_ARG, "gd_score_poses: null argument");
     if (n_poses > 0 && (!px || !py || !pz)) return fail(GD_ERR_ARG, "gd_score_poses: null coordinates");
     if (!(clash_dist >= 0.f) || clash_dist > 100.f) return fail(GD_ERR_ARG, "gd_score_poses: bad clash_dist");
     TopoHost T;
     gd_status st;
+    HostLigands HL;
+    const gd_ligands* topo = nullptr;
+    if ((st = ligands_on_host(topo0, s, HL, &topo, "gd_score_poses")) != GD_OK) return st;
     if ((st = prepare_topology(topo, min_bonds, T)) != GD_OK) return st;
     std::vector<int32_t> lig, off;
     if ((st = pose_layout(topo, n_poses, pose_lig, T.n_atoms, lig, off)) != GD_OK) return st;
@@ -62,15 +65,18 @@ gd_status score_poses(const gd_pocket* P, const gd_ligands* topo, int32_t n_pose
 // The same scoring with the call's tables staged in the library's static
 // device scratch (no device allocation).  The host tables are packed into one
 // buffer at 16-byte aligned offsets and copied with one stream-ordered copy.
-gd_status score_poses_noalloc(const gd_pocket* P, const gd_ligands* topo, int32_t n_poses, const int32_t* pose_lig,
+gd_status score_poses_noalloc(const gd_pocket* P, const gd_ligands* topo0, int32_t n_poses, const int32_t* pose_lig,
                               const float* px, const float* py, const float* pz, float clash_dist, int32_t min_bonds,
                               hipStream_t s, int32_t* S_out, uint8_t* clash_out) {
     const char* who = "gd_score_poses_noalloc";
-    if (!P || !topo || !S_out || !clash_out) return fail(GD_ERR_ARG, "%s: null argument", who);
+    if (!P || !topo0 || !S_out || !clash_out) return fail(GD_ERR_ARG, "%s: null argument", who);
     if (n_poses > 0 && (!px || !py || !pz)) return fail(GD_ERR_ARG, "%s: null coordinates", who);
     if (!(clash_dist >= 0.f) || clash_dist > 100.f) return fail(GD_ERR_ARG, "%s: bad clash_dist", who);
     TopoHost T;
     gd_status st;
+    HostLigands HL;
+    const gd_ligands* topo = nullptr;
+    if ((st = ligands_on_host(topo0, s, HL, &topo, who)) != GD_OK) return st;
     if ((st = prepare_topology(topo, min_bonds, T)) != GD_OK) return st;
     std::vector<int32_t> lig, off;
     if ((st = pose_layout(topo, n_poses, pose_lig, T.n_atoms, lig, off)) != GD_OK) return st;

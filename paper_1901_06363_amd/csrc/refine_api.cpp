@@ -47,16 +47,20 @@ static gd_status setup(const gd_pocket* P, const gd_ligands* topo, int32_t n_pos
     return GD_OK;
 }
 
-gd_status surrogate(const gd_pocket* P, const gd_ligands* topo, int32_t n_poses, const int32_t* pose_lig,
+gd_status surrogate(const gd_pocket* P, const gd_ligands* topo0, int32_t n_poses, const int32_t* pose_lig,
                     const float* px, const float* py, const float* pz, const float* t, const float* q,
                     const float* tau, int32_t tau_stride, const gd_bump_penalty* pb, const float* dF, hipStream_t s,
                     float* F_out, float* dt_out, float* dq_out, float* dtau_out, const char* who) {
     if (n_poses > 0 && (!t || !q || (!tau && tau_stride > 0))) return fail(GD_ERR_ARG, "%s: null parameters", who);
     if (dF ? (!dt_out || !dq_out || (tau_stride > 0 && !dtau_out)) : !F_out)
         return fail(GD_ERR_ARG, "%s: null output", who);
+    HostLigands HL;
+    const gd_ligands* topo = nullptr;
+    gd_status st = ligands_on_host(topo0, s, HL, &topo, who);
+    if (st != GD_OK) return st;
     AsyncScratch A(s);
     SurrogateCall C;
-    gd_status st = setup(P, topo, n_poses, pose_lig, px, py, pz, A, C, who);
+    st = setup(P, topo, n_poses, pose_lig, px, py, pz, A, C, who);
     if (st != GD_OK) return st;
     if (tau_stride < C.rmax) return fail(GD_ERR_ARG, "%s: tau_stride %d < rotamers %d", who, tau_stride, C.rmax);
     Penalty pen{};
@@ -82,7 +86,7 @@ gd_status surrogate(const gd_pocket* P, const gd_ligands* topo, int32_t n_poses,
     return e == hipSuccess ? GD_OK : hip_fail(e, who);
 }
 
-gd_status refine(const gd_pocket* P, const gd_ligands* topo, int32_t n_poses, const int32_t* pose_lig, float* px,
+gd_status refine(const gd_pocket* P, const gd_ligands* topo0, int32_t n_poses, const int32_t* pose_lig, float* px,
                  float* py, float* pz, const gd_refine_opts* o, float clash_dist, int32_t min_bonds, hipStream_t s,
                  float* F_out, int32_t* S_out, uint8_t* clash_out, uint8_t* accepted_out, float* rx_out,
                  float* ry_out, float* rz_out) {
@@ -94,9 +98,13 @@ gd_status refine(const gd_pocket* P, const gd_ligands* topo, int32_t n_poses, co
     if (!(clash_dist >= 0.f) || clash_dist > 100.f) return fail(GD_ERR_ARG, "%s: bad clash_dist", who);
     if (!(o->clash_weight >= 0.f) || !std::isfinite(o->clash_weight))
         return fail(GD_ERR_ARG, "%s: clash_weight must be finite and >= 0", who);
+    HostLigands HL;
+    const gd_ligands* topo = nullptr;
+    gd_status st = ligands_on_host(topo0, s, HL, &topo, who);
+    if (st != GD_OK) return st;
     AsyncScratch A(s);
     SurrogateCall C;
-    gd_status st = setup(P, topo, n_poses, pose_lig, px, py, pz, A, C, who);
+    st = setup(P, topo, n_poses, pose_lig, px, py, pz, A, C, who);
     if (st != GD_OK) return st;
     TopoHost TH;
     if ((st = prepare_topology(topo, min_bonds, TH)) != GD_OK) return st;

@@ -632,42 +632,109 @@ static void quat_matrix(const double* q, double* R) {
     R[6] = 2.0 * (x * z - w * y);       R[7] = 2.0 * (y * z + w * x);       R[8] = 1.0 - 2.0 * (x * x + y * y);
 }
 
-gd_status prepare_batch(const gd_pocket* pocket, const gd_ligands* L, const gd_knobs* K, hipStream_t stream,
-                        gd_batch** out) {
-    if (!pocket || !out) return fail(GD_ERR_ARG, "gd_prepare_batch: null argument");
-    *out = nullptr;
+// --------------------------------------------------------------------------
+// ligand descriptors in device memory
+
+bool is_device_ptr(const void* p) {
+    if (!p) return false;
+    hipPointerAttribute_t a;
+    hipError_t e = hipPointerGetAttributes(&a, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();  // unknown (pageable host) pointers are reported as an error
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+gd_status ligands_on_host(const gd_ligands* L, hipStream_t s, HostLigands& H, const gd_ligands** out,
+                          const char* who) {
+    *out = L;
+    if (!L) return fail(GD_ERR_ARG, "%s: null ligands", who);
+    if (L->on_device == 0) return GD_OK;
+    if (L->on_device != 1) return fail(GD_ERR_ARG, "%s: on_device must be 0 or 1", who);
+    const int n = L->n_ligands;
+    if (n < 1) return fail(GD_ERR_ARG, "%s: n_ligands < 1", who);
+    const void* arrs[] = {L->atom_off, L->x, L->y, L->z, L->bond_off, L->rot_off};
+    for (const void* a : arrs)
+        if (!is_device_ptr(a)) return fail(GD_ERR_ARG, "%s: on_device is set but an array is not device memory", who);
+    hipError_t e;
+    auto get = [&](auto& vec, const auto* src, size_t count) -> hipError_t {
+        vec.resize(std::max<size_t>(count, 1));
+        if (count == 0) return hipSuccess;
+        return hipMemcpyAsync(vec.data(), src, count * sizeof(vec[0]), hipMemcpyDeviceToHost, s);
+    };
+    if ((e = get(H.atom_off, L->atom_off, n + 1)) != hipSuccess || (e = get(H.bond_off, L->bond_off, n + 1)) != hipSuccess ||
+        (e = get(H.rot_off, L->rot_off, n + 1)) != hipSuccess || (e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_fail(e, who);
+    // the offsets size the other copies: check them first
+    for (int i = 0; i < n; i++)
+        if (H.atom_off[i + 1] < H.atom_off[i] || H.bond_off[i + 1] < H.bond_off[i] || H.rot_off[i + 1] < H.rot_off[i])
+            return fail(GD_ERR_ARG, "ligands: offsets not ascending at %d", i);
+    if (H.atom_off[0] != 0 || H.bond_off[0] != 0 || H.rot_off[0] != 0)
+        return fail(GD_ERR_ARG, "ligands: offsets must start at 0");
+    const size_t na = (size_t)H.atom_off[n], nb = (size_t)H.bond_off[n], nr = (size_t)H.rot_off[n];
+    if ((nb > 0 && !is_device_ptr(L->bonds)) || (nr > 0 && !is_device_ptr(L->rot)))
+        return fail(GD_ERR_ARG, "%s: on_device is set but an array is not device memory", who);
+    if ((e = get(H.x, L->x, na)) != hipSuccess || (e = get(H.y, L->y, na)) != hipSuccess ||
+        (e = get(H.z, L->z, na)) != hipSuccess || (e = get(H.bonds, L->bonds, 2 * nb)) != hipSuccess ||
+        (e = get(H.rot, L->rot, 2 * nr)) != hipSuccess || (e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_fail(e, who);
+    H.view = gd_ligands{n, H.atom_off.data(), H.x.data(), H.y.data(), H.z.data(), H.bond_off.data(),
+                        nb ? H.bonds.data() : nullptr, H.rot_off.data(), nr ? H.rot.data() : nullptr, 0};
+    *out = &H.view;
+    return GD_OK;
+}
+
+// --------------------------------------------------------------------------
+// batch preparation: host tables, then device copies
+
+// Host product of a batch preparation: the tables the kernels read, the
+// scalar fields of the device view (pointers unset) and the sizes of the
+// per-call device scratch.
+struct HostBatch {
+    std::vector<LigMeta> meta;
+    std::vector<RotInfo> rot;
+    std::vector<uint16_t> pairs, efar;
+    std::vector<uint8_t> mv;
+    std::vector<double> qmat;
+    std::vector<int32_t> items;
+    int64_t n_keys = 0, n_ang = 0;
+    int atoms = 0, nmax = 1;
+    BatchDev dev{};
+    gd_batch_info info{};
+    Tiling tiling;
+};
+
+static gd_status prepare_host(const gd_pocket* pocket, const gd_ligands* L, const gd_knobs* K, const char* who,
+                              HostBatch& H) {
     gd_status st;
     if ((st = validate_ligands_struct(L)) != GD_OK) return st;
     if ((st = validate_knobs(K)) != GD_OK) return st;
     std::vector<LigPrep> preps;
     if ((st = prep_all(L, K, false, K->clash_min_bonds, preps)) != GD_OK) return st;
     const int n = L->n_ligands, no = K->n_orient;
-    std::unique_ptr<gd_batch> B(new gd_batch());
-    std::vector<LigMeta> meta(n);
-    std::vector<RotInfo> rot;
-    std::vector<uint16_t> pairs, efar;
-    std::vector<uint8_t> mv;
+    H.meta.resize(n);
     int lmax = 1, rmax = 0, nmax = 1;
     int64_t key_off = 0, ang_off = 0, poses = 0, npairs = 0;
     double flops = 0, bytes = 0;
     for (int i = 0; i < n; i++) {
         LigPrep& p = preps[i];
         LigMeta m = p.meta;
-        m.rot_off = (int32_t)rot.size();
+        m.rot_off = (int32_t)H.rot.size();
         for (RotInfo ri : p.rot) {
-            ri.pair_off += (int32_t)pairs.size();
-            ri.mv_off[0] += (int32_t)mv.size();
-            ri.mv_off[1] += (int32_t)mv.size();
-            rot.push_back(ri);
+            ri.pair_off += (int32_t)H.pairs.size();
+            ri.mv_off[0] += (int32_t)H.mv.size();
+            ri.mv_off[1] += (int32_t)H.mv.size();
+            H.rot.push_back(ri);
         }
-        m.far_off = (int32_t)efar.size();
+        m.far_off = (int32_t)H.efar.size();
         m.n_far = (int32_t)p.efar.size();
-        pairs.insert(pairs.end(), p.pairs.begin(), p.pairs.end());
-        mv.insert(mv.end(), p.mv.begin(), p.mv.end());
-        efar.insert(efar.end(), p.efar.begin(), p.efar.end());
+        H.pairs.insert(H.pairs.end(), p.pairs.begin(), p.pairs.end());
+        H.mv.insert(H.mv.end(), p.mv.begin(), p.mv.end());
+        H.efar.insert(H.efar.end(), p.efar.begin(), p.efar.end());
         m.key_off = key_off;
         if (ang_off > (int64_t)std::numeric_limits<int32_t>::max())
-            return fail(GD_ERR_CAPACITY, "gd_prepare_batch: angle records exceed 2^31 entries; split the batch");
+            return fail(GD_ERR_CAPACITY, "%s: angle records exceed 2^31 entries; split the batch", who);
         m.ang_off = (int32_t)ang_off;
         key_off += no;
         ang_off += (int64_t)no * K->repetitions * m.nr * 2;
@@ -678,47 +745,112 @@ gd_status prepare_batch(const gd_pocket* pocket, const gd_ligands* L, const gd_k
         lmax = std::max(lmax, m.l);
         rmax = std::max(rmax, m.nr);
         nmax = std::max(nmax, p.nmax);
-        meta[i] = m;
+        H.meta[i] = m;
     }
-    if (pairs.size() > (size_t)std::numeric_limits<int32_t>::max() ||
-        efar.size() > (size_t)std::numeric_limits<int32_t>::max())
-        return fail(GD_ERR_CAPACITY, "gd_prepare_batch: pair lists exceed 2^31 entries; split the batch");
+    if (H.pairs.size() > (size_t)std::numeric_limits<int32_t>::max() ||
+        H.efar.size() > (size_t)std::numeric_limits<int32_t>::max())
+        return fail(GD_ERR_CAPACITY, "%s: pair lists exceed 2^31 entries; split the batch", who);
     // rotation matrices of the orientations
-    std::vector<double> qmat(9 * (size_t)no);
-    for (int o = 0; o < no; o++) quat_matrix(K->quats + 4 * (size_t)o, &qmat[9 * (size_t)o]);
+    H.qmat.resize(9 * (size_t)no);
+    for (int o = 0; o < no; o++) quat_matrix(K->quats + 4 * (size_t)o, &H.qmat[9 * (size_t)o]);
     // work queue: (ligand, orientation block), costliest ligands first
     const int opi = std::max(1, std::min(no, 8));
     std::vector<int> order(n);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return preps[a].cost > preps[b].cost; });
-    std::vector<int32_t> items;
     for (int idx = 0; idx < n; idx++)
         for (int o0 = 0; o0 < no; o0 += opi) {
-            items.push_back(order[idx]);
-            items.push_back(o0);
+            H.items.push_back(order[idx]);
+            H.items.push_back(o0);
         }
-    const int atoms = L->atom_off[n];
+    H.atoms = L->atom_off[n];
+    H.n_keys = key_off;
+    H.n_ang = std::max<int64_t>(ang_off, 1);
+    H.nmax = nmax;
+    BatchDev& D = H.dev;
+    D.n_lig = n;
+    D.n_orient = no;
+    D.reps = K->repetitions;
+    D.top_k = K->top_k;
+    D.lmax = lmax;
+    D.rmax = std::max(rmax, 1);
+    const double cd = (double)K->clash_dist;
+    D.cd2 = cd * cd;
+    D.cd2f = (float)D.cd2;
+    D.n_items = (int32_t)(H.items.size() / 2);
+    D.orient_per_item = opi;
+    gd_batch_info& I = H.info;
+    I.n_ligands = n;
+    I.max_atoms = lmax;
+    I.max_rot = D.rmax;
+    I.repetitions = K->repetitions;
+    I.top_k = K->top_k;
+    I.n_orient = no;
+    I.poses_expected = poses;
+    I.n_pairs_total = npairs;
+    I.n_atoms_total = H.atoms;
+    I.algo_flops = flops;
+    I.algo_bytes = bytes;
+    while (H.tiling.waves_per_block > 1 && dock_lds_bytes(lmax, nmax, H.tiling.waves_per_block) > lds_limit_per_block())
+        H.tiling.waves_per_block /= 2;
+    if (const char* env = getenv("GD_TILING")) {
+        int w, nb, ppl;
+        if (sscanf(env, "%d,%d,%d", &w, &nb, &ppl) == 3 && tiling_supported(w, nb, ppl)) {
+            H.tiling.waves_per_block = w;
+            H.tiling.angle_block = nb;
+            H.tiling.pairs_per_lane = ppl;
+        }
+    }
+    (void)pocket;
+    return GD_OK;
+}
+
+gd_status prepare_batch(const gd_pocket* pocket, const gd_ligands* L0, const gd_knobs* K, hipStream_t stream,
+                        gd_batch** out) {
+    const char* who = "gd_prepare_batch";
+    if (!pocket || !out) return fail(GD_ERR_ARG, "%s: null argument", who);
+    *out = nullptr;
+    gd_status st;
+    HostLigands HL;
+    const gd_ligands* L = nullptr;
+    if ((st = ligands_on_host(L0, stream, HL, &L, who)) != GD_OK) return st;
+    HostBatch H;
+    if ((st = prepare_host(pocket, L, K, who, H)) != GD_OK) return st;
+    std::unique_ptr<gd_batch> B(new gd_batch());
     hipError_t e;
 #define UP(buf, vec)                                                                                      \
     if ((e = B->buf.upload((vec).data(), (vec).size() * sizeof((vec)[0]), stream)) != hipSuccess)         \
-        return hip_fail(e, "gd_prepare_batch");
-    UP(lig, meta);
-    UP(rot, rot);
-    UP(pairs, pairs);
-    UP(mv, mv);
-    UP(efar, efar);
-    UP(qmat, qmat);
-    UP(items, items);
+        return hip_fail(e, who);
+    UP(lig, H.meta);
+    UP(rot, H.rot);
+    UP(pairs, H.pairs);
+    UP(mv, H.mv);
+    UP(efar, H.efar);
+    UP(qmat, H.qmat);
+    UP(items, H.items);
 #undef UP
-    if ((e = B->x.upload(L->x, sizeof(float) * atoms, stream)) != hipSuccess) return hip_fail(e, "gd_prepare_batch");
-    if ((e = B->y.upload(L->y, sizeof(float) * atoms, stream)) != hipSuccess) return hip_fail(e, "gd_prepare_batch");
-    if ((e = B->z.upload(L->z, sizeof(float) * atoms, stream)) != hipSuccess) return hip_fail(e, "gd_prepare_batch");
-    if ((e = B->keys.alloc(sizeof(uint64_t) * (size_t)key_off)) != hipSuccess) return hip_fail(e, "gd_prepare_batch");
-    if ((e = B->ang.alloc(sizeof(uint16_t) * (size_t)std::max<int64_t>(ang_off, 1))) != hipSuccess)
-        return hip_fail(e, "gd_prepare_batch");
-    if ((e = B->head.alloc(64)) != hipSuccess) return hip_fail(e, "gd_prepare_batch");
-    if ((e = B->counters.alloc(sizeof(int64_t) * GD_N_COUNTERS)) != hipSuccess) return hip_fail(e, "gd_prepare_batch");
+    const size_t cb = sizeof(float) * (size_t)H.atoms;
+    if (L0->on_device) {
+        // device to device: the batch outlives the caller's arrays
+        DevBuf* dst[3] = {&B->x, &B->y, &B->z};
+        const float* src[3] = {L0->x, L0->y, L0->z};
+        for (int c = 0; c < 3; c++) {
+            if ((e = dst[c]->alloc(cb)) != hipSuccess ||
+                (cb && (e = hipMemcpyAsync(dst[c]->ptr, src[c], cb, hipMemcpyDeviceToDevice, stream)) != hipSuccess))
+                return hip_fail(e, who);
+        }
+        if ((e = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(e, who);
+    } else {
+        if ((e = B->x.upload(L->x, cb, stream)) != hipSuccess || (e = B->y.upload(L->y, cb, stream)) != hipSuccess ||
+            (e = B->z.upload(L->z, cb, stream)) != hipSuccess)
+            return hip_fail(e, who);
+    }
+    if ((e = B->keys.alloc(sizeof(uint64_t) * (size_t)H.n_keys)) != hipSuccess ||
+        (e = B->ang.alloc(sizeof(uint16_t) * (size_t)H.n_ang)) != hipSuccess || (e = B->head.alloc(64)) != hipSuccess ||
+        (e = B->counters.alloc(sizeof(int64_t) * GD_N_COUNTERS)) != hipSuccess)
+        return hip_fail(e, who);
     BatchDev& D = B->dev;
+    D = H.dev;
     D.lig = (const LigMeta*)B->lig.ptr;
     D.rot = (const RotInfo*)B->rot.ptr;
     D.x = (const float*)B->x.ptr;
@@ -728,77 +860,54 @@ gd_status prepare_batch(const gd_pocket* pocket, const gd_ligands* L, const gd_k
     D.mv = (const uint8_t*)B->mv.ptr;
     D.efar = (const uint16_t*)B->efar.ptr;
     D.qmat = (const double*)B->qmat.ptr;
-    D.n_lig = n;
-    D.n_orient = no;
-    D.reps = K->repetitions;
-    D.top_k = K->top_k;
-    D.lmax = lmax;
-    D.rmax = std::max(rmax, 1);
-    double cd = (double)K->clash_dist;
-    D.cd2 = cd * cd;
-    D.cd2f = (float)D.cd2;
     D.keys = (uint64_t*)B->keys.ptr;
     D.ang = (uint16_t*)B->ang.ptr;
     D.items = (const int32_t*)B->items.ptr;
-    D.n_items = (int32_t)(items.size() / 2);
-    D.orient_per_item = opi;
     D.head = (int32_t*)B->head.ptr;
     D.counters = (unsigned long long*)B->counters.ptr;
-    B->nmax = nmax;
-    B->info.n_ligands = n;
-    B->info.max_atoms = lmax;
-    B->info.max_rot = D.rmax;
-    B->info.repetitions = K->repetitions;
-    B->info.top_k = K->top_k;
-    B->info.n_orient = no;
-    B->info.poses_expected = poses;
-    B->info.n_pairs_total = npairs;
-    B->info.n_atoms_total = atoms;
-    B->info.algo_flops = flops;
-    B->info.algo_bytes = bytes;
+    B->nmax = H.nmax;
+    B->info = H.info;
     B->h = pocket->dev.h;
-    while (B->tiling.waves_per_block > 1 &&
-           dock_lds_bytes(lmax, nmax, B->tiling.waves_per_block) > lds_limit_per_block())
-        B->tiling.waves_per_block /= 2;
-    if ((e = B->devcopy.upload(&B->dev, sizeof(BatchDev), stream)) != hipSuccess) return hip_fail(e, "gd_prepare_batch");
-    if (const char* env = getenv("GD_TILING")) {
-        int w, nb, ppl;
-        if (sscanf(env, "%d,%d,%d", &w, &nb, &ppl) == 3 && tiling_supported(w, nb, ppl)) {
-            B->tiling.waves_per_block = w;
-            B->tiling.angle_block = nb;
-            B->tiling.pairs_per_lane = ppl;
-        }
-    }
+    B->tiling = H.tiling;
+    if ((e = B->devcopy.upload(&B->dev, sizeof(BatchDev), stream)) != hipSuccess) return hip_fail(e, who);
     *out = B.release();
     return GD_OK;
 }
 
 // The two stages of a docking call: queue reset + docking kernel, then top-k
 // and pose replay.
-static hipError_t enqueue_dock_stage(const gd_pocket* P, gd_batch* B, gd_mode mode, hipStream_t s, int64_t* counters) {
-    const BatchDev& D = B->dev;
-    DockLaunch L{(const PocketDev*)P->devcopy.ptr, (const BatchDev*)B->devcopy.ptr,
-                 counters ? (unsigned long long*)counters : D.counters, D.lmax, B->nmax};
+static hipError_t enqueue_dock(const gd_pocket* P, const BatchDev& D, const BatchDev* Ddev, const Tiling& t, int nmax,
+                               gd_mode mode, hipStream_t s, unsigned long long* counters) {
+    DockLaunch L{(const PocketDev*)P->devcopy.ptr, Ddev, counters, D.lmax, nmax};
     hipError_t e;
     if ((e = launch_reset(D.head, L.counters, s)) != hipSuccess) return e;
     if (mode == GD_BATCHED) {
-        int grid = persistent_grid(B->tiling, D.lmax, B->nmax, D.n_items);
-        return launch_dock(L, B->tiling, true, 0, grid, s);
+        int grid = persistent_grid(t, D.lmax, nmax, D.n_items);
+        return launch_dock(L, t, true, 0, grid, s);
     }
-    const int w = B->tiling.waves_per_block;
-    const int grid = (D.n_orient + w - 1) / w;
+    const int grid = (D.n_orient + t.waves_per_block - 1) / t.waves_per_block;
     for (int i = 0; i < D.n_lig; i++)
-        if ((e = launch_dock(L, B->tiling, false, i, grid, s)) != hipSuccess) return e;
+        if ((e = launch_dock(L, t, false, i, grid, s)) != hipSuccess) return e;
     return hipSuccess;
+}
+
+static hipError_t enqueue_post(const gd_pocket* P, const BatchDev& D, double h, int nmax, hipStream_t s,
+                               gd_pose_rec* out, uint16_t* angles, float* pose_xyz) {
+    hipError_t e;
+    if ((e = launch_topk(D, out, angles, h, s)) != hipSuccess) return e;
+    if (pose_xyz)
+        if ((e = launch_replay(P->dev, D, out, pose_xyz, nmax, s)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+static hipError_t enqueue_dock_stage(const gd_pocket* P, gd_batch* B, gd_mode mode, hipStream_t s, int64_t* counters) {
+    return enqueue_dock(P, B->dev, (const BatchDev*)B->devcopy.ptr, B->tiling, B->nmax, mode, s,
+                        counters ? (unsigned long long*)counters : B->dev.counters);
 }
 
 static hipError_t enqueue_post_stage(const gd_pocket* P, gd_batch* B, hipStream_t s, gd_pose_rec* out,
                                      uint16_t* angles, float* pose_xyz) {
-    hipError_t e;
-    if ((e = launch_topk(B->dev, out, angles, B->h, s)) != hipSuccess) return e;
-    if (pose_xyz)
-        if ((e = launch_replay(P->dev, B->dev, out, pose_xyz, B->nmax, s)) != hipSuccess) return e;
-    return hipSuccess;
+    return enqueue_post(P, B->dev, B->h, B->nmax, s, out, angles, pose_xyz);
 }
 
 static hipError_t capture(hipStream_t s, hipGraphExec_t* exec, const std::function<hipError_t()>& body) {
@@ -863,6 +972,192 @@ gd_status dock_prepared(const gd_pocket* P, gd_batch* B, gd_mode mode, hipStream
     if ((e = timing_mark(B, s, true)) != hipSuccess || (e = hipGraphLaunch(B->graph_dock, s)) != hipSuccess ||
         (e = timing_mark(B, s, false)) != hipSuccess || (e = hipGraphLaunch(B->graph_post, s)) != hipSuccess)
         return hip_fail(e, "gd_dock_prepared: graph launch");
+    return GD_OK;
+}
+
+// --------------------------------------------------------------------------
+// pinned staging buffers for the asynchronous uploads of gd_dock_batch
+
+namespace {
+struct Staging {
+    void* host = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;  // recorded on the stream after the copy out of the buffer
+    int device = -1;
+    int state = 0;              // 0 idle, 1 held by a call, 2 copy in flight
+};
+std::mutex g_stage_mu;
+std::vector<Staging*> g_stage;  // kept for reuse until the process ends
+}  // namespace
+
+// A pinned host buffer of at least n bytes, held by the caller until
+// stage_release; idle buffers too small for the request are freed.
+static hipError_t stage_acquire(size_t n, Staging** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lock(g_stage_mu);
+    Staging* pick = nullptr;
+    for (Staging* st : g_stage) {
+        if (st->device != dev) continue;
+        if (st->state == 2) {
+            hipError_t q = hipEventQuery(st->done);
+            if (q == hipErrorNotReady) {
+                (void)hipGetLastError();
+                continue;
+            }
+            if (q != hipSuccess) return q;
+            st->state = 0;
+        }
+        if (st->state == 0 && st->cap >= n && (!pick || st->cap < pick->cap)) pick = st;
+    }
+    if (!pick) {
+        for (auto it = g_stage.begin(); it != g_stage.end();) {
+            Staging* st = *it;
+            if (st->device == dev && st->state == 0 && st->cap < n) {
+                (void)hipHostFree(st->host);
+                (void)hipEventDestroy(st->done);
+                delete st;
+                it = g_stage.erase(it);
+            } else {
+                ++it;
+            }
+        }
+        std::unique_ptr<Staging> st(new Staging());
+        st->cap = std::max<size_t>(n, (size_t)1 << 20);
+        if ((e = hipHostMalloc(&st->host, st->cap, hipHostMallocDefault)) != hipSuccess) return e;
+        if ((e = hipEventCreateWithFlags(&st->done, hipEventDisableTiming)) != hipSuccess) {
+            (void)hipHostFree(st->host);
+            return e;
+        }
+        st->device = dev;
+        pick = st.release();
+        g_stage.push_back(pick);
+    }
+    pick->state = 1;
+    *out = pick;
+    return hipSuccess;
+}
+
+// Give the buffer back: after the copy enqueued on s (copied = true) or at once.
+static hipError_t stage_release(Staging* st, hipStream_t s, bool copied) {
+    std::lock_guard<std::mutex> lock(g_stage_mu);
+    if (!copied) {
+        st->state = 0;
+        return hipSuccess;
+    }
+    hipError_t e = hipEventRecord(st->done, s);
+    st->state = e == hipSuccess ? 2 : 0;
+    return e;
+}
+
+gd_status dock_batch(const gd_pocket* P, const gd_ligands* L0, const gd_knobs* K, gd_mode mode, hipStream_t s,
+                     gd_pose_rec* out, uint16_t* angles, float* pose_xyz, int64_t* counters) {
+    const char* who = "gd_dock_batch";
+    if (!P || !out) return fail(GD_ERR_ARG, "%s: null argument", who);
+    if (mode != GD_PER_LIGAND && mode != GD_BATCHED) return fail(GD_ERR_ARG, "%s: bad mode", who);
+    gd_status st;
+    HostLigands HL;
+    const gd_ligands* L = nullptr;
+    if ((st = ligands_on_host(L0, s, HL, &L, who)) != GD_OK) return st;
+    HostBatch H;
+    if ((st = prepare_host(P, L, K, who, H)) != GD_OK) return st;
+    const BatchDev& D0 = H.dev;
+    const size_t lds = dock_lds_bytes(D0.lmax, H.nmax, H.tiling.waves_per_block);
+    if (lds > lds_limit_per_block())
+        return fail(GD_ERR_CAPACITY, "%s: the batch needs %zu B of LDS per block, the device allows %zu", who, lds,
+                    lds_limit_per_block());
+    // outputs in device memory are written in place, host outputs through device scratch
+    const size_t n_rec = (size_t)D0.n_lig * D0.top_k;
+    const size_t b_out = n_rec * sizeof(gd_pose_rec), b_ang = n_rec * D0.reps * D0.rmax * 2 * sizeof(uint16_t),
+                 b_xyz = n_rec * D0.lmax * 3 * sizeof(float), b_cnt = GD_N_COUNTERS * sizeof(int64_t);
+    void* user[4] = {out, angles, pose_xyz, counters};
+    const size_t ubytes[4] = {b_out, b_ang, b_xyz, b_cnt};
+    bool via_host[4];
+    bool sync = false;
+    for (int k = 0; k < 4; k++) {
+        via_host[k] = user[k] && !is_device_ptr(user[k]);
+        sync |= via_host[k];
+    }
+    // one stream-ordered arena: the staged tables first (one copy), then scratch
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        const size_t at = off;
+        off += (b + 255) & ~(size_t)255;
+        return at;
+    };
+    const size_t o_lig = take(H.meta.size() * sizeof(LigMeta)), o_rot = take(H.rot.size() * sizeof(RotInfo)),
+                 o_pairs = take(H.pairs.size() * 2), o_mv = take(H.mv.size()), o_efar = take(H.efar.size() * 2),
+                 o_qmat = take(H.qmat.size() * 8), o_items = take(H.items.size() * 4);
+    const size_t cb = sizeof(float) * (size_t)H.atoms;
+    const bool own_xyz = L0->on_device == 0;
+    const size_t o_x = own_xyz ? take(cb) : 0, o_y = own_xyz ? take(cb) : 0, o_z = own_xyz ? take(cb) : 0;
+    const size_t o_dev = take(sizeof(BatchDev));
+    const size_t staged = off;
+    const size_t o_keys = take(sizeof(uint64_t) * (size_t)H.n_keys), o_ang = take(sizeof(uint16_t) * (size_t)H.n_ang),
+                 o_head = take(64), o_cnt = take(b_cnt);
+    size_t o_user[4];
+    for (int k = 0; k < 4; k++) o_user[k] = via_host[k] ? take(ubytes[k]) : 0;
+    char* arena = nullptr;
+    hipError_t e = hipMallocAsync((void**)&arena, off, s);
+    if (e != hipSuccess) return hip_fail(e, who);
+    Staging* stg = nullptr;
+    bool copied = false;
+    auto bail = [&](hipError_t err) {
+        if (stg) (void)stage_release(stg, s, copied);
+        (void)hipFreeAsync(arena, s);
+        return hip_fail(err, who);
+    };
+    if ((e = stage_acquire(staged, &stg)) != hipSuccess) return bail(e);
+    char* hs = (char*)stg->host;
+    auto put = [&](size_t at, const void* src, size_t b) {
+        if (b) memcpy(hs + at, src, b);
+    };
+    put(o_lig, H.meta.data(), H.meta.size() * sizeof(LigMeta));
+    put(o_rot, H.rot.data(), H.rot.size() * sizeof(RotInfo));
+    put(o_pairs, H.pairs.data(), H.pairs.size() * 2);
+    put(o_mv, H.mv.data(), H.mv.size());
+    put(o_efar, H.efar.data(), H.efar.size() * 2);
+    put(o_qmat, H.qmat.data(), H.qmat.size() * 8);
+    put(o_items, H.items.data(), H.items.size() * 4);
+    if (own_xyz) {
+        put(o_x, L->x, cb);
+        put(o_y, L->y, cb);
+        put(o_z, L->z, cb);
+    }
+    BatchDev D = D0;
+    D.lig = (const LigMeta*)(arena + o_lig);
+    D.rot = (const RotInfo*)(arena + o_rot);
+    D.pairs = (const uint16_t*)(arena + o_pairs);
+    D.mv = (const uint8_t*)(arena + o_mv);
+    D.efar = (const uint16_t*)(arena + o_efar);
+    D.qmat = (const double*)(arena + o_qmat);
+    D.items = (const int32_t*)(arena + o_items);
+    D.x = own_xyz ? (const float*)(arena + o_x) : L0->x;  // device inputs are read in place
+    D.y = own_xyz ? (const float*)(arena + o_y) : L0->y;
+    D.z = own_xyz ? (const float*)(arena + o_z) : L0->z;
+    D.keys = (uint64_t*)(arena + o_keys);
+    D.ang = (uint16_t*)(arena + o_ang);
+    D.head = (int32_t*)(arena + o_head);
+    D.counters = (unsigned long long*)(arena + o_cnt);
+    put(o_dev, &D, sizeof(BatchDev));
+    if ((e = hipMemcpyAsync(arena, hs, staged, hipMemcpyHostToDevice, s)) != hipSuccess) return bail(e);
+    copied = true;
+    e = stage_release(stg, s, true);
+    stg = nullptr;
+    if (e != hipSuccess) return bail(e);
+    void* dst[4];
+    for (int k = 0; k < 4; k++) dst[k] = via_host[k] ? (void*)(arena + o_user[k]) : user[k];
+    if ((e = enqueue_dock(P, D, (const BatchDev*)(arena + o_dev), H.tiling, H.nmax, mode, s,
+                          dst[3] ? (unsigned long long*)dst[3] : D.counters)) != hipSuccess ||
+        (e = enqueue_post(P, D, P->dev.h, H.nmax, s, (gd_pose_rec*)dst[0], (uint16_t*)dst[1], (float*)dst[2])) !=
+            hipSuccess)
+        return bail(e);
+    for (int k = 0; k < 4; k++)
+        if (via_host[k] && (e = hipMemcpyAsync(user[k], dst[k], ubytes[k], hipMemcpyDeviceToHost, s)) != hipSuccess)
+            return bail(e);
+    if ((e = hipFreeAsync(arena, s)) != hipSuccess) return hip_fail(e, who);
+    if (sync && (e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, who);
     return GD_OK;
 }
 
@@ -1004,14 +1299,7 @@ gd_status gd_dock_prepared(const gd_pocket* pocket, gd_batch* batch, gd_mode mod
 gd_status gd_dock_batch(const gd_pocket* pocket, const gd_ligands* ligands, const gd_knobs* knobs, gd_mode mode,
                         void* stream, gd_pose_rec* out, uint16_t* angles, float* pose_xyz, int64_t* counters) {
     clear_error();
-    gd_batch* B = nullptr;
-    gd_status st = prepare_batch(pocket, ligands, knobs, (hipStream_t)stream, &B);
-    if (st != GD_OK) return st;
-    st = dock_prepared(pocket, B, mode, (hipStream_t)stream, out, angles, pose_xyz, counters);
-    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
-    delete B;
-    if (st != GD_OK) return st;
-    return e == hipSuccess ? GD_OK : hip_fail(e, "gd_dock_batch");
+    return dock_batch(pocket, ligands, knobs, mode, (hipStream_t)stream, out, angles, pose_xyz, counters);
 }
 
 }  // extern "C"

@@ -58,6 +58,19 @@ struct TreeHost {
 gd_status prepare_tree(const gd_ligands* L, TreeHost& out);
 gd_status validate_ligands_struct(const gd_ligands* L);
 
+// Host view of a ligand descriptor.  Host arrays (on_device = 0) are used as
+// they are; device arrays are copied to host vectors on `s` (after the
+// stream's earlier work) for the host-side validation and preparation.
+struct HostLigands {
+    gd_ligands view{};
+    std::vector<int32_t> atom_off, bond_off, bonds, rot_off, rot;
+    std::vector<float> x, y, z;
+};
+gd_status ligands_on_host(const gd_ligands* L, hipStream_t s, HostLigands& H, const gd_ligands** out,
+                          const char* who);
+// True when p is device (or managed) memory of the HIP runtime.
+bool is_device_ptr(const void* p);
+
 // Stream-ordered device copies of small host arrays, released after the call.
 struct AsyncScratch {
     hipStream_t s;

@@ -1,7 +1,9 @@
 /*
  * Docking through the C ABI alone (no Python): reads one small input file,
  * creates the pocket, docks every ligand of the file in the batched mode and
- * prints the ranked poses.
+ * prints the ranked poses.  Then docks again from device-resident ligand
+ * arrays (on_device = 1) on a stream of its own, asynchronously, and reports
+ * whether the ranked poses are identical.
  *
  * Input (little endian): int32 n_points, float32[3 n_points] points,
  * int32 n_ligands, int32 atom_off[n+1], float32 x, y, z[atoms],
@@ -9,7 +11,7 @@
  * int32 rot[2 rotamers], int32 n_orient, float64 quats[4 n_orient],
  * int32 hp_step, int32 top_k.
  * Output: one line per ranked pose, "ligand rank orient S clash overlap",
- * then "poses <candidate poses scored>".
+ * then "device-resident inputs identical <0|1>", then "poses <candidate poses scored>".
  *
  * Build: gcc -I<repo>/include -I/opt/rocm/include -D__HIP_PLATFORM_AMD__
  *        dock_file.c -L<lib dir> -lgd -L/opt/rocm/lib -lamdhip64
@@ -55,6 +57,14 @@ static int32_t take_i32(FILE* f) {
             return 1;                                                   \
         }                                                               \
     } while (0)
+
+/* a device copy of a host array (at least 4 bytes allocated); 0 on success */
+static int to_device(void** dst, const void* src, size_t bytes) {
+    hipError_t e = hipMalloc(dst, bytes ? bytes : 4);
+    if (e == hipSuccess && bytes) e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) fprintf(stderr, "device copy failed: %s\n", hipGetErrorString(e));
+    return e != hipSuccess;
+}
 
 int main(int argc, char** argv) {
     if (argc != 2) {
@@ -109,7 +119,39 @@ int main(int argc, char** argv) {
             const gd_pose_rec* r = out + (size_t)i * top_k + k;
             printf("%d %d %d %d %d %.17g\n", i, k, r->orient, r->S, r->clash, r->overlap);
         }
+
+    /* the same ligands from device memory, on a stream of its own */
+    int32_t *d_atom_off, *d_bond_off, *d_bonds, *d_rot_off, *d_rot;
+    float *d_x, *d_y, *d_z;
+    const size_t nb = (size_t)bond_off[n], nr = (size_t)rot_off[n];
+    if (to_device((void**)&d_atom_off, atom_off, sizeof(int32_t) * (size_t)(n + 1)) ||
+        to_device((void**)&d_x, x, sizeof(float) * (size_t)na) || to_device((void**)&d_y, y, sizeof(float) * (size_t)na) ||
+        to_device((void**)&d_z, z, sizeof(float) * (size_t)na) ||
+        to_device((void**)&d_bond_off, bond_off, sizeof(int32_t) * (size_t)(n + 1)) ||
+        to_device((void**)&d_bonds, bonds, sizeof(int32_t) * 2 * nb) ||
+        to_device((void**)&d_rot_off, rot_off, sizeof(int32_t) * (size_t)(n + 1)) ||
+        to_device((void**)&d_rot, rot, sizeof(int32_t) * 2 * nr))
+        return 1;
+    gd_ligands DL = {n, d_atom_off, d_x, d_y, d_z, d_bond_off, d_bonds, d_rot_off, d_rot, 1};
+    hipStream_t st;
+    CHECK_HIP(hipStreamCreate(&st));
+    gd_pose_rec* d_out2 = NULL;
+    CHECK_HIP(hipMalloc((void**)&d_out2, sizeof(gd_pose_rec) * n_rec));
+    CHECK_GD(gd_dock_batch(pocket, &DL, &K, GD_BATCHED, (void*)st, d_out2, NULL, NULL, NULL));
+    CHECK_HIP(hipStreamSynchronize(st));
+    gd_pose_rec* out2 = (gd_pose_rec*)malloc(sizeof(gd_pose_rec) * n_rec);
+    CHECK_HIP(hipMemcpy(out2, d_out2, sizeof(gd_pose_rec) * n_rec, hipMemcpyDeviceToHost));
+    int same = 1;
+    for (size_t r = 0; r < n_rec; r++)
+        same &= out[r].orient == out2[r].orient && out[r].S == out2[r].S && out[r].clash == out2[r].clash &&
+                out[r].n_atoms == out2[r].n_atoms && out[r].overlap == out2[r].overlap;
+    printf("device-resident inputs identical %d\n", same);
     printf("poses %lld\n", (long long)cnt[GD_CNT_POSES]);
+    (void)hipFree(d_out2);
+    (void)hipFree(d_atom_off); (void)hipFree(d_x); (void)hipFree(d_y); (void)hipFree(d_z);
+    (void)hipFree(d_bond_off); (void)hipFree(d_bonds); (void)hipFree(d_rot_off); (void)hipFree(d_rot);
+    CHECK_HIP(hipStreamDestroy(st));
+    free(out2);
 
     (void)hipFree(d_out);
     (void)hipFree(d_cnt);

@@ -1,6 +1,8 @@
 """The C ABI used from C alone: tests/c_abi/dock_file.c compiles and links
 against include/gd.h and libgd.so (CPU); on the GPU its ranked poses equal the
-Python binding's on the same input file."""
+Python binding's on the same input file, and docking the same ligands from
+device-resident arrays (on_device = 1, asynchronous on a stream of its own)
+gives the same poses."""
 import os
 import shutil
 import struct
@@ -62,7 +64,8 @@ def test_c_program_matches_binding(tmp_path):
     assert out.returncode == 0, out.stderr
     lines = out.stdout.strip().splitlines()
     assert lines[-1].startswith("poses ")
-    rows = np.array([[float(v) for v in ln.split()] for ln in lines[:-1]])
+    assert lines[-2] == "device-resident inputs identical 1", lines[-2]
+    rows = np.array([[float(v) for v in ln.split()] for ln in lines[:-2]])
     P = g.Pocket(pts, 0.5, 12.0)
     b = g.Batch(P, ligs, q, hp=10, top_k=3)
     h = b.dock(g.BATCHED).host()
