@@ -8,12 +8,20 @@
 // FK_tau rotates, root (atom 0) first, the side of every rotamer that does not
 // hold atom 0 by tau_b about its current axis (near -> far atom, right-handed).
 //
-// Backward pass (no stored activations: the pose is recomputed):
-//   dF/dt     = sum_i g_i,               g_i = grad rho~(X_i)
-//   dF/dq     = (I - qh qh^T)/|q| * <G, dR/dqh>,  G = sum_i g_i (Y_i - c0)^T
+// Backward pass (no stored activations: the pose is recomputed), with
+// o = c0 + t the centre of the rigid rotation and g_i = grad rho~(X_i):
+//   dF/dt     = sum_i g_i
+//   dF/dq     = (I - qh qh^T)/|q| * d(omega)/dqh . T,  T = sum_i (X_i - o) x g_i
 //   dF/dtau_b = K_b . sum_{i moving} (X_i - A_b) x g_i
-//             = K_b . (sum x_i x g_i - A_b x sum g_i)   (final-frame axis K_b, A_b)
-// One wavefront per pose; each lane holds two atoms (ligands of <= 128 atoms).
+//             = sum_{i moving} K_b . ((X_i - o) x g_i) - (K_b x (A_b - o)) . g_i
+// (final-frame axis K_b through A_b).  Lever arms are taken from o, so the sums
+// do not cancel for poses far from the coordinate origin.
+//
+// One wavefront per pose.  A ligand of at most 64 atoms has one atom per lane
+// (one slot); a larger one two (atom i in lane i % 64 of slot i / 64).  The
+// per-rotamer gradient terms are summed eight rotamers at a time by one
+// transposed reduction, and the final-frame axes are formed one rotamer per
+// lane.  Internally torsions are kept in tree order (root first).
 #include <hip/hip_runtime.h>
 
 #include "device_common.h"
@@ -26,18 +34,24 @@
 
 namespace gd {
 
-constexpr int kSlots = kMaxAtoms / kWave;  // atoms per lane
+constexpr int kSlotsMax = kMaxAtoms / kWave;  // atom slots per lane for the largest ligands
+static_assert(kSlotsMax == 2, "one or two atom slots per lane");
+static_assert(kMaxRot <= kWave, "one torsion per lane");
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+
+__device__ __forceinline__ float rlane(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
 
 // Sum over the wavefront, the total in every lane, without LDS: a butterfly
 // of DPP lane permutations (lane ^ 1, lane ^ 2, the two quads of a half row,
 // the two halves of a row) and then the gfx950 permlane swaps of rows of 16
 // and halves of the wave (the two outputs of a swap hold a lane's value and
 // its partner's).
-template <int CTRL>
-__device__ __forceinline__ float dpp_f(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
-}
-
 __device__ __forceinline__ float wsum(float v) {
     v += dpp_f<0xB1>(v);   // quad_perm [1,0,3,2]
     v += dpp_f<0x4E>(v);   // quad_perm [2,3,0,1]
@@ -49,12 +63,41 @@ __device__ __forceinline__ float wsum(float v) {
     return __int_as_float((int)q[0]) + __int_as_float((int)q[1]);
 }
 
-// Coordinate of a wave-uniform atom index held in the per-lane slots (atom i
-// lives in lane i % 64 of slot i / 64).
-__device__ __forceinline__ float atom_at(const float Y[kSlots][3], int i, int a) {
-    static_assert(kSlots == 2, "two atom slots per lane");
-    const float lo = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(Y[0][a]), i & 63));
-    const float hi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(Y[1][a]), i & 63));
+// Wave totals of eight values at once (a transposed butterfly): afterwards a
+// lane whose index has bits 5, 4, 3 equal to (b5, b4, b3) holds the total of
+// value 4 b5 + 2 b4 + b3.  A permlane swap of two registers sends half of each
+// to the partner lanes, so every stage halves the values a lane carries:
+// 32-lane halves (8 -> 4 values), 16-lane rows (4 -> 2), 8-lane halves of a
+// row (2 -> 1), then a plain butterfly within groups of eight lanes.
+__device__ __forceinline__ float wsum8(const float v[8]) {
+    float w[4], x[2];
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const auto p = __builtin_amdgcn_permlane32_swap(__float_as_int(v[j]), __float_as_int(v[j + 4]), false, false);
+        w[j] = __int_as_float((int)p[0]) + __int_as_float((int)p[1]);
+    }
+#pragma unroll
+    for (int j = 0; j < 2; j++) {
+        const auto p = __builtin_amdgcn_permlane16_swap(__float_as_int(w[j]), __float_as_int(w[j + 2]), false, false);
+        x[j] = __int_as_float((int)p[0]) + __int_as_float((int)p[1]);
+    }
+    const bool hi = (lane_id() & 8) != 0;
+    float y = (hi ? x[1] : x[0]) + dpp_f<0x128>(hi ? x[0] : x[1]);  // row_ror:8 = lane ^ 8 within a row
+    y += dpp_f<0xB1>(y);
+    y += dpp_f<0x4E>(y);
+    y += dpp_f<0x141>(y);
+    return y;
+}
+
+// The lane of wsum8's output that holds value j.
+__device__ __forceinline__ int wsum8_lane(int j) { return ((j >> 2) & 1) * 32 + ((j >> 1) & 1) * 16 + (j & 1) * 8; }
+
+// Coordinate a of a wave-uniform atom index held in the per-lane slots.
+template <int NS>
+__device__ __forceinline__ float atom_at(const float Y[NS][3], int i, int a) {
+    if (NS == 1) return rlane(Y[0][a], i);
+    const float lo = rlane(Y[0][a], i & 63);
+    const float hi = rlane(Y[NS - 1][a], i & 63);
     return i < kWave ? lo : hi;
 }
 
@@ -96,14 +139,21 @@ __device__ __forceinline__ void quat_mat(const float* q, float* R) {
 }
 
 // Per-wave state of one pose.
+template <int NS>
 struct PoseState {
     int l, nr, tree0, lig;
-    float x0[kSlots][3];  // input pose (this lane's atoms)
-    float c0[3];          // centroid of the input pose
-    uint64_t mv[kSlots];  // bit e: this lane's atom moves with rotamer e (root-first order)
+    float x0[NS][3];  // input pose (this lane's atoms)
+    float c0[3];      // centroid of the input pose
+    uint64_t mv[NS];  // bit e: this lane's atom moves with tree entry e (root-first order)
 };
 
-__device__ void load_pose(const TreeDev& T, const PoseDev& X, int pose, PoseState& S) {
+// Atom count of a pose's ligand (picks the slot form before load_pose).
+__device__ __forceinline__ int pose_atoms(const TreeDev& T, const PoseDev& X, int pose) {
+    return __builtin_amdgcn_readfirstlane(T.n_atoms[X.pose_lig[pose]]);
+}
+
+template <int NS>
+__device__ void load_pose(const TreeDev& T, const PoseDev& X, int pose, PoseState<NS>& S) {
     const int lane = lane_id();
     const int lig = X.pose_lig[pose], off = X.pose_off[pose];
     S.l = T.n_atoms[lig];
@@ -112,7 +162,7 @@ __device__ void load_pose(const TreeDev& T, const PoseDev& X, int pose, PoseStat
     S.tree0 = T.tree_off[lig];
     float s[3] = {0.f, 0.f, 0.f};
 #pragma unroll
-    for (int k = 0; k < kSlots; k++) {
+    for (int k = 0; k < NS; k++) {
         int i = lane + k * kWave;
         bool in = i < S.l;
         S.x0[k][0] = in ? X.px[off + i] : 0.f;
@@ -124,7 +174,7 @@ __device__ void load_pose(const TreeDev& T, const PoseDev& X, int pose, PoseStat
     }
     for (int a = 0; a < 3; a++) S.c0[a] = wsum(s[a]) / (float)S.l;
 #pragma unroll
-    for (int k = 0; k < kSlots; k++) {
+    for (int k = 0; k < NS; k++) {
         const int i = lane + k * kWave;
         uint64_t b = 0;
         for (int e = 0; e < S.nr; e++) {
@@ -136,28 +186,30 @@ __device__ void load_pose(const TreeDev& T, const PoseDev& X, int pose, PoseStat
 }
 
 // Forward kinematics + rigid motion; Ys gets FK_tau(X0) for this lane's
-// atoms, Xf the final pose.
-__device__ void pose_forward(const TreeDev& T, const PoseState& S, const float* t, const float* q, const float* tau,
-                             float* axes, float Ys[kSlots][3], float Xf[kSlots][3], float Rq[9]) {
+// atoms, Xf the final pose.  tau (tree order, this wave's LDS); with axes the
+// pivot and unit axis of every tree entry in the torsion frame are stored
+// there (6 floats per entry).
+template <int NS>
+__device__ void pose_forward(const TreeDev& T, const PoseState<NS>& S, const float* t, const float* q, const float* tau,
+                             float* axes, float Ys[NS][3], float Xf[NS][3], float Rq[9]) {
 #pragma unroll
-    for (int k = 0; k < kSlots; k++)
+    for (int k = 0; k < NS; k++)
         for (int a = 0; a < 3; a++) Ys[k][a] = S.x0[k][a];
-    // Lane r holds sin/cos of torsion r (one torsion per lane at most); each
-    // edge reads its pair with a uniform readlane instead of evaluating it.
-    static_assert(kMaxRot <= kWave, "one torsion per lane");
+    // lane e holds sin/cos of tree entry e; each edge reads its pair with a
+    // uniform readlane instead of evaluating it
     float s_lane = 0.f, c_lane = 1.f;
     if (lane_id() < S.nr) sincosf(tau[lane_id()], &s_lane, &c_lane);
     for (int e = 0; e < S.nr; e++) {
         const int4 te = T.tree[S.tree0 + e];
         const int ia = __builtin_amdgcn_readfirstlane(te.x), ib = __builtin_amdgcn_readfirstlane(te.y);
-        const float px = atom_at(Ys, ia, 0), py = atom_at(Ys, ia, 1), pz = atom_at(Ys, ia, 2);
-        float kx = atom_at(Ys, ib, 0) - px, ky = atom_at(Ys, ib, 1) - py, kz = atom_at(Ys, ib, 2) - pz;
+        const float px = atom_at<NS>(Ys, ia, 0), py = atom_at<NS>(Ys, ia, 1), pz = atom_at<NS>(Ys, ia, 2);
+        float kx = atom_at<NS>(Ys, ib, 0) - px, ky = atom_at<NS>(Ys, ib, 1) - py, kz = atom_at<NS>(Ys, ib, 2) - pz;
         const float inv = rsqrtf(kx * kx + ky * ky + kz * kz);
         kx *= inv;
         ky *= inv;
         kz *= inv;
         if (axes && lane_id() == 0) {
-            float* ax = axes + 6 * te.z;
+            float* ax = axes + 6 * e;
             ax[0] = px;
             ax[1] = py;
             ax[2] = pz;
@@ -165,15 +217,13 @@ __device__ void pose_forward(const TreeDev& T, const PoseState& S, const float* 
             ax[4] = ky;
             ax[5] = kz;
         }
-        const int rz = __builtin_amdgcn_readfirstlane(te.z);
-        const float s = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(s_lane), rz));
-        const float c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(c_lane), rz));
+        const float s = rlane(s_lane, e), c = rlane(c_lane, e);
         float tt = 1.f - c;
         float R[9] = {tt * kx * kx + c,      tt * kx * ky - s * kz, tt * kx * kz + s * ky,
                       tt * kx * ky + s * kz, tt * ky * ky + c,      tt * ky * kz - s * kx,
                       tt * kx * kz - s * ky, tt * ky * kz + s * kx, tt * kz * kz + c};
 #pragma unroll
-        for (int k = 0; k < kSlots; k++) {
+        for (int k = 0; k < NS; k++) {
             if ((S.mv[k] >> e) & 1) {
                 float d0 = Ys[k][0] - px, d1 = Ys[k][1] - py, d2 = Ys[k][2] - pz;
                 Ys[k][0] = px + (R[0] * d0 + R[1] * d1 + R[2] * d2);
@@ -184,7 +234,7 @@ __device__ void pose_forward(const TreeDev& T, const PoseState& S, const float* 
     }
     quat_mat(q, Rq);
 #pragma unroll
-    for (int k = 0; k < kSlots; k++) {
+    for (int k = 0; k < NS; k++) {
         float d0 = Ys[k][0] - S.c0[0], d1 = Ys[k][1] - S.c0[1], d2 = Ys[k][2] - S.c0[2];
         Xf[k][0] = (Rq[0] * d0 + Rq[1] * d1 + Rq[2] * d2) + S.c0[0] + t[0];
         Xf[k][1] = (Rq[3] * d0 + Rq[4] * d1 + Rq[5] * d2) + S.c0[1] + t[1];
@@ -197,12 +247,12 @@ __device__ void pose_forward(const TreeDev& T, const PoseState& S, const float* 
 // F (lane partial) and, with GRAD, its derivative from the per-atom gradients
 // g.  Atoms go through this wave's LDS (xs, gs: 3 floats per atom); lanes own
 // pairs and add their gradient contributions with LDS atomics.
-template <bool GRAD>
-__device__ void bump_penalty(const Penalty pen, const PoseState& S, const float Xf[kSlots][3], float g[kSlots][3],
+template <bool GRAD, int NS>
+__device__ void bump_penalty(const Penalty pen, const PoseState<NS>& S, const float Xf[NS][3], float g[NS][3],
                              float& F, float* xs, float* gs) {
     const int lane = lane_id();
 #pragma unroll
-    for (int k = 0; k < kSlots; k++) {
+    for (int k = 0; k < NS; k++) {
         const int i = lane + k * kWave;
         if (i < S.l)
             for (int a = 0; a < 3; a++) {
@@ -238,7 +288,7 @@ __device__ void bump_penalty(const Penalty pen, const PoseState& S, const float 
     if (GRAD) {
         wave_sync();
 #pragma unroll
-        for (int k = 0; k < kSlots; k++) {
+        for (int k = 0; k < NS; k++) {
             const int i = lane + k * kWave;
             if (i < S.l)
                 for (int a = 0; a < 3; a++) g[k][a] += gs[3 * i + a];
@@ -247,22 +297,33 @@ __device__ void bump_penalty(const Penalty pen, const PoseState& S, const float 
     wave_sync();
 }
 
-// F and (optionally) dF/d(t, q, tau) at the given parameters.  tau, gtau and
-// axes (6 floats per rotamer: pivot and unit axis in the torsion frame) are
-// this wave's LDS arrays indexed by rotamer (list order); only lane-uniform
-// values are returned.  With pen.w > 0 F is the clash-penalised surrogate;
-// xs and gs are then this wave's LDS scratch (3 floats per atom).
-template <bool GRAD>
-__device__ float surrogate_eval(const PocketDev& P, const TreeDev& T, const PoseState& S, const float* t,
-                                const float* q, const float* tau, float* axes, float* gt, float* gq, float* gtau,
-                                float Xout[kSlots][3], const Penalty pen = Penalty{}, float* xs = nullptr,
-                                float* gs = nullptr) {
+// LDS of one wave: torsions and their gradient (tree order), the torsion-frame
+// pivot and axis of every tree entry (6 floats), the final-frame axis K and
+// K x (A - o) of every entry (8 floats, two 16-byte rows), and with the bump
+// penalty the atoms and their gradients (3 floats per atom).
+struct WaveBuf {
+    float* tau;
+    float* gtau;
+    float* axes;
+    float* kax;
+    float* xs;
+    float* gs;
+};
+
+// F and (optionally) dF/d(t, q, tau) at the given parameters; only
+// lane-uniform values are returned, gtau in the wave's LDS.  With pen.w > 0 F
+// is the clash-penalised surrogate.  WANT_F = false skips the value's sum
+// (the ascent needs only the gradient).
+template <bool GRAD, int NS, bool WANT_F = true>
+__device__ float surrogate_eval(const PocketDev& P, const TreeDev& T, const PoseState<NS>& S, const float* t,
+                                const float* q, const WaveBuf& W, float* gt, float* gq, float Xout[NS][3],
+                                const Penalty pen = Penalty{}) {
     const int lane = lane_id();
-    float Ys[kSlots][3], Xf[kSlots][3], g[kSlots][3], Rq[9];
-    pose_forward(T, S, t, q, tau, GRAD ? axes : nullptr, Ys, Xf, Rq);
+    float Ys[NS][3], Xf[NS][3], g[NS][3], Rq[9];
+    pose_forward<NS>(T, S, t, q, W.tau, GRAD ? W.axes : nullptr, Ys, Xf, Rq);
     float F = 0.f;
 #pragma unroll
-    for (int k = 0; k < kSlots; k++) {
+    for (int k = 0; k < NS; k++) {
         int i = lane + k * kWave;
         if (i < S.l) {
             F += rho_tri(P, Xf[k][0], Xf[k][1], Xf[k][2], g[k][0], g[k][1], g[k][2]);
@@ -272,63 +333,95 @@ __device__ float surrogate_eval(const PocketDev& P, const TreeDev& T, const Pose
         if (Xout)
             for (int a = 0; a < 3; a++) Xout[k][a] = Xf[k][a];
     }
-    if (pen.w > 0.f) bump_penalty<GRAD>(pen, S, Xf, g, F, xs, gs);
-    F = wsum(F);
-    if (!GRAD) return F;
-    // translation
-    for (int a = 0; a < 3; a++) gt[a] = wsum(g[0][a] + g[1][a]);
-    // x x g per atom, for the quaternion and the torsions
-    float xg[kSlots][3];
+    if (pen.w > 0.f) bump_penalty<GRAD, NS>(pen, S, Xf, g, F, W.xs, W.gs);
+    if (!GRAD) return wsum(F);
+    // lever arms from the centre of the rigid rotation
+    const float ox = S.c0[0] + t[0], oy = S.c0[1] + t[1], oz = S.c0[2] + t[2];
+    float xg[NS][3];
 #pragma unroll
-    for (int k = 0; k < kSlots; k++) {
-        xg[k][0] = Xf[k][1] * g[k][2] - Xf[k][2] * g[k][1];
-        xg[k][1] = Xf[k][2] * g[k][0] - Xf[k][0] * g[k][2];
-        xg[k][2] = Xf[k][0] * g[k][1] - Xf[k][1] * g[k][0];
+    for (int k = 0; k < NS; k++) {
+        const float rx = Xf[k][0] - ox, ry = Xf[k][1] - oy, rz = Xf[k][2] - oz;
+        xg[k][0] = ry * g[k][2] - rz * g[k][1];
+        xg[k][1] = rz * g[k][0] - rx * g[k][2];
+        xg[k][2] = rx * g[k][1] - ry * g[k][0];
+    }
+    // the rigid-body sums in one transposed reduction: sum g (3), the torque (3), F
+    float tq[3];
+    {
+        float v[8];
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            v[a] = g[0][a];
+            v[3 + a] = xg[0][a];
+#pragma unroll
+            for (int k = 1; k < NS; k++) {
+                v[a] += g[k][a];
+                v[3 + a] += xg[k][a];
+            }
+        }
+        v[6] = WANT_F ? F : 0.f;
+        v[7] = 0.f;
+        const float r = wsum8(v);
+        for (int a = 0; a < 3; a++) {
+            gt[a] = rlane(r, wsum8_lane(a));
+            tq[a] = rlane(r, wsum8_lane(3 + a));
+        }
+        if (WANT_F) F = rlane(r, wsum8_lane(6));
     }
     // quaternion: a tangent change dq of the unit quaternion (w, v) turns the
-    // pose by omega = 2 (w dv - dw v + v x dv) about c0 + t, so dF = omega . tau
-    // with the torque tau = sum (X - c0 - t) x g; divided by |q| for the
-    // unnormalised parameter
+    // pose by omega = 2 (w dv - dw v + v x dv) about o, so dF = omega . T;
+    // divided by |q| for the unnormalised parameter
     {
-        float sx[3];
-        for (int a = 0; a < 3; a++) sx[a] = wsum(xg[0][a] + xg[1][a]);
-        const float ox = S.c0[0] + t[0], oy = S.c0[1] + t[1], oz = S.c0[2] + t[2];
-        const float tx = sx[0] - (oy * gt[2] - oz * gt[1]);
-        const float ty = sx[1] - (oz * gt[0] - ox * gt[2]);
-        const float tz = sx[2] - (ox * gt[1] - oy * gt[0]);
         const float in = 1.f / sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
         const float w = q[0] * in, x = q[1] * in, y = q[2] * in, z = q[3] * in;
-        gq[0] = -2.f * (tx * x + ty * y + tz * z) * in;
-        gq[1] = 2.f * (w * tx + (ty * z - tz * y)) * in;
-        gq[2] = 2.f * (w * ty + (tz * x - tx * z)) * in;
-        gq[3] = 2.f * (w * tz + (tx * y - ty * x)) * in;
+        gq[0] = -2.f * (tq[0] * x + tq[1] * y + tq[2] * z) * in;
+        gq[1] = 2.f * (w * tq[0] + (tq[1] * z - tq[2] * y)) * in;
+        gq[2] = 2.f * (w * tq[1] + (tq[2] * x - tq[0] * z)) * in;
+        gq[3] = 2.f * (w * tq[2] + (tq[0] * y - tq[1] * x)) * in;
     }
-    // torsions, in the final frame: K . sum over the moving atoms of
-    // (x_i - A) x g_i, with the pivot A and axis K of the forward pass carried
-    // into the final frame.  Per atom that is K . (x_i x g_i) - (K x A) . g_i,
-    // so each lane forms its atoms' scalar terms and one wave sum per rotamer
-    // finishes the job.
+    // torsions: lane e carries tree entry e's pivot and axis into the final
+    // frame, K = Rq k and A - o = Rq (p - c0), and keeps K and K x (A - o)
     wave_sync();
-    for (int e = 0; e < S.nr; e++) {
-        const int4 te = T.tree[S.tree0 + e];
-        const float* axe = axes + 6 * te.z;
+    if (lane < S.nr) {
+        const float* axe = W.axes + 6 * lane;
         const float d0 = axe[0] - S.c0[0], d1 = axe[1] - S.c0[1], d2 = axe[2] - S.c0[2];
-        const float ax = (Rq[0] * d0 + Rq[1] * d1 + Rq[2] * d2) + S.c0[0] + t[0];
-        const float ay = (Rq[3] * d0 + Rq[4] * d1 + Rq[5] * d2) + S.c0[1] + t[1];
-        const float az = (Rq[6] * d0 + Rq[7] * d1 + Rq[8] * d2) + S.c0[2] + t[2];
+        const float ax = Rq[0] * d0 + Rq[1] * d1 + Rq[2] * d2;
+        const float ay = Rq[3] * d0 + Rq[4] * d1 + Rq[5] * d2;
+        const float az = Rq[6] * d0 + Rq[7] * d1 + Rq[8] * d2;
         const float kx = Rq[0] * axe[3] + Rq[1] * axe[4] + Rq[2] * axe[5];
         const float ky = Rq[3] * axe[3] + Rq[4] * axe[4] + Rq[5] * axe[5];
         const float kz = Rq[6] * axe[3] + Rq[7] * axe[4] + Rq[8] * axe[5];
-        const float cx = ky * az - kz * ay, cy = kz * ax - kx * az, cz = kx * ay - ky * ax;  // K x A
-        float v = 0.f;
+        float* kr = W.kax + 8 * lane;
+        kr[0] = kx;
+        kr[1] = ky;
+        kr[2] = kz;
+        kr[4] = ky * az - kz * ay;
+        kr[5] = kz * ax - kx * az;
+        kr[6] = kx * ay - ky * ax;
+    }
+    wave_sync();
+    // per atom K . ((X - o) x g) - (K x (A - o)) . g over the entries that
+    // move it, eight entries per transposed reduction
+    for (int e0 = 0; e0 < S.nr; e0 += 8) {
+        float v[8];
 #pragma unroll
-        for (int k = 0; k < kSlots; k++) {
-            const float term = (kx * xg[k][0] + ky * xg[k][1] + kz * xg[k][2]) -
-                               (cx * g[k][0] + cy * g[k][1] + cz * g[k][2]);
-            v += ((S.mv[k] >> e) & 1) ? term : 0.f;
+        for (int j = 0; j < 8; j++) {
+            v[j] = 0.f;
+            const int e = e0 + j;
+            if (e < S.nr) {
+                const float* kr = W.kax + 8 * e;
+                const float kx = kr[0], ky = kr[1], kz = kr[2], cx = kr[4], cy = kr[5], cz = kr[6];
+#pragma unroll
+                for (int k = 0; k < NS; k++) {
+                    const float term = (kx * xg[k][0] + ky * xg[k][1] + kz * xg[k][2]) -
+                                       (cx * g[k][0] + cy * g[k][1] + cz * g[k][2]);
+                    v[j] += ((S.mv[k] >> e) & 1) ? term : 0.f;
+                }
+            }
         }
-        v = wsum(v);
-        if (lane == 0) gtau[te.z] = v;
+        const float r = wsum8(v);
+        const int j = ((lane >> 5) & 1) * 4 + ((lane >> 4) & 1) * 2 + ((lane >> 3) & 1);
+        if ((lane & 7) == 0 && e0 + j < S.nr) W.gtau[e0 + j] = r;
     }
     wave_sync();
     return F;
@@ -336,38 +429,31 @@ __device__ float surrogate_eval(const PocketDev& P, const TreeDev& T, const Pose
 
 // ---------------------------------------------------------------------------
 
-template <bool PEN>
-__global__ void __launch_bounds__(256) surrogate_kernel(PocketDev P, TreeDev T, PoseDev X, int n_poses,
-                                                        const float* t, const float* q, const float* tau,
-                                                        int tau_stride, const float* dF, float* F_out, float* dt_out,
-                                                        float* dq_out, float* dtau_out, Penalty pen_in) {
-    __shared__ float tau_all[4][kMaxRot], gtau_all[4][kMaxRot], axes_all[4][6 * kMaxRot];
-    __shared__ float pen_x[4][PEN ? 3 * kMaxAtoms : 1], pen_g[4][PEN ? 3 * kMaxAtoms : 1];
-    const Penalty pen = PEN ? pen_in : Penalty{};
-    const int wave = threadIdx.x / kWave;
-    const int pose = blockIdx.x * 4 + wave;
-    if (pose >= n_poses) return;
+// One pose of the surrogate kernel in the slot form NS: F, or its gradient
+// scaled by dF.
+template <bool PEN, int NS>
+__device__ void surrogate_pose(const PocketDev& P, const TreeDev& T, const PoseDev& X, int pose, const float* t,
+                               const float* q, const float* tau, int tau_stride, const float* dF, float* F_out,
+                               float* dt_out, float* dq_out, float* dtau_out, const Penalty& pen, const WaveBuf& W) {
     const int lane = lane_id();
-    float* tau_l = tau_all[wave];
-    float* gtau = gtau_all[wave];
-    PoseState S;
-    load_pose(T, X, pose, S);
+    PoseState<NS> S;
+    load_pose<NS>(T, X, pose, S);
     const float* tp = t + 3 * (size_t)pose;
     const float* qp = q + 4 * (size_t)pose;
-    for (int r = lane; r < kMaxRot; r += kWave) {
-        tau_l[r] = r < S.nr ? tau[(size_t)tau_stride * pose + r] : 0.f;
-        gtau[r] = 0.f;
+    // torsions into tree order
+    int rot_e = 0;
+    if (lane < S.nr) {
+        rot_e = T.tree[S.tree0 + lane].z;
+        W.tau[lane] = tau[(size_t)tau_stride * pose + rot_e];
     }
     wave_sync();
     if (!dF) {
-        float F = surrogate_eval<false>(P, T, S, tp, qp, tau_l, nullptr, nullptr, nullptr, nullptr, nullptr, pen,
-                                        pen_x[wave], pen_g[wave]);
+        float F = surrogate_eval<false, NS>(P, T, S, tp, qp, W, nullptr, nullptr, nullptr, pen);
         if (lane == 0) F_out[pose] = F;
         return;
     }
     float gt[3], gq[4];
-    float F = surrogate_eval<true>(P, T, S, tp, qp, tau_l, axes_all[wave], gt, gq, gtau, nullptr, pen, pen_x[wave],
-                                   pen_g[wave]);
+    float F = surrogate_eval<true, NS>(P, T, S, tp, qp, W, gt, gq, nullptr, pen);
     const float up = dF[pose];
     if (lane == 0) {
         if (F_out) F_out[pose] = F;
@@ -375,34 +461,44 @@ __global__ void __launch_bounds__(256) surrogate_kernel(PocketDev P, TreeDev T, 
         for (int a = 0; a < 4; a++) dq_out[4 * (size_t)pose + a] = up * gq[a];
     }
     for (int r = lane; r < tau_stride; r += kWave)
-        dtau_out[(size_t)tau_stride * pose + r] = r < S.nr ? up * gtau[r] : 0.f;
+        if (r >= S.nr) dtau_out[(size_t)tau_stride * pose + r] = 0.f;
+    if (lane < S.nr) dtau_out[(size_t)tau_stride * pose + rot_e] = up * W.gtau[lane];
 }
 
-// The whole ascent of one pose in one wavefront: parameters stay in
-// registers; the final pose is written to (rx, ry, rz).  PEN: the
-// clash-penalised surrogate (its own instance, so that the plain one keeps its
-// registers and LDS).
 template <bool PEN>
-__global__ void __launch_bounds__(256) refine_kernel(PocketDev P, TreeDev T, PoseDev X, int n_poses, RefineParams rp,
-                                                     float* rx, float* ry, float* rz, float* F_out) {
+__global__ void __launch_bounds__(256) surrogate_kernel(PocketDev P, TreeDev T, PoseDev X, int n_poses,
+                                                        const float* t, const float* q, const float* tau,
+                                                        int tau_stride, const float* dF, float* F_out, float* dt_out,
+                                                        float* dq_out, float* dtau_out, Penalty pen_in) {
     __shared__ float tau_all[4][kMaxRot], gtau_all[4][kMaxRot], axes_all[4][6 * kMaxRot];
+    __shared__ __align__(16) float kax_all[4][8 * kMaxRot];
     __shared__ float pen_x[4][PEN ? 3 * kMaxAtoms : 1], pen_g[4][PEN ? 3 * kMaxAtoms : 1];
+    const Penalty pen = PEN ? pen_in : Penalty{};
     const int wave = threadIdx.x / kWave;
     const int pose = blockIdx.x * 4 + wave;
     if (pose >= n_poses) return;
+    const WaveBuf W{tau_all[wave], gtau_all[wave], axes_all[wave], kax_all[wave], pen_x[wave], pen_g[wave]};
+    if (pose_atoms(T, X, pose) <= kWave)
+        surrogate_pose<PEN, 1>(P, T, X, pose, t, q, tau, tau_stride, dF, F_out, dt_out, dq_out, dtau_out, pen, W);
+    else
+        surrogate_pose<PEN, 2>(P, T, X, pose, t, q, tau, tau_stride, dF, F_out, dt_out, dq_out, dtau_out, pen, W);
+}
+
+// The whole ascent of one pose in one wavefront (slot form NS): parameters
+// stay in registers; the final pose is written to (rx, ry, rz).
+template <bool PEN, int NS>
+__device__ void refine_pose(const PocketDev& P, const TreeDev& T, const PoseDev& X, int pose, const RefineParams& rp,
+                            float* rx, float* ry, float* rz, float* F_out, const WaveBuf& W) {
     const int lane = lane_id();
-    float* tau = tau_all[wave];
-    float* gtau = gtau_all[wave];
-    PoseState S;
-    load_pose(T, X, pose, S);
+    PoseState<NS> S;
+    load_pose<NS>(T, X, pose, S);
     const Penalty pen = PEN ? Penalty{rp.clash_weight, rp.cd2, rp.efar, rp.far_off, rp.n_far} : Penalty{};
     float t[3] = {0.f, 0.f, 0.f}, q[4] = {1.f, 0.f, 0.f, 0.f};
     float gt[3], gq[4];
-    for (int r = lane; r < kMaxRot; r += kWave) tau[r] = gtau[r] = 0.f;
+    for (int r = lane; r < kMaxRot; r += kWave) W.tau[r] = W.gtau[r] = 0.f;
     wave_sync();
     for (int s = 0; s < rp.steps; s++) {
-        surrogate_eval<true>(P, T, S, t, q, tau, axes_all[wave], gt, gq, gtau, nullptr, pen, pen_x[wave],
-                             pen_g[wave]);
+        surrogate_eval<true, NS, false>(P, T, S, t, q, W, gt, gq, nullptr, pen);
         float dt[3] = {rp.lr_t * gt[0], rp.lr_t * gt[1], rp.lr_t * gt[2]};
         float n = sqrtf(dt[0] * dt[0] + dt[1] * dt[1] + dt[2] * dt[2]);
         float sc = n > rp.max_dt ? rp.max_dt / n : 1.f;
@@ -414,23 +510,40 @@ __global__ void __launch_bounds__(256) refine_kernel(PocketDev P, TreeDev T, Pos
         }
         qn = 1.f / sqrtf(qn);
         for (int a = 0; a < 4; a++) q[a] *= qn;
-        for (int r = lane; r < S.nr; r += kWave)
-            tau[r] += fminf(fmaxf(rp.lr_tau * gtau[r], -rp.max_dtau), rp.max_dtau);
+        if (lane < S.nr) W.tau[lane] += fminf(fmaxf(rp.lr_tau * W.gtau[lane], -rp.max_dtau), rp.max_dtau);
         wave_sync();
     }
-    float Xf[kSlots][3];
-    float F = surrogate_eval<false>(P, T, S, t, q, tau, nullptr, nullptr, nullptr, nullptr, Xf, pen, pen_x[wave],
-                                    pen_g[wave]);
+    float Xf[NS][3];
+    float F = surrogate_eval<false, NS>(P, T, S, t, q, W, nullptr, nullptr, Xf, pen);
     const int off = X.pose_off[pose];
-    for (int k = 0; k < kSlots; k++) {
-        int i = lane_id() + k * kWave;
+#pragma unroll
+    for (int k = 0; k < NS; k++) {
+        int i = lane + k * kWave;
         if (i < S.l) {
             rx[off + i] = Xf[k][0];
             ry[off + i] = Xf[k][1];
             rz[off + i] = Xf[k][2];
         }
     }
-    if (lane_id() == 0) F_out[pose] = F;
+    if (lane == 0) F_out[pose] = F;
+}
+
+// PEN: the clash-penalised surrogate (its own instance, so that the plain one
+// keeps its registers and LDS).
+template <bool PEN>
+__global__ void __launch_bounds__(256) refine_kernel(PocketDev P, TreeDev T, PoseDev X, int n_poses, RefineParams rp,
+                                                     float* rx, float* ry, float* rz, float* F_out) {
+    __shared__ float tau_all[4][kMaxRot], gtau_all[4][kMaxRot], axes_all[4][6 * kMaxRot];
+    __shared__ __align__(16) float kax_all[4][8 * kMaxRot];
+    __shared__ float pen_x[4][PEN ? 3 * kMaxAtoms : 1], pen_g[4][PEN ? 3 * kMaxAtoms : 1];
+    const int wave = threadIdx.x / kWave;
+    const int pose = blockIdx.x * 4 + wave;
+    if (pose >= n_poses) return;
+    const WaveBuf W{tau_all[wave], gtau_all[wave], axes_all[wave], kax_all[wave], pen_x[wave], pen_g[wave]};
+    if (pose_atoms(T, X, pose) <= kWave)
+        refine_pose<PEN, 1>(P, T, X, pose, rp, rx, ry, rz, F_out, W);
+    else
+        refine_pose<PEN, 2>(P, T, X, pose, rp, rx, ry, rz, F_out, W);
 }
 
 // Keep the refined pose iff it is bump-free and strictly improves S.

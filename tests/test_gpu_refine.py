@@ -251,3 +251,45 @@ def test_refine_penalty_single_step(g, setup):
         worst = max(worst, float(np.sqrt(((It[off:off + l] - Xo) ** 2).sum(1).mean())))
         off += l
     assert worst <= 1e-4, worst
+
+
+@gpu
+def test_surrogate_gradient_far_from_origin(g, setup):
+    """The same pocket and poses moved by (100, -80, 60) A: lever arms are
+    taken from the rotation centre, so the torque and torsion gradients keep
+    the same bar (every component within 1e-3 of its group norm, faces
+    excused as above) although coordinates are ~140 A from the origin."""
+    import torch
+    S = setup
+    shift = np.array([100.0, -80.0, 60.0], np.float32)
+    pts = configs.REFINE.pocket_points().astype(np.float32) + shift
+    P = g.Pocket(pts, 0.5, 12.0, blur_sigma=SIG, blur_h=BH, blur_cutoff_sigmas=CUTS, blur_pad=8.0)
+    B = oracle.OracleBlur(oracle.OraclePocket(pts, 0.5), SIG, CUTS, BH)
+    ligs, pl = S["ligs"], S["pose_lig"]
+    rows = [(r + shift).astype(np.float32) for r in S["rows"]]
+    allx = np.concatenate(rows)
+    dev = lambda a: torch.tensor(np.ascontiguousarray(a), device="cuda")
+    px, py, pz = dev(allx[:, 0]), dev(allx[:, 1]), dev(allx[:, 2])
+    n = len(pl)
+    nrmax = max(ligs.n_rot(i) for i in range(ligs.n))
+    t, q, tau = _params(n, nrmax, 3)
+    T = lambda a: torch.tensor(a, device="cuda")
+    dF = np.ones(n, np.float32)
+    dt, dq, dtau = (x.cpu().numpy() for x in g.surrogate_bwd(P, ligs, pl, px, py, pz, T(t), T(q), T(tau), T(dF)))
+    excused, worst = 0, 0.0
+    for p in range(n):
+        lig = ligs.ligand(pl[p])
+        nr = ligs.n_rot(pl[p])
+        prm = np.concatenate([t[p], q[p], tau[p, :nr]]).astype(np.float64)
+        Fo, go, Xo = B.surrogate(lig, rows[p].astype(np.float64), prm)
+        gg = np.concatenate([dt[p], dq[p], dtau[p, :nr]])
+        rel = max(np.max(np.abs(gg[sl] - go[sl])) / max(np.linalg.norm(go[sl]), 1e-3)
+                  for sl in (slice(0, 3), slice(3, 7), slice(7, 7 + nr)) if sl.stop > sl.start)
+        if rel > 1e-3:
+            assert _face_dist(Xo) < FP32_XYZ, (p, rel, _face_dist(Xo))
+            excused += 1
+        else:
+            worst = max(worst, rel)
+    print("surrogate gradient 140 A from the origin: worst relative component error %.2e, %d of %d poses excused"
+          % (worst, excused, n))
+    assert excused <= n // 4
