@@ -80,7 +80,7 @@ typedef struct {
  * order), and optionally the blurred density grid.  Synchronous.
  * Errors: GD_ERR_ARG (null, n_points < 1, h not a power of two, negative pad),
  * GD_ERR_CAPACITY (more than 512 cells per axis or 2^24 cells in all, or D would
- * exceed 65535).
+ * exceed 65535; a density grid of more than 1024 nodes per axis or 2^28 in all).
  */
 gd_status gd_create_pocket(const gd_pocket_desc* desc, void* stream, gd_pocket** out);
 gd_status gd_destroy_pocket(gd_pocket* pocket);

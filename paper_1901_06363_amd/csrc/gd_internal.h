@@ -58,6 +58,11 @@ struct PocketDev {
     const float* rho;
     int32_t blo[3], bdim[3];
     float bh, inv_bh;
+    // the same grid corner-packed: node (x, y, z), x in [-1, bdim0), y in
+    // [-1, bdim1), z in [-1, bdim2], holds rho at (x, y), (x+1, y), (x, y+1),
+    // (x+1, y+1) of layer z (0 outside the box), x fastest, so a trilinear
+    // cell is two 16-byte loads
+    const float4* rho4;
 };
 
 // Kernel-visible view of a prepared batch.

@@ -103,21 +103,24 @@ __device__ __forceinline__ float atom_at(const float Y[NS][3], int i, int a) {
 
 // Trilinear density and its gradient; corners outside the tabulated box are 0
 // (every node beyond the box lies farther than the cutoff from the points).
+// The cell's eight corners are two 16-byte nodes of the corner-packed grid;
+// a cell with no corner in the box reads nothing.
 __device__ __forceinline__ float rho_tri(const PocketDev& P, float x, float y, float z, float& gx, float& gy,
                                          float& gz) {
     float ux = x * P.inv_bh, uy = y * P.inv_bh, uz = z * P.inv_bh;
     float fx0 = floorf(ux), fy0 = floorf(uy), fz0 = floorf(uz);
     float fx = ux - fx0, fy = uy - fy0, fz = uz - fz0;
     int ix = (int)fx0 - P.blo[0], iy = (int)fy0 - P.blo[1], iz = (int)fz0 - P.blo[2];
-    float r[8];
-#pragma unroll
-    for (int c = 0; c < 8; c++) {
-        int jx = ix + (c & 1), jy = iy + ((c >> 1) & 1), jz = iz + (c >> 2);
-        bool in = (unsigned)jx < (unsigned)P.bdim[0] && (unsigned)jy < (unsigned)P.bdim[1] &&
-                  (unsigned)jz < (unsigned)P.bdim[2];
-        // at most 1024 nodes per axis (checked at pocket creation): the index fits 32 bits
-        r[c] = in ? P.rho[(jz * P.bdim[1] + jy) * P.bdim[0] + jx] : 0.f;
+    float4 lo = make_float4(0.f, 0.f, 0.f, 0.f), hi = lo;
+    // at most 1024 nodes per axis (checked at pocket creation): the index fits 32 bits
+    if ((unsigned)(ix + 1) <= (unsigned)P.bdim[0] && (unsigned)(iy + 1) <= (unsigned)P.bdim[1] &&
+        (unsigned)(iz + 1) <= (unsigned)P.bdim[2]) {
+        const int qx = P.bdim[0] + 1, qxy = qx * (P.bdim[1] + 1);
+        const int n0 = (iz + 1) * qxy + (iy + 1) * qx + (ix + 1);
+        lo = P.rho4[n0];
+        hi = P.rho4[n0 + qxy];
     }
+    const float r[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
     float ax = 1.f - fx, ay = 1.f - fy, az = 1.f - fz;
     // interpolate along x, then y, then z
     float r00 = ax * r[0] + fx * r[1], r10 = ax * r[2] + fx * r[3];

@@ -248,6 +248,7 @@ gd_status create_pocket(const gd_pocket_desc* desc, hipStream_t stream, gd_pocke
     D.h = h;
     D.inv_h = inv_h;
     D.rho = nullptr;
+    D.rho4 = nullptr;
     for (int a = 0; a < 3; a++) {
         D.blo[a] = 0;
         D.bdim[a] = 0;
@@ -268,6 +269,8 @@ gd_status create_pocket(const gd_pocket_desc* desc, hipStream_t stream, gd_pocke
             if (bdim[a] > 1024) return fail(GD_ERR_CAPACITY, "gd_create_pocket: density grid too large");
             btot *= bdim[a];
         }
+        // the plain grid and its corner-packed copy (about 4x) stay within a few GiB
+        if (btot > ((size_t)1 << 28)) return fail(GD_ERR_CAPACITY, "gd_create_pocket: density grid too large");
         std::vector<double> rho(btot, 0.0);
         const double cut2 = cut * cut, inv2s2 = 1.0 / (2.0 * sg * sg);
         const int reach = (int)ceil(cut / bh) + 1;
@@ -289,6 +292,26 @@ gd_status create_pocket(const gd_pocket_desc* desc, hipStream_t stream, gd_pocke
         for (size_t i = 0; i < btot; i++) rf[i] = (float)rho[i];
         if ((e = P->rho.upload(rf.data(), rf.size() * 4, stream)) != hipSuccess) return hip_fail(e, "gd_create_pocket");
         D.rho = (const float*)P->rho.ptr;
+        // corner-packed copy for the trilinear gathers (see PocketDev::rho4)
+        const int qx = bdim[0] + 1, qy = bdim[1] + 1, qz = bdim[2] + 2;
+        std::vector<float> pk((size_t)qx * qy * qz * 4, 0.f);
+        auto at = [&](int x, int y, int z) {
+            return (x >= 0 && x < bdim[0] && y >= 0 && y < bdim[1] && z >= 0 && z < bdim[2])
+                       ? rf[((size_t)z * bdim[1] + y) * bdim[0] + x]
+                       : 0.f;
+        };
+        for (int z = -1; z <= bdim[2]; z++)
+            for (int y = -1; y < bdim[1]; y++)
+                for (int x = -1; x < bdim[0]; x++) {
+                    float* o = &pk[4 * (((size_t)(z + 1) * qy + (y + 1)) * qx + (x + 1))];
+                    o[0] = at(x, y, z);
+                    o[1] = at(x + 1, y, z);
+                    o[2] = at(x, y + 1, z);
+                    o[3] = at(x + 1, y + 1, z);
+                }
+        if ((e = P->rho4.upload(pk.data(), pk.size() * 4, stream)) != hipSuccess)
+            return hip_fail(e, "gd_create_pocket");
+        D.rho4 = (const float4*)P->rho4.ptr;
         for (int a = 0; a < 3; a++) {
             D.blo[a] = blo[a];
             D.bdim[a] = bdim[a];

@@ -107,7 +107,7 @@ gd_status pose_layout(const gd_ligands* topo, int32_t n_poses, const int32_t* po
 
 struct gd_pocket {
     gd::PocketDev dev{};
-    gd::DevBuf edt, occ, rho, devcopy;
+    gd::DevBuf edt, occ, rho, rho4, devcopy;
     gd::DevBuf pts;          // FP64 planes x, y, z of the raw points (continuous Eq. 1)
     int n_points = 0, pts_pad = 0;
     double centroid[3] = {0, 0, 0};
