@@ -34,13 +34,18 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
         cmd = [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, s), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        procs.append((s, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
-        while sum(p.poll() is None for _, p in procs) >= jobs:
-            procs[[p.poll() is None for _, p in procs].index(True)][1].wait()
+        # compiler output goes to a file: a pipe nobody reads while waiting
+        # would block a compiler that prints more than the pipe holds
+        log = open(obj + ".log", "w+b")
+        procs.append((s, subprocess.Popen(cmd, stdout=log, stderr=subprocess.STDOUT), log))
+        while sum(p.poll() is None for _, p, _ in procs) >= jobs:
+            procs[[p.poll() is None for _, p, _ in procs].index(True)][1].wait()
     failed = []
-    for s, p in procs:
-        out, _ = p.communicate()
-        txt = out.decode(errors="replace")
+    for s, p, log in procs:
+        p.wait()
+        log.seek(0)
+        txt = log.read().decode(errors="replace")
+        log.close()
         lines = [ln for ln in txt.splitlines() if "packed-fp32-ops" not in ln and ln.strip()]
         if p.returncode != 0:
             failed.append((s, "\n".join(lines)))
