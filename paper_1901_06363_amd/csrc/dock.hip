@@ -354,7 +354,7 @@ __device__ __forceinline__ void score_pass(const PocketDev& P, const Sweep& sw, 
 #pragma unroll
         for (int a = 0; a < KANG; a++) {
             const int k = kb + k0 + NB * a;
-            const int deg = base + ((a < A) & (k < n) ? k : 0) * stride;
+            const int deg = base + (((a < A) & (k < n)) ? k : 0) * stride;
             c[a] = ldg(trig + deg);
             s[a] = ldg(trig + 360 + deg);
         }
@@ -451,23 +451,34 @@ __device__ int eval_candidates(const PocketDev& P, const BatchDev& B, const Swee
     // survivors than the LDS list holds): lanes = straddling pairs, looping
     // over the angles of the word.
     if (sw.pruned) {
+        const int ns = sw.nsurv;
         for (int w0 = 0; w0 < n; w0 += kWave) {
             const int k = w0 + lane;
             const int deg = base + (k < n ? k : 0) * stride;
             const float c = 2.f * ldg(trig + deg), s = 2.f * ldg(trig + 360 + deg);
-            float d0 = 3.0e38f, d1 = 3.0e38f;
+            float d = 3.0e38f;
+            // four survivors from one 16-byte broadcast read of A and two of
+            // (B, C) (the lists are 16-byte aligned); eight per step, so that
+            // six reads are in flight before the arithmetic
+            auto four = [&](int q0) {
+                const f4 a = *(const lds_float4*)(W.survA + q0);
+                const f4 b0 = *(const lds_float4*)(W.survBC + q0), b1 = *(const lds_float4*)(W.survBC + q0 + 2);
+                const float e0 = fmaf(b0.y, s, fmaf(b0.x, c, a.x));
+                const float e1 = fmaf(b0.w, s, fmaf(b0.z, c, a.y));
+                const float e2 = fmaf(b1.y, s, fmaf(b1.x, c, a.z));
+                const float e3 = fmaf(b1.w, s, fmaf(b1.z, c, a.w));
+                return fminf(fminf(e0, e1), fminf(e2, e3));
+            };
             int q = 0;
-            for (; q + 1 < sw.nsurv; q += 2) {
-                const f2 e0 = W.survBC[q], e1 = W.survBC[q + 1];
-                const float a0 = W.survA[q], a1 = W.survA[q + 1];
-                d0 = fminf(d0, fmaf(e0.y, s, fmaf(e0.x, c, a0)));
-                d1 = fminf(d1, fmaf(e1.y, s, fmaf(e1.x, c, a1)));
+            for (; q + 7 < ns; q += 8) d = fminf(d, fminf(four(q), four(q + 4)));
+            if (q + 3 < ns) {
+                d = fminf(d, four(q));
+                q += 4;
             }
-            if (q < sw.nsurv) {
-                const f2 e0 = W.survBC[q];
-                d0 = fminf(d0, fmaf(e0.y, s, fmaf(e0.x, c, W.survA[q])));
+            for (; q < ns; q++) {
+                const f2 e = W.survBC[q];
+                d = fminf(d, fmaf(e.y, s, fmaf(e.x, c, W.survA[q])));
             }
-            const float d = fminf(d0, d1);
             if (k < n) W.st[k] = (uint8_t)((d < sw.thr_lo ? 1 : 0) | (d < sw.thr_hi ? 2 : 0));
         }
     } else {
@@ -786,14 +797,21 @@ __device__ __forceinline__ void endpoint(const PocketDev& P, const BatchDev& B, 
     // scan stops at the first word of pairs that holds one)
     const uint16_t* fp = B.efar + L.far_off;
     clash = false;
-    for (int q0 = 0; q0 < L.n_far && !clash; q0 += kWave) {
-        const int q = q0 + lane;
-        bool c = false;
-        if (q < L.n_far) {
-            const uint16_t pr = ldg(fp + q);
-            const int i = pr & 0xff, j = pr >> 8;
-            c = dist2(Xx[i], Xy[i], Xz[i], Xx[j], Xy[j], Xz[j]) < B.cd2;
+    // four pairs per lane per step (their reads in flight together)
+    for (int q0 = 0; q0 < L.n_far && !clash; q0 += 4 * kWave) {
+        uint16_t pr[4];
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+            const int q = q0 + t * kWave + lane;
+            pr[t] = q < L.n_far ? ldg(fp + q) : (uint16_t)0xffff;
         }
+        bool c = false;
+#pragma unroll
+        for (int t = 0; t < 4; t++)
+            if (pr[t] != 0xffff) {
+                const int i = pr[t] & 0xff, j = pr[t] >> 8;
+                c |= dist2(Xx[i], Xy[i], Xz[i], Xx[j], Xy[j], Xz[j]) < B.cd2;
+            }
         clash = __ballot(c) != 0;
     }
     acc.poses += 1;
