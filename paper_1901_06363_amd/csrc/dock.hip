@@ -85,7 +85,7 @@ typedef __attribute__((address_space(3))) uint8_t lds_u8;
 typedef __attribute__((address_space(3))) uint16_t lds_u16;
 
 constexpr int kSurvCap = 128;  // straddling pairs that can still bump in one sweep (LDS list)
-constexpr int kMvPad = 8;      // sentinel rows after the moving list (cover one step of the score pass)
+constexpr int kMvPad = 16;     // sentinel rows after the moving list (cover one step of the score pass)
 
 // The per-wave slice is sized for the batch's largest ligand and decides how
 // many waves fit a CU, so the moving-atom rows are packed to 36 bytes (no
@@ -321,8 +321,9 @@ __device__ __forceinline__ uint32_t fold_groups(uint64_t m) {
 // value and its partner's, whichever output holds which).
 template <int NB>
 __device__ __forceinline__ int group_sum(int v) {
-    static_assert(NB >= 8 && NB <= 32, "angle blocks of 8, 16 or 32");
-    if (NB == 8) v += __builtin_amdgcn_update_dpp(0, v, 0x128, 0xf, 0xf, false);  // row_ror:8
+    static_assert(NB >= 4 && NB <= 32, "angle blocks of 4, 8, 16 or 32");
+    if (NB == 4) v += __builtin_amdgcn_update_dpp(0, v, 0x124, 0xf, 0xf, false);  // row_ror:4
+    if (NB <= 8) v += __builtin_amdgcn_update_dpp(0, v, 0x128, 0xf, 0xf, false);  // row_ror:8
     if (NB <= 16) {
         const auto p = __builtin_amdgcn_permlane16_swap(v, v, false, false);
         v = (int)p[0] + (int)p[1];
@@ -331,12 +332,10 @@ __device__ __forceinline__ int group_sum(int v) {
     return (int)q[0] + (int)q[1];
 }
 
-template <int NB, bool BOX>
-__device__ __forceinline__ void score_pass(const PocketDev& P, const Sweep& sw, const WaveLds& W, const float* trig,
-                                           int base, int stride, int n) {
+template <int NB, int KANG, int KATU, bool BOX>
+__device__ __forceinline__ void score_blocks(const PocketDev& P, const Sweep& sw, const WaveLds& W, const float* trig,
+                                             int base, int stride, int kfirst, int n) {
     constexpr int G = kWave / NB;
-    constexpr int KANG = NB == 8 ? 4 : NB == 16 ? 2 : 1;
-    constexpr int KATU = NB == 8 ? 1 : NB == 16 ? 2 : 4;
     static_assert(G * KATU <= kMvPad + 1, "sentinel rows must cover a step");
     const int lane = lane_id();
     const int k0 = lane & (NB - 1), g = lane / NB;
@@ -348,7 +347,7 @@ __device__ __forceinline__ void score_pass(const PocketDev& P, const Sweep& sw, 
     const float thr = sw.gface;
     const int m = sw.m;
     const __attribute__((address_space(1))) char* edt = (const __attribute__((address_space(1))) char*)P.edt;
-    for (int kb = 0; kb < n; kb += NB * KANG) {
+    for (int kb = kfirst; kb < n; kb += NB * KANG) {
         const int A = min(KANG, (n - kb + NB - 1) / NB);
         float c[KANG], s[KANG];
 #pragma unroll
@@ -426,6 +425,24 @@ __device__ __forceinline__ void score_pass(const PocketDev& P, const Sweep& sw, 
                 }
             }
     }
+}
+
+// A remainder of at most four angles in one block of 4 angles x 16 atom
+// groups (out of line, so that the wide pass keeps its registers).
+__device__ __noinline__ void score_tail4(const PocketDev* Pp, const Sweep* swp, const WaveLds* Wp, const float* trig,
+                                        int base, int stride, int kfirst, int n) {
+    score_blocks<4, 1, 1, false>(*Pp, *swp, *Wp, trig, base, stride, kfirst, n);
+}
+
+template <int NB, bool BOX>
+__device__ __forceinline__ void score_pass(const PocketDev& P, const Sweep& sw, const WaveLds& W, const float* trig,
+                                           int base, int stride, int n) {
+    constexpr int KANG = NB == 8 ? 4 : NB == 16 ? 2 : 1;
+    constexpr int KATU = NB == 8 ? 1 : NB == 16 ? 2 : 4;
+    const int r = n % (NB * KANG);
+    const int wide = (BOX || r > 4 || r == 0) ? n : n - r;
+    score_blocks<NB, KANG, KATU, BOX>(P, sw, W, trig, base, stride, 0, wide);
+    if (!BOX && wide < n) score_tail4(&P, &sw, &W, trig, base, stride, wide, n);
     wave_sync();
 }
 
