@@ -334,7 +334,7 @@ __device__ __forceinline__ int group_sum(int v) {
 
 template <int NB, int KANG, int KATU, bool BOX>
 __device__ __forceinline__ void score_blocks(const PocketDev& P, const Sweep& sw, const WaveLds& W, const float* trig,
-                                             int base, int stride, int kfirst, int n) {
+                                             int base, int stride, int kfirst, int n, int T) {
     constexpr int G = kWave / NB;
     static_assert(G * KATU <= kMvPad + 1, "sentinel rows must cover a step");
     const int lane = lane_id();
@@ -359,10 +359,12 @@ __device__ __forceinline__ void score_blocks(const PocketDev& P, const Sweep& sw
         }
         int sum[KANG];
         uint64_t badm[KANG];
+        bool alive[KANG];
 #pragma unroll
         for (int a = 0; a < KANG; a++) {
             sum[a] = 0;
             badm[a] = 0;
+            alive[a] = true;
         }
         // byte offsets of the KATU x KANG lookups of the step at row j0 (the
         // sentinel's for an uncertain cell, whose candidate is flagged)
@@ -391,7 +393,7 @@ __device__ __forceinline__ void score_blocks(const PocketDev& P, const Sweep& sw
                                    (fz < fnz);
                         badm[a] |= __ballot(live & !sure);
                         const float fi2 = fmaf(fz, fsz2, fmaf(fy, fsy2, fx + fx));
-                        off[t][a] = (uint32_t)((live & sure) ? fi2 : fsent2);
+                        off[t][a] = (uint32_t)((live & sure & alive[a]) ? fi2 : fsent2);
                     }
                 }
             }
@@ -408,16 +410,18 @@ __device__ __forceinline__ void score_blocks(const PocketDev& P, const Sweep& sw
                     v[t][a] = a < A ? (int)*(const __attribute__((address_space(1))) uint16_t*)(edt + off[t][a]) : 0;
             if (j0 + KATU * G < m) offsets(j0 + KATU * G);
 #pragma unroll
-            for (int a = 0; a < KANG; a++)
+            for (int a = 0; a < KANG; a++) {
 #pragma unroll
                 for (int t = 0; t < KATU; t++) sum[a] += v[t][a];
+                alive[a] = alive[a] & ((sum[a] < T) | (kb + k0 + NB * a == 0));
+            }
         }
         // sum the groups of each angle across lanes; uncertain flags folded from the ballots
 #pragma unroll
         for (int a = 0; a < KANG; a++)
             if (a < A) {
                 const int tot = group_sum<NB>(sum[a]);
-                const uint32_t badbits = fold_groups<NB>(badm[a]);
+                const uint32_t badbits = fold_groups<NB>(badm[a] | __ballot(!alive[a]));
                 const int k = kb + NB * a + lane;
                 if (lane < NB && k < n) {
                     W.Slo[k] = tot;
@@ -430,19 +434,19 @@ __device__ __forceinline__ void score_blocks(const PocketDev& P, const Sweep& sw
 // A remainder of at most four angles in one block of 4 angles x 16 atom
 // groups (out of line, so that the wide pass keeps its registers).
 __device__ __noinline__ void score_tail4(const PocketDev* Pp, const Sweep* swp, const WaveLds* Wp, const float* trig,
-                                        int base, int stride, int kfirst, int n) {
-    score_blocks<4, 1, 1, false>(*Pp, *swp, *Wp, trig, base, stride, kfirst, n);
+                                        int base, int stride, int kfirst, int n, int T) {
+    score_blocks<4, 1, 1, false>(*Pp, *swp, *Wp, trig, base, stride, kfirst, n, T);
 }
 
 template <int NB, bool BOX>
 __device__ __forceinline__ void score_pass(const PocketDev& P, const Sweep& sw, const WaveLds& W, const float* trig,
-                                           int base, int stride, int n) {
+                                           int base, int stride, int n, int T) {
     constexpr int KANG = NB == 8 ? 4 : NB == 16 ? 2 : 1;
     constexpr int KATU = NB == 8 ? 1 : NB == 16 ? 2 : 4;
     const int r = n % (NB * KANG);
     const int wide = (BOX || r > 4 || r == 0) ? n : n - r;
-    score_blocks<NB, KANG, KATU, BOX>(P, sw, W, trig, base, stride, 0, wide);
-    if (!BOX && wide < n) score_tail4(&P, &sw, &W, trig, base, stride, wide, n);
+    score_blocks<NB, KANG, KATU, BOX>(P, sw, W, trig, base, stride, 0, wide, T);
+    if (!BOX && wide < n) score_tail4(&P, &sw, &W, trig, base, stride, wide, n, T);
     wave_sync();
 }
 
@@ -456,10 +460,6 @@ __device__ int eval_candidates(const PocketDev& P, const BatchDev& B, const Swee
     constexpr int G = kWave / NB;
     acc.poses += n;
 
-    if (sw.inside)
-        score_pass<NB, false>(P, sw, W, trig, base, stride, n);
-    else
-        score_pass<NB, true>(P, sw, W, trig, base, stride, n);
 
     // ---- bump pass.  After a successful prune: lanes = candidate angles (64
     // per word), each takes the minimum of d^2 = A + 2B cos + 2C sin over the
@@ -518,6 +518,34 @@ __device__ int eval_candidates(const PocketDev& P, const BatchDev& B, const Swee
         }
     }
     wave_sync();
+
+    // ---- score pass.  A schedule starting at angle 0 has the unturned
+    // fragment as its first candidate: when its S is certain and it cannot
+    // bump, no other candidate whose partial sum reaches that S can win (ties
+    // go to the earlier position), so such candidates stop gathering and keep
+    // their partial sum as a lower bound (their upper bound left open).  The
+    // extra pass that scores the unturned fragment pays off on sweeps of more
+    // than 32 candidates.
+    int T = 0x7fffffff;
+    if (base == 0 && sw.inside && n > 32) {
+        int s0 = 0;
+        bool ok = true;
+        for (int j = lane; j < sw.m; j += kWave) {
+            const f4 ra = W.MVa[j], rb = W.MVb[j];
+            const float yx = ra.x + ra.w, yy = ra.y + rb.x, yz = ra.z + rb.y;
+            const float fx = __builtin_rintf(yx), fy = __builtin_rintf(yy), fz = __builtin_rintf(yz);
+            const float e = fmaxf(fmaxf(fabsf(yx - fx), fabsf(yy - fy)), fabsf(yz - fz));
+            ok = ok & (e <= sw.gface);
+            const float fi = fmaf(fz, (float)P.dim[0] * (float)P.dim[1], fmaf(fy, (float)P.dim[0], fx));
+            s0 += ok ? (int)P.edt[(uint32_t)fi] : 0;
+        }
+        s0 = wave_sum(s0);
+        if (__ballot(!ok) == 0 && W.st[0] == 0) T = s0;
+    }
+    if (sw.inside)
+        score_pass<NB, false>(P, sw, W, trig, base, stride, n, T);
+    else
+        score_pass<NB, true>(P, sw, W, trig, base, stride, n, T);
 
     // ---- decision: key = S << 9 | position (a schedule has at most 360
     // positions).  The certain candidates' S comes from in-box cells only (at
