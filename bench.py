@@ -631,17 +631,18 @@ def screen_leg(gd, torch, np, args, steps, warmup, n_lig=0, tiling=""):
 
 
 class ChunkOutputs:
-    """Two sets of docking outputs sized for the largest chunk, viewed per
-    chunk: consecutive steps alternate sets so that one chunk's refinement
-    can read its poses while the next chunk docks."""
+    """Sets of docking outputs sized for the largest chunk, viewed per chunk
+    (chunk c always uses set c mod the number of sets, so each chunk's
+    captured graph keeps its output pointers): a chunk's refinement reads its
+    poses while the following chunks dock into other sets."""
 
-    def __init__(self, gd, torch, n_max, k, reps, rmax, lmax):
+    def __init__(self, gd, torch, n_max, k, reps, rmax, lmax, n_sets=2):
         dev = torch.device("cuda")
         self.gd, self.k = gd, k
         self.sets = [dict(recs=torch.empty(n_max * k * 6, dtype=torch.int32, device=dev),
                           ang=torch.empty(n_max * k * reps * rmax * 2, dtype=torch.int16, device=dev),
                           xyz=torch.empty(n_max * k * lmax * 3, dtype=torch.float32, device=dev),
-                          cnt=torch.zeros(4, dtype=torch.int64, device=dev)) for _ in range(2)]
+                          cnt=torch.zeros(4, dtype=torch.int64, device=dev)) for _ in range(n_sets)]
 
     def view(self, i, B):
         s = self.sets[i]
@@ -709,11 +710,12 @@ def large_headline(gd, torch, np, args):
     log("large: chunk 0 prepared in %.1f s, tiling %s (%s)" % (prep_s[0], tiling,
                                                                 "given" if args.tiling else "autotuned"))
     lmax = max(w.lmax, B0.max_atoms)
-    outs = ChunkOutputs(gd, torch, chunk, w.top_k, B0.repetitions, 16 if w.bmax <= 16 else w.bmax, lmax)
+    n_sets = 4  # a chunk's docking waits for the refinement four steps back, not the one just enqueued
+    outs = ChunkOutputs(gd, torch, chunk, w.top_k, B0.repetitions, 16 if w.bmax <= 16 else w.bmax, lmax, n_sets)
     n_steps = args.warmup + args.steps
     cnt_hist = torch.zeros((n_steps, 4), dtype=torch.int64, device="cuda")
     acc_hist = torch.zeros(n_steps, dtype=torch.int64, device="cuda")
-    ref_done = [None, None]
+    ref_done = [None] * n_sets
     configured = set()
     timed_batches = []
     t0 = None
@@ -730,7 +732,7 @@ def large_headline(gd, torch, np, args):
             acc_hist[s_] = r["accepted"].sum()
         done = torch.cuda.Event()
         done.record(rstream)
-        ref_done[s_ % 2] = done
+        ref_done[(s_ % nch) % n_sets] = done
 
     pending = None
     for s in range(n_steps):
@@ -755,9 +757,9 @@ def large_headline(gd, torch, np, args):
             configured.add(c)
         if B.max_atoms > lmax or B.max_rot > 16:
             raise RuntimeError("chunk %d exceeds the output buffers" % c)
-        o = outs.view(s % 2, B)
-        if ref_done[s % 2] is not None:
-            main.wait_event(ref_done[s % 2])  # the refinement two steps back read this output set
+        o = outs.view(c % n_sets, B)
+        if ref_done[c % n_sets] is not None:
+            main.wait_event(ref_done[c % n_sets])  # the last refinement that read this output set
         B.dock(gd.BATCHED, o)
         cnt_hist[s].copy_(o.counters)
         ev = torch.cuda.Event()
