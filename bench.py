@@ -252,7 +252,10 @@ def refine_leg(gd, torch, np, n_lig, l2=None):
                               algo_gather_bytes_per_launch=gather_bytes, algo_flops_per_launch=flops,
                               flops_TFLOPs=flops / (kms * 1e-3) / 1e12,
                               flops_frac_of_fp32_peak=flops / (kms * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS,
-                              peak_source="l2_gather_peak.f32_GBps (random 4-byte gathers from an L2-resident table)"),
+                              peak_source="l2_gather_peak.f32_GBps (random 4-byte gathers from an L2-resident table)",
+                              note="the 8 density nodes of 4 B per atom and pass are read as two 16-byte corner-packed "
+                                   "nodes, a quarter of the probe's requests per byte, so a fraction near 1 does not "
+                                   "make the kernel gather-bound: its counters show it bound by instruction issue"),
                 penalised=dict(clash_weight=cw, kernel_ms=outp["kernel_ms"],
                                accepted=int(outp["accepted"].sum().item())))
 
