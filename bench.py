@@ -9,8 +9,9 @@ ligand, streamed in chunks of 65,536 ligands.  One step = one chunk: queue
 reset, the persistent docking kernel (placement, greedy sweeps, scoring, bump
 tests, FP64 commits, endpoint), top-k reduction, replay of the selected poses,
 then 50 ascent steps of the density-surrogate refinement of the chunk's top-8
-poses with exact rescoring and acceptance (on a second stream, overlapping the
-next chunk's docking).  Step s docks chunk s mod 16, so warm-up plus timed
+poses with exact rescoring and acceptance, on the same stream right behind
+the docking (their host-side set-up overlaps the docking: uploads go through
+pinned staging).  Step s docks chunk s mod 16, so warm-up plus timed
 steps cover the whole library.  Chunks are generated and prepared (validated,
 topology and work queue built, copied to HBM) on a host thread while earlier
 chunks dock; the timed steps start only once every chunk is resident in HBM.
@@ -635,9 +636,8 @@ def screen_leg(gd, torch, np, args, steps, warmup, n_lig=0, tiling=""):
 
 class ChunkOutputs:
     """Sets of docking outputs sized for the largest chunk, viewed per chunk
-    (chunk c always uses set c mod the number of sets, so each chunk's
-    captured graph keeps its output pointers): a chunk's refinement reads its
-    poses while the following chunks dock into other sets."""
+    (a chunk always uses the same set, so its captured graph keeps its output
+    pointers)."""
 
     def __init__(self, gd, torch, n_max, k, reps, rmax, lmax, n_sets=2):
         dev = torch.device("cuda")
@@ -661,7 +661,6 @@ def large_headline(gd, torch, np, args):
     the module docstring)."""
     import threading
     from synth import configs
-    from paper_1901_06363_amd.stream import poses_from_topk
     w = configs.LARGE
     rx = configs.REFINE.extra
     n_lib = args.large_ligands or w.n_ligands
@@ -673,11 +672,11 @@ def large_headline(gd, torch, np, args):
     P = gd.Pocket(w.pocket_points(), 0.5, w.pad, blur_sigma=rx["blur_sigma"], blur_h=rx["blur_h"])
     q = w.quaternions()
     side = torch.cuda.Stream()
-    rstream = torch.cuda.Stream()
-    main = torch.cuda.current_stream()
 
     # host thread: generate and prepare every chunk once, in order; they stay resident in HBM
     slots = [None] * nch
+    gidx = [None] * nch  # per chunk: the rows of its top-k poses in CSR order (device), and their ligands
+    plig = [None] * nch
     ready = [threading.Event() for _ in range(nch)]
     prep_s = [0.0] * nch
     err = []
@@ -687,7 +686,18 @@ def large_headline(gd, torch, np, args):
             for i, first in enumerate(starts):
                 t = time.perf_counter()
                 ligs = w.ligands(first, min(chunk, n_lib - first))
-                slots[i] = gd.Batch(P, ligs, q, stream=side, hp=w.hp, top_k=w.top_k)
+                B_ = gd.Batch(P, ligs, q, stream=side, hp=w.hp, top_k=w.top_k)
+                # gather index of the chunk's top-k poses from the (n, k, max_atoms, 3) outputs into CSR
+                # rows (fixed by the atom counts), uploaded once with the chunk
+                nat = np.diff(np.asarray(ligs.atom_off)).astype(np.int64)
+                pl = np.repeat(np.arange(B_.n_ligands), w.top_k)
+                pa = nat[pl]
+                first_row = np.concatenate([[0], np.cumsum(pa)[:-1]])
+                idx = np.repeat(np.arange(len(pl)) * B_.max_atoms - first_row, pa) + np.arange(pa.sum())
+                with torch.cuda.stream(side):
+                    gidx[i] = torch.from_numpy(idx.astype(np.int32)).to("cuda")
+                plig[i] = pl
+                slots[i] = B_
                 prep_s[i] = time.perf_counter() - t
                 ready[i].set()
         except BaseException as e:  # re-raised by the consumer
@@ -713,36 +723,20 @@ def large_headline(gd, torch, np, args):
     log("large: chunk 0 prepared in %.1f s, tiling %s (%s)" % (prep_s[0], tiling,
                                                                 "given" if args.tiling else "autotuned"))
     lmax = max(w.lmax, B0.max_atoms)
-    n_sets = 4  # a chunk's docking waits for the refinement four steps back, not the one just enqueued
-    outs = ChunkOutputs(gd, torch, chunk, w.top_k, B0.repetitions, 16 if w.bmax <= 16 else w.bmax, lmax, n_sets)
+    # one output set: a chunk's refinement runs on the same stream right behind its docking
+    outs = ChunkOutputs(gd, torch, chunk, w.top_k, B0.repetitions, 16 if w.bmax <= 16 else w.bmax, lmax, 1)
     n_steps = args.warmup + args.steps
     cnt_hist = torch.zeros((n_steps, 4), dtype=torch.int64, device="cuda")
     acc_hist = torch.zeros(n_steps, dtype=torch.int64, device="cuda")
-    ref_done = [None] * n_sets
     configured = set()
     timed_batches = []
     t0 = None
-
-    def refine_step(p):
-        # the top-8 refinement of a docked chunk on its own stream, enqueued
-        # after the next chunk's docking so that its host-side set-up (and any
-        # pageable upload, which waits for the stream) overlaps that docking
-        s_, B_, o_, ev_ = p
-        rstream.wait_event(ev_)
-        with torch.cuda.stream(rstream):
-            pose_lig, px, py, pz = poses_from_topk(o_, B_.lig)
-            r = gd.refine(P, B_.lig, pose_lig, px, py, pz, stream=rstream, **ropt)
-            acc_hist[s_] = r["accepted"].sum()
-        done = torch.cuda.Event()
-        done.record(rstream)
-        ref_done[(s_ % nch) % n_sets] = done
-
-    pending = None
+    # Each step enqueues, on one stream: the chunk's docking (graph: queue reset, persistent kernel, top-k,
+    # replay), the gather of its top-8 poses into CSR rows, and their refinement and exact rescoring.  The
+    # refinement's host-side preparation and uploads (pinned staging) run while the chunk docks, so the device
+    # goes from one chunk's refinement straight to the next chunk's docking.
     for s in range(n_steps):
         if s == args.warmup:
-            if pending is not None:
-                refine_step(pending)
-                pending = None
             th.join()  # every chunk resident before the timed region
             if err:
                 raise err[0]
@@ -760,21 +754,16 @@ def large_headline(gd, torch, np, args):
             configured.add(c)
         if B.max_atoms > lmax or B.max_rot > 16:
             raise RuntimeError("chunk %d exceeds the output buffers" % c)
-        o = outs.view(c % n_sets, B)
-        if ref_done[c % n_sets] is not None:
-            main.wait_event(ref_done[c % n_sets])  # the last refinement that read this output set
+        o = outs.view(0, B)
         B.dock(gd.BATCHED, o)
         cnt_hist[s].copy_(o.counters)
-        ev = torch.cuda.Event()
-        ev.record(main)
-        if pending is not None:
-            refine_step(pending)
-        pending = (s, B, o, ev)
+        X = o.xyz.reshape(-1, 3).index_select(0, gidx[c])
+        r = gd.refine(P, B.lig, plig[c], X[:, 0].contiguous(), X[:, 1].contiguous(), X[:, 2].contiguous(), **ropt)
+        acc_hist[s] = r["accepted"].sum()
         if t0 is not None:
             timed_batches.append(B)
         if s < args.warmup or (s - args.warmup) % 4 == 3:
             log("large: step %d (chunk %d) enqueued, %.1f s" % (s, c, time.perf_counter() - t_setup))
-    refine_step(pending)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     kms = {}
@@ -833,7 +822,7 @@ def large_headline(gd, torch, np, args):
     n_launch = len(kernel_ms)
     n_timed = len(timed_batches)
     torch.cuda.synchronize()
-    del slots, outs, timed_batches, B0, B, o, pending
+    del slots, outs, timed_batches, B0, B, o, X, r, gidx
     torch.cuda.empty_cache()
 
     achieved = flops / k_s / 1e12

@@ -1074,6 +1074,17 @@ static hipError_t stage_release(Staging* st, hipStream_t s, bool copied) {
     return e;
 }
 
+hipError_t upload_async(void* dev, const void* host, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    Staging* st = nullptr;
+    hipError_t e = stage_acquire(n, &st);
+    if (e != hipSuccess) return e;
+    memcpy(st->host, host, n);
+    e = hipMemcpyAsync(dev, st->host, n, hipMemcpyHostToDevice, s);
+    const hipError_t r = stage_release(st, s, e == hipSuccess);
+    return e != hipSuccess ? e : r;
+}
+
 gd_status dock_batch(const gd_pocket* P, const gd_ligands* L0, const gd_knobs* K, gd_mode mode, hipStream_t s,
                      gd_pose_rec* out, uint16_t* angles, float* pose_xyz, int64_t* counters) {
     const char* who = "gd_dock_batch";

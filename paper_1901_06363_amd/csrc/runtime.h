@@ -71,6 +71,12 @@ gd_status ligands_on_host(const gd_ligands* L, hipStream_t s, HostLigands& H, co
 // True when p is device (or managed) memory of the HIP runtime.
 bool is_device_ptr(const void* p);
 
+// Copy n bytes of host memory to device memory on s through one of the
+// library's pinned staging buffers: the call returns once the bytes are in the
+// staging buffer, without waiting for earlier work on s (a copy from pageable
+// memory would).
+hipError_t upload_async(void* dev, const void* host, size_t n, hipStream_t s);
+
 // Stream-ordered device copies of small host arrays, released after the call.
 struct AsyncScratch {
     hipStream_t s;
@@ -87,7 +93,7 @@ struct AsyncScratch {
         if (e != hipSuccess) return e;
         ptrs.push_back(p);
         if (!v.empty()) {
-            e = hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
+            e = upload_async(p, v.data(), v.size() * sizeof(T), s);
             if (e != hipSuccess) return e;
         }
         *out = (const T*)p;
