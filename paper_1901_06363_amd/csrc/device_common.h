@@ -11,6 +11,15 @@ namespace gd {
 // wavefront helpers
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
+// The lane index computed where it is used: code that runs once per sweep or
+// pose takes it from here, so that the compiler does not keep lane-derived
+// addresses from the start of the kernel in registers (or scratch memory)
+// across the inner loops.
+__device__ __forceinline__ int lane_id_here() {
+    int r;
+    asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(r));
+    return r;
+}
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -37,11 +46,16 @@ __device__ __forceinline__ int wave_sum(int v) {
            __builtin_amdgcn_readlane(v, 63);
 }
 
-// 64-bit wave sum (for exact scores of atoms far outside the grid box).
+// 64-bit wave sum (for exact scores of atoms far outside the grid box), in
+// three limbs of 24, 24 and 16 bits summed as 32-bit integers (64 lanes add at
+// most 6 bits), so it needs no lane-index registers; exact modulo 2^64.
 __device__ __forceinline__ long long wave_sum64(long long v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
+    const unsigned long long u = (unsigned long long)v;
+    const int l0 = wave_sum((int)(u & 0xffffffu));
+    const int l1 = wave_sum((int)((u >> 24) & 0xffffffu));
+    const int l2 = wave_sum((int)(short)(u >> 48));
+    return (long long)((unsigned long long)(long long)l0 + ((unsigned long long)(long long)l1 << 24) +
+                       ((unsigned long long)(long long)l2 << 48));
 }
 
 // Scores are reported in 31 bits: a pose whose S reaches 2^31 - 1 (an atom

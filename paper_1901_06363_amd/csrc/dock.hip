@@ -433,9 +433,21 @@ __device__ __forceinline__ void score_blocks(const PocketDev& P, const Sweep& sw
 
 // A remainder of at most four angles in one block of 4 angles x 16 atom
 // groups (out of line, so that the wide pass keeps its registers).
-__device__ __noinline__ void score_tail4(const PocketDev* Pp, const Sweep* swp, const WaveLds* Wp, const float* trig,
-                                        int base, int stride, int kfirst, int n, int T) {
-    score_blocks<4, 1, 1, false>(*Pp, *swp, *Wp, trig, base, stride, kfirst, n, T);
+// Its arguments are values and pointers only, so that no record of the
+// caller's has to be placed in scratch memory for the call.
+__device__ __noinline__ void score_tail4(const PocketDev* Pp, const lds_float4* MVa, const lds_float4* MVb,
+                                        const lds_float* MVc, lds_int* Slo, lds_int* Shi, float gface, int m,
+                                        const float* trig, int base, int stride, int kfirst, int n, int T) {
+    Sweep sw;
+    sw.gface = gface;
+    sw.m = m;
+    WaveLds W;
+    W.MVa = (lds_float4*)MVa;
+    W.MVb = (lds_float4*)MVb;
+    W.MVc = (lds_float*)MVc;
+    W.Slo = Slo;
+    W.Shi = Shi;
+    score_blocks<4, 1, 1, false>(*Pp, sw, W, trig, base, stride, kfirst, n, T);
 }
 
 template <int NB, bool BOX>
@@ -446,7 +458,8 @@ __device__ __forceinline__ void score_pass(const PocketDev& P, const Sweep& sw, 
     const int r = n % (NB * KANG);
     const int wide = (BOX || r > 4 || r == 0) ? n : n - r;
     score_blocks<NB, KANG, KATU, BOX>(P, sw, W, trig, base, stride, 0, wide, T);
-    if (!BOX && wide < n) score_tail4(&P, &sw, &W, trig, base, stride, wide, n, T);
+    if (!BOX && wide < n)
+        score_tail4(&P, W.MVa, W.MVb, W.MVc, W.Slo, W.Shi, sw.gface, sw.m, trig, base, stride, wide, n, T);
     wave_sync();
 }
 
@@ -597,7 +610,7 @@ __device__ int eval_candidates(const PocketDev& P, const BatchDev& B, const Swee
 // bit-exact result and only the pivot changes (keep_axis).
 // Lanes 0-2 hold one component each, so the three divisions are one.
 __device__ __forceinline__ void sweep_axis(const WaveLds& W, int lp, int a, int c, int piv, bool keep_axis) {
-    const int lane = lane_id();
+    const int lane = lane_id_here();
     const int comp = lane < 3 ? lane : 0;
     if (!keep_axis) {
         const double d = W.X[comp * lp + c] - W.X[comp * lp + a];
@@ -774,10 +787,11 @@ __device__ __forceinline__ void sweep_setup(const PocketDev& P, const BatchDev& 
     gterm = wave_maxf(gterm);
     // sentinel rows after the list: U = V = 0 at the centre of cell (0, 0, nz),
     // whose linear index is the zero sentinel cell
-    if (lane < kMvPad) {
-        W.MVa[sw.m + lane] = mk4(0.f, 0.f, (float)P.dim[2], 0.f);
-        W.MVb[sw.m + lane] = mk4(0.f, 0.f, 0.f, 0.f);
-        W.MVc[sw.m + lane] = 0.f;
+    const int lane_s = lane_id_here();
+    if (lane_s < kMvPad) {
+        W.MVa[sw.m + lane_s] = mk4(0.f, 0.f, (float)P.dim[2], 0.f);
+        W.MVb[sw.m + lane_s] = mk4(0.f, 0.f, 0.f, 0.f);
+        W.MVc[sw.m + lane_s] = 0.f;
     }
     // a lookup is certain when each coordinate is more than the guard away from
     // a cell face, i.e. within 1/2 - guard of the cell centre; the FP32
@@ -813,7 +827,7 @@ __device__ __forceinline__ void commit(const uint8_t* mvl, int m, const WaveLds&
 
 // Rigid placement X = R(q)(x - c_L) + c_P.
 __device__ void place(const PocketDev& P, const BatchDev& B, const LigMeta& L, int o, const WaveLds& W) {
-    const int lane = lane_id();
+    const int lane = lane_id_here();
     const int lp = lds_pitch(B.lmax);
     const __attribute__((address_space(4))) double* R = (const __attribute__((address_space(4))) double*)(B.qmat + 9 * (size_t)o);
     for (int i = lane; i < L.l; i += kWave) {
@@ -869,7 +883,10 @@ __device__ void dock_orientation(const PocketDev& P, const BatchDev& B, int lig,
     const LigMeta L = ldc_record(B.lig + lig);
     place(P, B, L, o, W);
     const int nrec = B.reps * L.nr * 2;
-    uint16_t* ang = B.ang + L.ang_off + (size_t)o * nrec;
+    // The chosen angles are collected one per lane (record q in lane q mod 64)
+    // and stored 64 at a time, so no pointer into the output stays live
+    // across the sweeps.
+    int angv = 0, q = 0;
     for (int rep = 0; rep < B.reps; rep++) {
         for (int r = 0; r < L.nr; r++) {
             const RotInfo* rp = B.rot + L.rot_off + r;
@@ -893,7 +910,13 @@ __device__ void dock_orientation(const PocketDev& P, const BatchDev& B, int lig,
                 }
                 commit(sw.mvl, sw.m, W, sw.lp, deg);
                 acc.sweeps++;
-                if (lane_id() == 0) ang[(rep * L.nr + r) * 2 + side] = (uint16_t)deg;
+                const int ql = q & (kWave - 1);
+                angv = lane_id() == ql ? deg : angv;
+                if (ql == kWave - 1 || q == nrec - 1) {
+                    uint16_t* dst = B.ang + L.ang_off + (size_t)o * nrec + (q - ql);
+                    if (lane_id() <= ql) dst[lane_id()] = (uint16_t)angv;
+                }
+                q++;
             }
         }
     }
@@ -927,7 +950,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) d
     const PocketDev& P = *Pp;
     const BatchDev& B = *Bp;
     extern __shared__ __align__(16) char smem[];
-    const int wave = threadIdx.x / kWave;
+    const int wave = uniform(threadIdx.x / kWave);
     const WaveLds W = carve(smem + wave * wave_lds_bytes(B.lmax, nmax), B.lmax, nmax);
     const int o = uniform(blockIdx.x * (blockDim.x / kWave) + wave);
     Acc acc;
@@ -944,7 +967,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) d
     const PocketDev& P = *Pp;
     const BatchDev& B = *Bp;
     extern __shared__ __align__(16) char smem[];
-    const int wave = threadIdx.x / kWave;
+    const int wave = uniform(threadIdx.x / kWave);
     const WaveLds W = carve(smem + wave * wave_lds_bytes(B.lmax, nmax), B.lmax, nmax);
     Acc acc;
     for (;;) {
@@ -1023,7 +1046,7 @@ __global__ void __launch_bounds__(256) topk_kernel(BatchDev B, gd_pose_rec* out,
 __global__ void __launch_bounds__(256) replay_kernel(PocketDev P, BatchDev B, const gd_pose_rec* recs, float* xyz,
                                                      int nmax) {
     extern __shared__ __align__(16) char smem[];
-    const int wave = threadIdx.x / kWave;
+    const int wave = uniform(threadIdx.x / kWave);
     const int idx = blockIdx.x * (blockDim.x / kWave) + wave;
     if (idx >= B.n_lig * B.top_k) return;
     const int lig = idx / B.top_k;
@@ -1065,7 +1088,7 @@ __global__ void __launch_bounds__(256) replay_kernel(PocketDev P, BatchDev B, co
 __global__ void __launch_bounds__(256) profile_kernel(const PocketDev* Pp, BatchDev B, const gd_pose_rec* recs,
                                                       int step, int32_t* S_out, uint8_t* f_out, int32_t* size_out) {
     extern __shared__ __align__(16) char smem[];
-    const int wave = threadIdx.x / kWave;
+    const int wave = uniform(threadIdx.x / kWave);
     const int idx = blockIdx.x * (blockDim.x / kWave) + wave;
     if (idx >= B.n_lig * B.top_k) return;
     const int lane = lane_id();
