@@ -289,6 +289,31 @@ __device__ __forceinline__ void bump_block(const Sweep& sw, const WaveLds& W, in
     }
 }
 
+// Eight pairs per lane do not fit the inlined register budget: that block
+// runs out of line, with values and pointers as arguments (no record of the
+// caller's in memory), and returns its bits.
+struct BumpBits {
+    uint64_t cert, maybe;
+};
+template <int K>
+__device__ __noinline__ BumpBits bump_block_far(const uint16_t* pairs, int side, int lp, float thr_lo, float thr_hi,
+                                                const lds_double* X, const lds_double* SW, const lds_float4* AD,
+                                                int q0, int nq, int nw, float c2, float s2) {
+    Sweep sw;
+    sw.pairs = pairs;
+    sw.side = side;
+    sw.lp = lp;
+    sw.thr_lo = thr_lo;
+    sw.thr_hi = thr_hi;
+    WaveLds W;
+    W.X = (lds_double*)X;
+    W.SW = (lds_double*)SW;
+    W.AD = (lds_float4*)AD;
+    BumpBits b{0, 0};
+    bump_block<K>(sw, W, q0, nq, nw, c2, s2, b.cert, b.maybe);
+    return b;
+}
+
 // Score pass over the candidate angles base + k*stride (k < n).  Lanes are
 // (k0 < NB, atom group g < G = 64/NB); a block covers up to KANG*NB angles
 // and a lane scores the angles kb + k0 + NB*a (a < KANG) over the atoms g,
@@ -523,9 +548,17 @@ __device__ int eval_candidates(const PocketDev& P, const BatchDev& B, const Swee
             uint64_t cert = 0, maybe = 0;
             const int nq = sw.npairs;
             int q0 = 0;
-            if (PPL > 1)
+            if (PPL > 4) {
+                for (; nq - q0 > kWave * (PPL - 1); q0 += kWave * PPL) {
+                    const BumpBits b = bump_block_far<PPL>(sw.pairs, sw.side, sw.lp, sw.thr_lo, sw.thr_hi, W.X, W.SW,
+                                                           W.AD, q0, nq, nw, cl, sl);
+                    cert |= b.cert;
+                    maybe |= b.maybe;
+                }
+            } else if (PPL > 1) {
                 for (; nq - q0 > kWave * (PPL - 1); q0 += kWave * PPL)
                     bump_block<PPL>(sw, W, q0, nq, nw, cl, sl, cert, maybe);
+            }
             for (; q0 < nq; q0 += kWave) bump_block<1>(sw, W, q0, nq, nw, cl, sl, cert, maybe);
             if (lane < nw) W.st[w0 + lane] = (uint8_t)(((cert >> lane) & 1) | (((maybe >> lane) & 1) << 1));
         }

@@ -113,6 +113,34 @@ def test_batched_equals_per_ligand_and_tilings(g):
 
 
 @gpu
+def test_pairs_per_lane_on_heavy_ligands(g):
+    """The heaviest ligands of the large library (most straddling pairs per
+    sweep, where more pairs can survive the prune than the LDS list holds and
+    the bump pass holds 1, 2, 4 or 8 pairs per lane): every tiling and both
+    forms give identical results, and three of them match the oracle."""
+    w = configs.LARGE
+    P, O = _pockets(w, g)
+    pool = w.ligands(0, 2048)
+    n_atoms = np.diff(np.asarray(pool.atom_off))
+    heavy = [int(i) for i in np.argsort(-n_atoms, kind="stable")[:12]]
+    ligs = pool.subset(heavy)
+    q = synth.quaternions(13, 32)
+    b = g.Batch(P, ligs, q, hp=w.hp, top_k=32)
+    ref = b.dock(1).host()
+    for t in [(8, 32, 1), (8, 32, 2), (8, 32, 8), (4, 16, 8), (2, 8, 8)]:
+        b.set_tiling(*t)
+        for mode in (0, 1):
+            got = b.dock(mode).host()
+            for k in ("orient", "S", "clash", "angles", "xyz"):
+                assert np.array_equal(got[k], ref[k]), (t, mode, k)
+    sub = ligs.subset(range(3))
+    b3 = g.Batch(P, sub, q, hp=w.hp, top_k=32)
+    b3.set_tiling(8, 32, 8)
+    orc = gpuutil.oracle_dock_batch(O, sub, oracle.knobs(hp=w.hp), q)
+    gpuutil.compare_full_ranking(b3.dock(1).host(), orc, sub)
+
+
+@gpu
 def test_repeat_runs_are_identical(g):
     w = configs.SCREEN
     P, _ = _pockets(w, g)
