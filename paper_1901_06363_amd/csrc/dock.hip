@@ -438,7 +438,10 @@ __device__ __forceinline__ void score_blocks(const PocketDev& P, const Sweep& sw
             for (int a = 0; a < KANG; a++) {
 #pragma unroll
                 for (int t = 0; t < KATU; t++) sum[a] += v[t][a];
-                alive[a] = alive[a] & ((sum[a] < T) | (kb + k0 + NB * a == 0));
+                // a candidate stops once its partial sum over all atom groups
+                // reaches the bound (every lane of the candidate agrees)
+                if (T != 0x7fffffff)
+                    alive[a] = alive[a] & ((group_sum<NB>(sum[a]) < T) | (kb + k0 + NB * a == 0));
             }
         }
         // sum the groups of each angle across lanes; uncertain flags folded from the ballots
@@ -570,10 +573,10 @@ __device__ int eval_candidates(const PocketDev& P, const BatchDev& B, const Swee
     // bump, no other candidate whose partial sum reaches that S can win (ties
     // go to the earlier position), so such candidates stop gathering and keep
     // their partial sum as a lower bound (their upper bound left open).  The
-    // extra pass that scores the unturned fragment pays off on sweeps of more
-    // than 32 candidates.
+    // extra pass that scores the unturned fragment is skipped on sweeps of at
+    // most 8 candidates.
     int T = 0x7fffffff;
-    if (base == 0 && sw.inside && n > 32) {
+    if (base == 0 && sw.inside && n > 8) {
         int s0 = 0;
         bool ok = true;
         for (int j = lane; j < sw.m; j += kWave) {

@@ -522,10 +522,27 @@ static void prep_one(const gd_ligands* L, const gd_knobs* K, int i, bool topo_on
                 if (!m[b] && T.dist[(size_t)a * l + b] >= minb) out.pairs.push_back((uint16_t)(a | (b << 8)));
         }
         ri.n_pairs = (int32_t)out.pairs.size() - ri.pair_off;
+        // each side's moving atoms farthest from the bond axis first (in the
+        // input conformation): a candidate's partial sum then tends to reach
+        // the sweep's bound in fewer steps (S is an integer sum, so the order
+        // does not change any result)
+        const double ax = (double)L->x[a0 + ri.c] - L->x[a0 + ri.a], ay = (double)L->y[a0 + ri.c] - L->y[a0 + ri.a],
+                     az = (double)L->z[a0 + ri.c] - L->z[a0 + ri.a];
+        const double an = std::sqrt(ax * ax + ay * ay + az * az);
+        auto radial = [&](int a) {
+            const double ux = (double)L->x[a0 + a] - L->x[a0 + ri.a], uy = (double)L->y[a0 + a] - L->y[a0 + ri.a],
+                         uz = (double)L->z[a0 + a] - L->z[a0 + ri.a];
+            const double cx = uy * az - uz * ay, cy = uz * ax - ux * az, cz = ux * ay - uy * ax;
+            return an > 0 ? std::sqrt(cx * cx + cy * cy + cz * cz) / an : 0.0;
+        };
         for (int side = 0; side < 2; side++) {
             ri.mv_off[side] = (int32_t)out.mv.size();
+            std::vector<std::pair<double, int>> order;
             for (int a = 0; a < l; a++)
-                if ((m[a] != 0) == (side == 0)) out.mv.push_back((uint8_t)a);
+                if ((m[a] != 0) == (side == 0)) order.push_back({-radial(a), a});
+            std::stable_sort(order.begin(), order.end(),
+                             [](const std::pair<double, int>& p, const std::pair<double, int>& q) { return p.first < q.first; });
+            for (const auto& e : order) out.mv.push_back((uint8_t)e.second);
             ri.n_mv[side] = (int32_t)out.mv.size() - ri.mv_off[side];
             double rel = (double)ri.n_mv[side] / (double)l;
             if (rel <= (double)K->threshold) {
