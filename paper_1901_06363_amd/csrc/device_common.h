@@ -20,6 +20,12 @@ __device__ __forceinline__ int lane_id_here() {
     asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(r));
     return r;
 }
+// 0.0f in a vector register, formed where it is used (for the same reason).
+__device__ __forceinline__ float zero_here() {
+    float r;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(r));
+    return r;
+}
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

@@ -823,11 +823,14 @@ __device__ __forceinline__ void sweep_setup(const PocketDev& P, const BatchDev& 
     gterm = wave_maxf(gterm);
     // sentinel rows after the list: U = V = 0 at the centre of cell (0, 0, nz),
     // whose linear index is the zero sentinel cell
+    // (the values are formed here: kept from the kernel's start they would
+    // hold four registers across the inner loops)
     const int lane_s = lane_id_here();
     if (lane_s < kMvPad) {
-        W.MVa[sw.m + lane_s] = mk4(0.f, 0.f, (float)P.dim[2], 0.f);
-        W.MVb[sw.m + lane_s] = mk4(0.f, 0.f, 0.f, 0.f);
-        W.MVc[sw.m + lane_s] = 0.f;
+        const float z = zero_here();
+        W.MVa[sw.m + lane_s] = mk4(z, z, z + (float)P.dim[2], z);
+        W.MVb[sw.m + lane_s] = mk4(z, z, z, z);
+        W.MVc[sw.m + lane_s] = z;
     }
     // a lookup is certain when each coordinate is more than the guard away from
     // a cell face, i.e. within 1/2 - guard of the cell centre; the FP32
@@ -913,16 +916,22 @@ __device__ __forceinline__ void endpoint(const PocketDev& P, const BatchDev& B, 
 }
 
 // The greedy sweep of one orientation (Alg. 2).
+// Outputs of a work item (orientations o0 .. o0 + n - 1 of one ligand), held
+// in registers until they fill whole runs of memory: the chosen angles one
+// per lane (record q of the item in lane q mod 64, stored 64 at a time; an
+// item's records are contiguous), the keys one per lane (stored at the end).
+struct ItemOut {
+    int angv = 0, q = 0;
+    uint64_t keyv = 0;
+};
+
 template <int NB, int PPL>
-__device__ void dock_orientation(const PocketDev& P, const BatchDev& B, int lig, int o, const WaveLds& W,
-                                 const float* trig, Acc& acc) {
+__device__ void dock_orientation(const PocketDev& P, const BatchDev& B, int lig, int o, int o0, int n_item,
+                                 const WaveLds& W, const float* trig, Acc& acc, ItemOut& out) {
     const LigMeta L = ldc_record(B.lig + lig);
     place(P, B, L, o, W);
     const int nrec = B.reps * L.nr * 2;
-    // The chosen angles are collected one per lane (record q in lane q mod 64)
-    // and stored 64 at a time, so no pointer into the output stays live
-    // across the sweeps.
-    int angv = 0, q = 0;
+    const int total = n_item * nrec;
     for (int rep = 0; rep < B.reps; rep++) {
         for (int r = 0; r < L.nr; r++) {
             const RotInfo* rp = B.rot + L.rot_off + r;
@@ -946,21 +955,22 @@ __device__ void dock_orientation(const PocketDev& P, const BatchDev& B, int lig,
                 }
                 commit(sw.mvl, sw.m, W, sw.lp, deg);
                 acc.sweeps++;
-                const int ql = q & (kWave - 1);
-                angv = lane_id() == ql ? deg : angv;
-                if (ql == kWave - 1 || q == nrec - 1) {
-                    uint16_t* dst = B.ang + L.ang_off + (size_t)o * nrec + (q - ql);
-                    if (lane_id() <= ql) dst[lane_id()] = (uint16_t)angv;
+                const int ql = out.q & (kWave - 1);
+                out.angv = lane_id() == ql ? deg : out.angv;
+                if (ql == kWave - 1 || out.q == total - 1) {
+                    uint16_t* dst = B.ang + L.ang_off + (size_t)o0 * nrec + (out.q - ql);
+                    if (lane_id() <= ql) dst[lane_id()] = (uint16_t)out.angv;
                 }
-                q++;
+                out.q++;
             }
         }
     }
     int S;
     bool clash;
     endpoint(P, B, L, W, S, clash, acc);
-    if (lane_id() == 0)
-        B.keys[L.key_off + o] = ((uint64_t)clash << 63) | ((uint64_t)(uint32_t)S << 32) | (uint64_t)(uint32_t)o;
+    const uint64_t key = ((uint64_t)clash << 63) | ((uint64_t)(uint32_t)S << 32) | (uint64_t)(uint32_t)o;
+    out.keyv = lane_id() == o - o0 ? key : out.keyv;
+    if (o - o0 == n_item - 1 && lane_id() < n_item) B.keys[L.key_off + o0 + lane_id()] = out.keyv;
 }
 
 __device__ void flush(unsigned long long* counters, Acc& acc) {
@@ -990,7 +1000,10 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) d
     const WaveLds W = carve(smem + wave * wave_lds_bytes(B.lmax, nmax), B.lmax, nmax);
     const int o = uniform(blockIdx.x * (blockDim.x / kWave) + wave);
     Acc acc;
-    if (o < B.n_orient) dock_orientation<NB, PPL>(P, B, lig, o, W, c_trig32, acc);
+    if (o < B.n_orient) {
+        ItemOut out;
+        dock_orientation<NB, PPL>(P, B, lig, o, o, 1, W, c_trig32, acc, out);
+    }
     flush(counters, acc);
 }
 
@@ -1009,11 +1022,13 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) d
     for (;;) {
         int item = 0;
         if (lane_id() == 0) item = atomicAdd(B.head, 1);
-        item = uniform(__shfl(item, 0));
+        item = uniform(item);  // lane 0 took the item and is the first active lane
         if (item >= B.n_items) break;
         const int lig = ldc(B.items + 2 * item), o0 = ldc(B.items + 2 * item + 1);
         const int o1 = min(o0 + B.orient_per_item, B.n_orient);
-        for (int o = o0; o < o1; o++) dock_orientation<NB, PPL>(P, B, lig, o, W, c_trig32, acc);
+        // at most 8 orientations per item (one key per lane)
+        ItemOut out;
+        for (int o = o0; o < o1; o++) dock_orientation<NB, PPL>(P, B, lig, o, o0, o1 - o0, W, c_trig32, acc, out);
     }
     flush(counters, acc);
 }
