@@ -96,6 +96,29 @@ def test_knob_settings_parity(g, kn):
 
 
 @gpu
+@pytest.mark.parametrize("mode", [0, 1])
+def test_ragged_items_and_long_angle_records(g, mode):
+    """Outputs are held per work item (up to 8 orientations of a ligand) and
+    stored when 64 angle records or the item are complete: 37 orientations
+    (a last item of 5), three repetitions (72 records per orientation for the
+    ligand with 12 rotatable bonds, 12 for the one with 2, so stores fall
+    inside and across orientations), against the oracle's full ranking."""
+    w = configs.SCREEN
+    P, O = _pockets(w, g)
+    pool = w.ligands(0, 400)
+    nrot = np.diff(np.asarray(pool.rot_off))
+    pick = [int(np.argmax(nrot)), int(np.argmin(nrot))] + list(range(0, 400, 100))
+    ligs = pool.subset(pick)
+    q = synth.quaternions(23, 37)
+    kn = dict(hp=30, repetitions=3)
+    b = g.Batch(P, ligs, q, top_k=37, **kn)
+    res = b.dock(mode).host()
+    orc = gpuutil.oracle_dock_batch(O, ligs, oracle.knobs(**kn), q)
+    gpuutil.compare_full_ranking(res, orc, ligs)
+    assert res["counters"][0] == b.poses_expected == sum(r.n_cand for r in orc)
+
+
+@gpu
 def test_batched_equals_per_ligand_and_tilings(g):
     w = configs.SCREEN
     P, _ = _pockets(w, g)
